@@ -1,0 +1,232 @@
+"""DPIA expressions for the dot / asum / gemv strategy families.
+
+Each builder returns the text of one functional DPIA expression; its value
+under the semantics of Secs. 4.2 and 5.1 (evaluated by ``eval_numpy`` or
+``eval_scalar``) is what a kernel running that strategy must produce bit for
+bit.
+
+The shape follows the blocked dot product of Sec. 2.1, eq. (2): the input is
+split into chunks of W elements, one chunk per work-group (mapWorkgroup);
+each chunk is split into L rows of C elements, one row per local work-item
+(mapLocal), and every work-item folds its row sequentially (reduceSeq) with
+the fused operator ``lam x a. (fst x * snd x) + a``.  Two readings of the
+printed equation are needed and are taken here:
+
+* eq. (2) applies ``split 2048`` to a single element and sizes the chunk as
+  2048*128; the reading used is that ``split n`` makes rows of length n
+  (its type in Fig. 5a, nm.d -> m.n.d), so a chunk is ``split C`` into L
+  rows of C: W = L*C.
+* the per-work-group results must be combined.  Eq. (2) leaves them to the
+  outer ``reduce``; here each chunk first combines its L lane results inside
+  the work-group, either with a sequential ``reduceSeq`` ("seq") or with a
+  binary tree in local memory ("tree": log2 L levels of
+  ``mapLocal (reduceSeq add 0) (split 2 v)``, leaves in lane order, built
+  from Fig. 5a primitives only), and the G chunk results are then folded by
+  a sequential ``reduceSeq`` from +0 in chunk order (the final loop of the
+  blocked listing in Sec. 2.2).
+
+Strided lane order: the contiguous strategy gives work-item l the elements
+l*C .. l*C + C-1 of its chunk.  The strided strategy gives it elements
+l, l+L, l+2L, ..., expressed as ``transpose (split L ch)`` (an extension: a
+layout primitive that swaps the two outer indices).  The test suite checks
+it against the same order written with Fig. 5a primitives alone (a reduce
+whose accumulator is an array of L lanes, as in the vector accumulators of
+the dot kernel of Sec. 6.2).
+
+asum uses ``lam x a. abs x + a``; the paper benchmarks asum (Sec. 7.1) but
+Fig. 5a has no absolute value, so ``abs`` is an added scalar primitive.
+
+gemv (y = A x, the BLAS operation with alpha = 1, beta = 0): rows are grouped
+R per work-group and every row is reduced with the same lane / combine
+strategy as a dot product of that row with x.  With two row parts, each half
+row is reduced on its own and the two halves are folded by
+``reduceSeq add 0``.
+
+The compensated ("kahan") variant keeps a pair (s, c) per accumulator:
+Kahan's summation step (N. J. Higham, Accuracy and Stability of Numerical
+Algorithms, 2nd ed., Alg. 4.2) inside the lanes, Knuth's TwoSum to merge two
+pairs in the combines, and optionally a binary64 final fold of s - c.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .eval_numpy import evaluate
+
+ADD = "(lam (e a) (+ e a))"
+MUL_ADD = "(lam (z a) (+ (* (fst z) (snd z)) a))"
+ABS_ADD = "(lam (e a) (+ (abs e) a))"
+
+# Kahan step on acc = (s, c) with element z = (x, y):
+#   y' = x*y - c ; t = s + y' ; new acc = (t, (t - s) - y')
+KAHAN_MUL_STEP = ("(lam (z acc) ((lam (yk) ((lam (t) (pair t (- (- t (fst acc)) yk)))"
+                  " (+ (fst acc) yk))) (- (* (fst z) (snd z)) (snd acc))))")
+
+# Merge of an earlier pair l = (s1, c1) with a later pair r = (s2, c2), by
+# TwoSum: s = s1 + s2 ; bp = s - s1 ; e = (s1 - (s - bp)) + (s2 - bp) ;
+# new pair (s, (c1 + c2) - e).  Element first, accumulator second.
+KAHAN_MERGE = ("(lam (r l) ((lam (s) ((lam (bp) (pair s (- (+ (snd l) (snd r))"
+               " (+ (- (fst l) (- s bp)) (- (fst r) bp))))) (- s (fst l))))"
+               " (+ (fst l) (fst r))))")
+
+ZERO_PAIR = "(pair 0 0)"
+
+
+@dataclass(frozen=True)
+class Plan:
+    """The oracle's reading of one strategy.
+
+    seq (C)        elements folded sequentially by one work-item
+    lanes (L)      work-items per chunk (mapLocal width)
+    order          "contiguous" (rows of C) or "strided" (stride-L rows)
+    combine        "tree" (pairwise in local memory) or "seq" (reduceSeq)
+    accum          "plain" or "kahan"
+    final_f64      kahan only: fold the chunk results in binary64
+    rows (R)       gemv: rows per work-group
+    row_parts      gemv: 1, or 2 halves reduced separately
+    """
+    seq: int
+    lanes: int
+    order: str = "contiguous"
+    combine: str = "tree"
+    accum: str = "plain"
+    final_f64: bool = False
+    rows: int = 1
+    row_parts: int = 1
+
+    @property
+    def chunk(self) -> int:
+        return self.seq * self.lanes
+
+    def check(self):
+        if self.seq < 1 or self.lanes < 1:
+            raise ValueError("seq and lanes must be positive")
+        if self.order not in ("contiguous", "strided"):
+            raise ValueError(f"bad order {self.order!r}")
+        if self.combine not in ("tree", "seq"):
+            raise ValueError(f"bad combine {self.combine!r}")
+        if self.combine == "tree" and self.lanes & (self.lanes - 1):
+            raise ValueError("a tree combine needs a power-of-two lane count")
+        if self.accum not in ("plain", "kahan"):
+            raise ValueError(f"bad accum {self.accum!r}")
+        if self.row_parts not in (1, 2):
+            raise ValueError("row_parts must be 1 or 2")
+
+
+def _rows_of(view: str, plan: Plan) -> str:
+    if plan.order == "contiguous":
+        return f"(split {plan.seq} {view})"
+    return f"(transpose (split {plan.lanes} {view}))"
+
+
+def _lanes(view: str, plan: Plan, step: str, init: str) -> str:
+    """Arr(L): each work-item's sequential fold of its row of the chunk."""
+    return (f"(mapLocal (toPrivate (lam (s) (reduceSeq {step} {init} s)))"
+            f" {_rows_of(view, plan)})")
+
+
+def _combine(lanes: str, plan: Plan, merge: str, init: str) -> str:
+    """Fold the L lane results of one chunk into one value."""
+    if plan.combine == "seq" or plan.lanes == 1:
+        return f"(reduceSeq {merge} {init} {lanes})"
+    v = lanes
+    n = plan.lanes
+    while n > 2:
+        v = (f"((toLocal (lam (v) (mapLocal (lam (q) (reduceSeq {merge} {init} q))"
+             f" (split 2 v)))) {v})")
+        n //= 2
+    return f"(reduceSeq {merge} {init} {v})"
+
+
+def _chunk_value(view: str, plan: Plan, step: str) -> str:
+    if plan.accum == "kahan":
+        return _combine(_lanes(view, plan, step, ZERO_PAIR), plan, KAHAN_MERGE, ZERO_PAIR)
+    return _combine(_lanes(view, plan, step, "0"), plan, ADD, "0")
+
+
+def _final(partials: str, plan: Plan) -> str:
+    if plan.accum == "kahan":
+        if plan.final_f64:
+            return (f"(reduceSeq (lam (p a) (+ (- (f64 (fst p)) (f64 (snd p))) a))"
+                    f" (f64 0) {partials})")
+        return f"((lam (r) (- (fst r) (snd r))) (reduceSeq {KAHAN_MERGE} {ZERO_PAIR} {partials}))"
+    return f"(reduceSeq {ADD} 0 {partials})"
+
+
+def _reduction(n: int, view: str, plan: Plan, step: str) -> str:
+    plan.check()
+    if n % plan.chunk:
+        raise ValueError(f"n={n} is not a multiple of the chunk {plan.chunk}")
+    partials = (f"(mapWorkgroup (lam (ch) {_chunk_value('ch', plan, step)})"
+                f" (split {plan.chunk} {view}))")
+    return _final(partials, plan)
+
+
+def dot_expr(n: int, plan: Plan) -> str:
+    """dot xs ys under ``plan``; inputs ``xs``, ``ys`` of length n."""
+    step = KAHAN_MUL_STEP if plan.accum == "kahan" else MUL_ADD
+    return _reduction(n, "(zip xs ys)", plan, step)
+
+
+def asum_expr(n: int, plan: Plan) -> str:
+    """sum of |xs[i]| under ``plan``; input ``xs`` of length n."""
+    if plan.accum != "plain":
+        raise ValueError("asum is defined for plain accumulation only")
+    return _reduction(n, "xs", plan, ABS_ADD)
+
+
+def gemv_expr(m: int, k: int, plan: Plan, a_format: str = "f32") -> str:
+    """y = A x under ``plan``; inputs ``A`` (m rows of k), ``x`` (k) and, for
+    fp8, ``scale`` (m): row r is ``scale[r] * (row r of decoded A) . x``."""
+    plan.check()
+    if plan.accum != "plain":
+        raise ValueError("gemv is defined for plain accumulation only")
+    if m % plan.rows:
+        raise ValueError(f"m={m} is not a multiple of rows={plan.rows}")
+    part = k // plan.row_parts
+    if k % plan.row_parts or part != plan.chunk:
+        raise ValueError(f"k={k} must equal row_parts*lanes*seq")
+
+    def row_value(row: str) -> str:
+        view = f"(zip {row} x)"
+        if plan.row_parts == 1:
+            return _chunk_value(view, plan, MUL_ADD)
+        halves = f"(map (lam (h) {_chunk_value('h', plan, MUL_ADD)}) (split {part} {view}))"
+        return f"(reduceSeq {ADD} 0 {halves})"
+
+    if a_format == "f32":
+        body = f"(map (lam (row) {row_value('row')}) rows)"
+        src = "A"
+    elif a_format in ("bf16", "fp8"):
+        dec = f"(map (lam (c) ({a_format} c)) {{}})"
+        if a_format == "bf16":
+            body = f"(map (lam (row) {row_value(dec.format('row'))}) rows)"
+            src = "A"
+        else:
+            body = (f"(map (lam (rw) (* (snd rw) {row_value(dec.format('(fst rw)'))}))"
+                    f" rows)")
+            src = "(zip A scale)"
+    else:
+        raise ValueError(f"bad a_format {a_format!r}")
+    return f"(join (mapWorkgroup (lam (rows) {body}) (split {plan.rows} {src})))"
+
+
+# ------------------------------------------------------------------ running
+
+def dot(xs: np.ndarray, ys: np.ndarray, plan: Plan, num: str = "f32"):
+    return evaluate(dot_expr(len(xs), plan), {"xs": xs, "ys": ys}, num)
+
+
+def asum(xs: np.ndarray, plan: Plan, num: str = "f32"):
+    return evaluate(asum_expr(len(xs), plan), {"xs": xs}, num)
+
+
+def gemv(A: np.ndarray, x: np.ndarray, plan: Plan, a_format: str = "f32",
+         scale: np.ndarray = None, num: str = "f32"):
+    inputs = {"A": A, "x": x}
+    if a_format == "fp8":
+        inputs["scale"] = scale
+    return evaluate(gemv_expr(A.shape[0], A.shape[1], plan, a_format), inputs, num)
