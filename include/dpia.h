@@ -1,0 +1,199 @@
+/*
+ * dpia.h -- C ABI of the MI355X (gfx950) strategy-preserving reduction
+ * library: dot, asum and gemv computed under an explicit DPIA
+ * parallelisation strategy, with the floating-point association order the
+ * strategy's functional expression fixes.
+ *
+ * The method: Atkey, Steuwer, Lindley, Dubach, "Strategy Preserving
+ * Compilation for Parallel Functional Code".  A strategy is the blocked
+ * dot-product expression of Sec. 2.1, eq. (2):
+ *
+ *   reduceSeq (+) 0 (mapWorkgroup (lam ch. COMBINE (mapLocal
+ *       (lam s. reduceSeq (lam x a. (fst x * snd x) + a) 0 s) (ROWS ch)))
+ *     (split W (zip xs ys)))
+ *
+ * with W = L*C, ROWS ch = split C ch (contiguous: work-item l folds
+ * elements l*C .. l*C+C-1 of its chunk) or the strided rows l, l+L, ...,
+ * and COMBINE the in-work-group fold of the L work-item results: a binary
+ * tree in local memory (Sec. 6.1 toLocal; every node (0 + left) + right,
+ * leaves in work-item order) or a sequential reduceSeq.  The chunk results
+ * are folded by a sequential reduceSeq from +0 in chunk order (the last
+ * loop of the blocked listing of Sec. 2.2).  map and its hierarchy variants
+ * mean the same (Sec. 6.1) and reduce is a left fold from its initial value
+ * in increasing index order (Sec. 4.2, Stage II), so the strategy fixes
+ * every rounding: results are bit-identical to a CPU evaluation of that
+ * expression, independent of the physical grid, the stream, repetition and
+ * the number of passes.
+ *
+ * Conventions for every call below:
+ *  - Every array argument is a device pointer (hipMalloc'd or a torch CUDA
+ *    tensor's data) owned by the caller; the library never allocates, frees
+ *    or synchronises.  Calls are asynchronous on `stream` (NULL = the
+ *    default stream); results stay in device memory.
+ *  - Arrays are dense, unit-stride, and 16-byte aligned; gemv's A is
+ *    row-major with leading dimension lda (in elements), and
+ *    lda * element size must be a multiple of 16 bytes.
+ *  - All validation happens before any launch.  On an error nothing is
+ *    launched, no output is touched, and a description is available from
+ *    dpia_last_error_detail() in the calling thread.
+ *  - No floating-point atomics are used; the only atomic is an integer
+ *    arrival counter of the 1-pass combine.
+ */
+#ifndef DPIA_H
+#define DPIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPIA_ABI_VERSION 1u
+
+/* Same type as hipStream_t. */
+typedef struct ihipStream_t* dpia_stream_t;
+
+typedef enum {
+  DPIA_OK = 0,
+  DPIA_ERR_NULL = 1,       /* a required pointer is NULL                    */
+  DPIA_ERR_SHAPE = 2,      /* sizes do not fit the strategy, or misaligned   */
+  DPIA_ERR_STRATEGY = 3,   /* invalid descriptor (see dpia_strategy)        */
+  DPIA_ERR_DTYPE = 4,      /* unsupported element / output type combination */
+  DPIA_ERR_WORKSPACE = 5,  /* workspace NULL or smaller than required       */
+  DPIA_ERR_HIP = 6,        /* a HIP launch failed (detail has its text)     */
+  DPIA_ERR_ABI = 7         /* descriptor abi_version != DPIA_ABI_VERSION    */
+} dpia_status;
+
+typedef enum {
+  DPIA_F32 = 0,            /* IEEE binary32                                  */
+  DPIA_F64 = 1,            /* IEEE binary64 (Kahan result only)              */
+  DPIA_I32 = 2,            /* 32-bit integers, arithmetic modulo 2^32        */
+  DPIA_BF16 = 3,           /* bfloat16 storage, decoded exactly to binary32  */
+  DPIA_FP8_E4M3 = 4        /* OCP fp8 E4M3 storage (max 448, no inf)         */
+} dpia_dtype;
+
+typedef enum { DPIA_OP_DOT = 0, DPIA_OP_ASUM = 1, DPIA_OP_GEMV = 2 } dpia_op;
+
+typedef enum {
+  DPIA_ORDER_CONTIGUOUS = 0, /* ROWS ch = split C ch                          */
+  DPIA_ORDER_STRIDED = 1     /* ROWS ch = transpose (split L ch): l, l+L, ... */
+} dpia_order;
+
+typedef enum {
+  DPIA_COMBINE_TREE = 0,     /* pairwise tree over the L lanes, lane order     */
+  DPIA_COMBINE_SEQ = 1       /* reduceSeq (+) 0 over the L lanes              */
+} dpia_combine;
+
+typedef enum {
+  DPIA_ACCUM_PLAIN = 0,      /* binary32 (or integer) accumulators            */
+  DPIA_ACCUM_KAHAN = 1       /* compensated (s, c) accumulators, dot only:
+                                Kahan's step in the lanes (Higham, Accuracy
+                                and Stability of Numerical Algorithms,
+                                Alg. 4.2), Knuth's TwoSum merge in the
+                                combines, value s - c                       */
+} dpia_accum;
+
+/*
+ * Strategy descriptor.  Level assignment is implied: chunks are the
+ * mapWorkgroup level, lanes the mapLocal level, the per-lane fold is
+ * reduceSeq in private memory (toPrivate), a tree combine lives in local
+ * memory (toLocal), chunk results in global memory.
+ *
+ *  seq_len      C, elements folded sequentially by one lane (>= 1)
+ *  local_size   L, lanes per chunk (>= 1; a power of two for a tree)
+ *  order        dpia_order
+ *  wg_combine   dpia_combine (L = 1 always means 0 + lane)
+ *  passes       1: the last work-group to finish folds the chunk results;
+ *               2: a second kernel does.  Same expression, same bits.
+ *               gemv needs no cross-work-group step and takes 1 or 2.
+ *  accum        dpia_accum
+ *  final_f64    Kahan only: fold the chunk values s - c in binary64
+ *  rows_per_wg  gemv: R rows per work-group (M must be a multiple)
+ *  row_parts    gemv: 1, or 2 halves per row, each reduced with (C, L)
+ *               and folded as (0 + h0) + h1
+ *  max_grid     0 = automatic; else an upper bound on launched work-groups
+ *               (work is distributed by a grid-stride loop; no effect on
+ *               the result)
+ */
+typedef struct {
+  uint32_t abi_version;
+  uint32_t seq_len;
+  uint32_t local_size;
+  uint32_t order;
+  uint32_t wg_combine;
+  uint32_t passes;
+  uint32_t accum;
+  uint32_t final_f64;
+  uint32_t rows_per_wg;
+  uint32_t row_parts;
+  uint32_t max_grid;
+} dpia_strategy;
+
+/*
+ * Validate a strategy for an operation and problem size and report the
+ * workspace it needs.  Host only, no HIP call, thread-safe.
+ *   op, dt   operation and input element type (for gemv: the type of A)
+ *   m, n     dot/asum: m ignored, n = vector length;
+ *            gemv: m rows, n = k columns
+ *   ws_bytes_out (may be NULL) receives the workspace size in bytes.
+ */
+dpia_status dpia_strategy_check(const dpia_strategy* s, dpia_op op, dpia_dtype dt,
+                                int64_t m, int64_t n, size_t* ws_bytes_out);
+
+/*
+ * out[0] = dot(x, y) under strategy s (Sec. 2.1, eq. (2)).
+ *   dt       DPIA_F32 or DPIA_I32 (both x and y)
+ *   n        length; a multiple of W = seq_len * local_size (n = 0 gives +0)
+ *   out_dt   DPIA_F32 for F32 input, DPIA_I32 for I32, DPIA_F64 allowed only
+ *            with accum = KAHAN and final_f64 = 1 (else the binary64 fold is
+ *            rounded once to binary32)
+ *   ws       device workspace of at least dpia_strategy_check's size.  Its
+ *            arrival-counter word must be zero before the first 1-pass call
+ *            on it (allocate it zeroed); every call leaves it zero.  Calls
+ *            sharing one workspace must be ordered (same stream).
+ */
+dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                     const void* y, void* out, dpia_dtype out_dt, void* ws, size_t ws_bytes,
+                     dpia_stream_t stream);
+
+/*
+ * out[0] = sum |x[i]| under strategy s, with the per-lane operator
+ * lam x a. abs x + a (the paper benchmarks asum, Sec. 7.1; abs is the one
+ * scalar primitive added to Fig. 5a).  dt = out_dt = DPIA_F32, plain only.
+ * Workspace rules as for dpia_dot.
+ */
+dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                      void* out, dpia_dtype out_dt, void* ws, size_t ws_bytes,
+                      dpia_stream_t stream);
+
+/*
+ * y = A x (BLAS gemv, alpha = 1, beta = 0; Sec. 7.1 benchmark): every row is
+ * reduced like a dot product of that row with x under (C, L, order,
+ * combine), R rows per work-group.
+ *   a_dt       DPIA_F32, DPIA_BF16, DPIA_FP8_E4M3 (binary32 accumulation of
+ *              decoded values) or DPIA_I32 (then x, y are I32 too)
+ *   m, k, lda  A is m x k row-major with leading dimension lda >= k;
+ *              k = seq_len * local_size * row_parts, m a multiple of R
+ *   row_scale  FP8 only (else NULL): y[r] = row_scale[r] * (row r . x)
+ *   x, y       k and m elements (binary32, or I32 with an I32 A)
+ *   ws         unused (pass NULL, 0)
+ */
+dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
+                      int64_t lda, const void* A, const float* row_scale, const void* x,
+                      void* y, void* ws, size_t ws_bytes, dpia_stream_t stream);
+
+/* Static text for a status code. */
+const char* dpia_status_str(dpia_status st);
+
+/* Description of the last error in the calling thread ("" if none). */
+const char* dpia_last_error_detail(void);
+
+/* DPIA_ABI_VERSION of the loaded library. */
+uint32_t dpia_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPIA_H */

@@ -1,0 +1,149 @@
+"""MI355X strategy-preserving dot / asum / gemv (DPIA strategies on gfx950).
+
+Thin Python binding of include/dpia.h: argument marshalling only.  Every
+step of the computation runs in the HIP kernels of libdpia.so; PyTorch
+supplies device memory and the current stream.  See the header for the
+semantics of a strategy and of each entry point.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, replace
+
+from . import _lib
+from ._lib import (BF16, CONTIGUOUS, F32, F64, FP8_E4M3, I32, KAHAN, OP_ASUM, OP_DOT,  # noqa: F401
+                   OP_GEMV, PLAIN, SEQ, STRIDED, TREE, DpiaError, last_error_detail)
+
+
+@dataclass(frozen=True)
+class Strategy:
+    """Mirror of dpia_strategy (include/dpia.h)."""
+    seq_len: int                  # C: elements folded sequentially per lane
+    local_size: int               # L: lanes per chunk
+    order: int = CONTIGUOUS       # CONTIGUOUS | STRIDED
+    wg_combine: int = TREE        # TREE | SEQ
+    passes: int = 2               # 1 | 2
+    accum: int = PLAIN            # PLAIN | KAHAN
+    final_f64: int = 0
+    rows_per_wg: int = 1
+    row_parts: int = 1
+    max_grid: int = 0
+
+    def c(self) -> _lib.CStrategy:
+        return _lib.CStrategy(_lib.ABI_VERSION, self.seq_len, self.local_size, self.order,
+                              self.wg_combine, self.passes, self.accum, self.final_f64,
+                              self.rows_per_wg, self.row_parts, self.max_grid)
+
+    def with_(self, **kw) -> "Strategy":
+        return replace(self, **kw)
+
+
+def strategy_check(s: Strategy, op: int, dtype: int, m: int, n: int) -> int:
+    """Validates ``s`` for the problem; returns the workspace size in bytes."""
+    cs = s.c()
+    ws = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().dpia_strategy_check(ctypes.byref(cs), op, dtype, m, n,
+                                              ctypes.byref(ws)), "dpia_strategy_check")
+    return ws.value
+
+
+# ------------------------------------------------------------ torch glue
+
+def _torch():
+    import torch
+    return torch
+
+
+_DT = {}
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if not _DT:
+        _DT.update({torch.float32: F32, torch.float64: F64, torch.int32: I32,
+                    torch.uint32: I32, torch.bfloat16: BF16, torch.uint16: BF16,
+                    torch.float8_e4m3fn: FP8_E4M3, torch.uint8: FP8_E4M3})
+    if t.dtype not in _DT:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    return _DT[t.dtype]
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(s: Strategy, op: int, dtype: int, m: int, n: int, device="cuda"):
+    """A zeroed workspace tensor of the size the strategy needs (or None)."""
+    nbytes = strategy_check(s, op, dtype, m, n)
+    if nbytes == 0:
+        return None
+    return _torch().zeros(nbytes, dtype=_torch().uint8, device=device)
+
+
+def _ws(ws):
+    if ws is None:
+        return ctypes.c_void_p(0), 0
+    return _dev(ws), ws.numel() * ws.element_size()
+
+
+def dot(x, y, s: Strategy, out=None, ws=None, out_dtype=None, stream=None):
+    torch = _torch()
+    dt = _dtype_code(x)
+    if _dtype_code(y) != dt:
+        raise TypeError("x and y must have the same dtype")
+    n = x.numel()
+    if out is None:
+        od = out_dtype or (torch.float64 if (s.accum == KAHAN and s.final_f64) else x.dtype)
+        out = torch.empty(1, dtype=od, device=x.device)
+    if ws is None:
+        ws = workspace(s, OP_DOT, dt, 0, n, x.device)
+    cs = s.c()
+    w, wb = _ws(ws)
+    _lib.check(_lib.lib().dpia_dot(ctypes.byref(cs), dt, n, _dev(x), _dev(y), _dev(out),
+                                   _dtype_code(out), w, wb, _stream(stream)), "dpia_dot")
+    return out
+
+
+def asum(x, s: Strategy, out=None, ws=None, stream=None):
+    torch = _torch()
+    n = x.numel()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=x.device)
+    if ws is None:
+        ws = workspace(s, OP_ASUM, F32, 0, n, x.device)
+    cs = s.c()
+    w, wb = _ws(ws)
+    _lib.check(_lib.lib().dpia_asum(ctypes.byref(cs), _dtype_code(x), n, _dev(x), _dev(out),
+                                    _dtype_code(out), w, wb, _stream(stream)), "dpia_asum")
+    return out
+
+
+def gemv(A, x, s: Strategy, y=None, row_scale=None, a_dtype=None, stream=None):
+    """y = A x.  ``A`` is a 2-D row-major tensor (float32, bfloat16 / uint16
+    codes, float8_e4m3fn / uint8 codes, or int32); ``a_dtype`` overrides the
+    element type read from A's dtype."""
+    torch = _torch()
+    m, k = A.shape
+    adt = a_dtype if a_dtype is not None else _dtype_code(A)
+    lda = A.stride(0)
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major")
+    if y is None:
+        y = torch.empty(m, dtype=torch.int32 if adt == I32 else torch.float32, device=A.device)
+    cs = s.c()
+    sc = _dev(row_scale) if row_scale is not None else ctypes.c_void_p(0)
+    _lib.check(_lib.lib().dpia_gemv(ctypes.byref(cs), adt, m, k, lda,
+                                    ctypes.c_void_p(A.data_ptr()), sc, _dev(x), _dev(y),
+                                    ctypes.c_void_p(0), 0, _stream(stream)), "dpia_gemv")
+    return y

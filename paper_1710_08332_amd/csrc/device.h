@@ -1,0 +1,208 @@
+// Device building blocks shared by the reduction and gemv kernels.
+//
+// A strategy (blocked dot product, Sec. 2.1 eq. (2)) is run as follows.
+// A "team" of threads evaluates one chunk (one mapWorkgroup iteration): each
+// of the chunk's L lanes (mapLocal iterations) folds its C elements with
+// reduceSeq in registers (toPrivate), then the team combines the L lane
+// values (tree or sequential).  Which hardware thread holds which lane, and
+// how many lanes or elements one load brings in, changes no operation and no
+// operand order: every lane still folds its own elements in increasing
+// index, and every combine node is (0 + left) + right on the same operands.
+//
+// Compiled with -ffp-contract=off (and the pragma below): every product and
+// every sum is rounded on its own, as the expression says.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#pragma clang fp contract(off)
+
+namespace dpia {
+
+enum : int { kContiguous = 0, kStrided = 1 };
+enum : int { kTree = 0, kSeq = 1 };
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Load NV consecutive elements of type E from an address aligned to
+// min(16, NV * sizeof(E)) bytes, with the widest loads that fit.
+template <typename E, int NV>
+__device__ __forceinline__ void vload(const E* __restrict__ p, E (&out)[NV]) {
+  constexpr int B = static_cast<int>(sizeof(E)) * NV;
+  const char* src = reinterpret_cast<const char*>(p);
+  char* dst = reinterpret_cast<char*>(out);
+  if constexpr (B >= 16) {
+#pragma unroll
+    for (int i = 0; i < B / 16; ++i) {
+      u32x4 r = *reinterpret_cast<const u32x4*>(src + 16 * i);
+      __builtin_memcpy(dst + 16 * i, &r, 16);
+    }
+  } else if constexpr (B == 8) {
+    u32x2 r = *reinterpret_cast<const u32x2*>(src);
+    __builtin_memcpy(dst, &r, 8);
+  } else if constexpr (B == 4) {
+    unsigned int r = *reinterpret_cast<const unsigned int*>(src);
+    __builtin_memcpy(dst, &r, 4);
+  } else if constexpr (B == 2) {
+    unsigned short r = *reinterpret_cast<const unsigned short*>(src);
+    __builtin_memcpy(dst, &r, 2);
+  } else {
+    static_assert(B == 1, "unsupported vector width");
+    out[0] = p[0];
+  }
+}
+
+// ------------------------------------------------------------ accumulators
+// Each accumulator type provides zero() (the literal 0 of the expression,
+// +0 for binary32) and add(e, acc) = the reduceSeq operator (+) applied to an
+// element e and the accumulator acc (element first, as in the paper's
+// reduce), plus warp shuffles for the tree.
+
+struct PlainF32 {
+  using T = float;
+  __device__ static T zero() { return 0.0f; }
+  __device__ static T add(T e, T acc) { return e + acc; }
+  __device__ static T shfl_xor(T v, int d) { return __shfl_xor(v, d, 64); }
+};
+
+struct PlainU32 {
+  using T = uint32_t;
+  __device__ static T zero() { return 0u; }
+  __device__ static T add(T e, T acc) { return e + acc; }
+  __device__ static T shfl_xor(T v, int d) {
+    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), d, 64));
+  }
+};
+
+// Compensated pair (s, c), value s - c.  add(r, l) merges a later pair r
+// into an earlier accumulator l with Knuth's TwoSum:
+//   s = l.s + r.s ; bp = s - l.s ; e = (l.s - (s - bp)) + (r.s - bp) ;
+//   result (s, (l.c + r.c) - e).
+struct KPair {
+  float s, c;
+};
+
+struct KahanF32 {
+  using T = KPair;
+  __device__ static T zero() { return KPair{0.0f, 0.0f}; }
+  __device__ static T add(T r, T l) {
+    const float s = l.s + r.s;
+    const float bp = s - l.s;
+    const float e = (l.s - (s - bp)) + (r.s - bp);
+    return KPair{s, (l.c + r.c) - e};
+  }
+  __device__ static T shfl_xor(T v, int d) {
+    return KPair{__shfl_xor(v.s, d, 64), __shfl_xor(v.c, d, 64)};
+  }
+};
+
+// One node of the pairwise tree: reduceSeq (+) 0 over [left, right].
+template <class A>
+__device__ __forceinline__ typename A::T tree_node(typename A::T left, typename A::T right) {
+  return A::add(right, A::add(left, A::zero()));
+}
+
+// ------------------------------------------------------------ team combine
+// Combine the lane values of one chunk.  `acc` holds the NL lane values of
+// this thread (NL = lanes per thread: NV for the strided order, 1 for the
+// contiguous order), lanes t*NL .. t*NL + NL-1 of the team.  Returns the
+// chunk value in team thread 0.  `scratch` is this team's LDS region.  All
+// threads of the work-group must call this together (it has barriers).
+template <class A, int NL, int COMBINE>
+__device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL], int t, int team,
+                                                       int L, typename A::T* scratch) {
+  using T = typename A::T;
+  if constexpr (COMBINE == kSeq) {
+#pragma unroll
+    for (int v = 0; v < NL; ++v) scratch[t * NL + v] = acc[v];
+    __syncthreads();
+    T r = A::zero();
+    if (t == 0) {
+      for (int l = 0; l < L; ++l) r = A::add(scratch[l], r);
+    }
+    __syncthreads();
+    return r;
+  } else {
+    // levels inside the thread: adjacent lane pairs
+#pragma unroll
+    for (int w = NL; w > 1; w >>= 1) {
+#pragma unroll
+      for (int i = 0; i < w / 2; ++i) acc[i] = tree_node<A>(acc[2 * i], acc[2 * i + 1]);
+    }
+    T v = acc[0];
+    // levels across the threads of one wavefront: butterfly over ascending
+    // distances pairs thread t with t^d, the lower one holding the left node
+    const int in_wave = team < 64 ? team : 64;
+    for (int d = 1; d < in_wave; d <<= 1) {
+      T other = A::shfl_xor(v, d);
+      v = (t & d) ? tree_node<A>(other, v) : tree_node<A>(v, other);
+    }
+    if (team > 64) {
+      // levels across wavefronts, through LDS
+      const int waves = team / 64;
+      if ((t & 63) == 0) scratch[t >> 6] = v;
+      __syncthreads();
+      if (t < 64) {
+        v = (t < waves) ? scratch[t] : A::zero();
+        for (int d = 1; d < waves; d <<= 1) {
+          T other = A::shfl_xor(v, d);
+          v = (t & d) ? tree_node<A>(other, v) : tree_node<A>(v, other);
+        }
+      }
+      __syncthreads();
+    }
+    return v;
+  }
+}
+
+// ------------------------------------------------------------ lane folds
+// Fold the lanes of one chunk.  `view` gives element access relative to the
+// chunk start: view.template load<NV>(off, terms) loads elements off ..
+// off+NV-1 and Op::step(term, acc) is the lane operator.
+template <class Op, int ORDER, int NV, class View>
+__device__ __forceinline__ void lane_folds(const View& view, bool active, int t, int L, int C,
+                                           typename Op::T (&acc)[ORDER == kStrided ? NV : 1]) {
+  using Term = typename Op::Term;
+  if constexpr (ORDER == kStrided) {
+    // lane l = t*NV + v folds elements l, l + L, l + 2L, ...
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = Op::Arith::zero();
+    if (!active) return;
+    int off = t * NV;
+#pragma unroll 8
+    for (int k = 0; k < C; ++k) {
+      Term z[NV];
+      view.template load<NV>(off, z);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = Op::step(z[v], acc[v]);
+      off += L;
+    }
+  } else {
+    // lane l = t folds elements l*C, l*C + 1, ..., NV of them per load
+    acc[0] = Op::Arith::zero();
+    if (!active) return;
+    const int base = t * C;
+#pragma unroll 4
+    for (int k = 0; k < C; k += NV) {
+      Term z[NV];
+      view.template load<NV>(base + k, z);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[0] = Op::step(z[v], acc[0]);
+    }
+  }
+}
+
+template <class Op, int ORDER, int NV, int COMBINE, class View>
+__device__ __forceinline__ typename Op::T chunk_value(const View& view, bool active, int t,
+                                                      int team, int L, int C,
+                                                      typename Op::T* scratch) {
+  constexpr int NL = (ORDER == kStrided) ? NV : 1;
+  typename Op::T acc[NL];
+  lane_folds<Op, ORDER, NV>(view, active, t, L, C, acc);
+  return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
+}
+
+}  // namespace dpia

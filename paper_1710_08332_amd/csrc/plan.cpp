@@ -1,0 +1,232 @@
+// Strategy validation and launch planning.  Pure host C++: no HIP call, so
+// it also runs on machines without a GPU.
+#include "plan.h"
+
+#include <sstream>
+
+namespace dpia {
+
+namespace {
+
+thread_local std::string g_detail;
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Largest power of two <= cap that divides every value in `vals`.
+int widest_vector(int cap, std::initializer_list<int64_t> vals) {
+  int v = cap;
+  while (v > 1) {
+    bool ok = true;
+    for (int64_t x : vals) ok = ok && (x % v == 0);
+    if (ok) break;
+    v >>= 1;
+  }
+  return v;
+}
+
+dpia_status fail(std::string* detail, dpia_status st, const std::string& msg) {
+  if (detail) *detail = msg;
+  return st;
+}
+
+}  // namespace
+
+void set_detail(const std::string& d) { g_detail = d; }
+void clear_detail() { g_detail.clear(); }
+const char* detail_cstr() { return g_detail.c_str(); }
+
+size_t elem_bytes(dpia_dtype dt) {
+  switch (dt) {
+    case DPIA_F32: return 4;
+    case DPIA_F64: return 8;
+    case DPIA_I32: return 4;
+    case DPIA_BF16: return 2;
+    case DPIA_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t m,
+                      int64_t n, Plan* p, std::string* detail) {
+  std::ostringstream os;
+  if (!s) return fail(detail, DPIA_ERR_NULL, "strategy descriptor is NULL");
+  if (s->abi_version != DPIA_ABI_VERSION) {
+    os << "descriptor abi_version " << s->abi_version << " != library " << DPIA_ABI_VERSION;
+    return fail(detail, DPIA_ERR_ABI, os.str());
+  }
+  if (op != DPIA_OP_DOT && op != DPIA_OP_ASUM && op != DPIA_OP_GEMV)
+    return fail(detail, DPIA_ERR_STRATEGY, "unknown operation");
+  if (s->seq_len < 1 || s->local_size < 1)
+    return fail(detail, DPIA_ERR_STRATEGY, "seq_len and local_size must be >= 1");
+  if (s->order > DPIA_ORDER_STRIDED) return fail(detail, DPIA_ERR_STRATEGY, "unknown order");
+  if (s->wg_combine > DPIA_COMBINE_SEQ)
+    return fail(detail, DPIA_ERR_STRATEGY, "unknown wg_combine");
+  if (s->passes != 1 && s->passes != 2)
+    return fail(detail, DPIA_ERR_STRATEGY, "passes must be 1 or 2");
+  if (s->accum > DPIA_ACCUM_KAHAN) return fail(detail, DPIA_ERR_STRATEGY, "unknown accum");
+  if (s->final_f64 > 1) return fail(detail, DPIA_ERR_STRATEGY, "final_f64 must be 0 or 1");
+  if (s->final_f64 && s->accum != DPIA_ACCUM_KAHAN)
+    return fail(detail, DPIA_ERR_STRATEGY, "final_f64 applies to the Kahan accumulation only");
+  if (s->wg_combine == DPIA_COMBINE_TREE && !is_pow2(s->local_size))
+    return fail(detail, DPIA_ERR_STRATEGY, "a tree combine needs a power-of-two local_size");
+  if (s->rows_per_wg < 1) return fail(detail, DPIA_ERR_STRATEGY, "rows_per_wg must be >= 1");
+  if (s->row_parts != 1 && s->row_parts != 2)
+    return fail(detail, DPIA_ERR_STRATEGY, "row_parts must be 1 or 2");
+
+  // element types
+  if (op == DPIA_OP_DOT) {
+    if (dt != DPIA_F32 && dt != DPIA_I32)
+      return fail(detail, DPIA_ERR_DTYPE, "dot takes F32 or I32 vectors");
+    if (s->accum == DPIA_ACCUM_KAHAN && dt != DPIA_F32)
+      return fail(detail, DPIA_ERR_DTYPE, "Kahan accumulation is defined for F32 only");
+  } else if (op == DPIA_OP_ASUM) {
+    if (dt != DPIA_F32) return fail(detail, DPIA_ERR_DTYPE, "asum takes F32 vectors");
+    if (s->accum != DPIA_ACCUM_PLAIN)
+      return fail(detail, DPIA_ERR_STRATEGY, "asum supports plain accumulation only");
+  } else {
+    if (dt != DPIA_F32 && dt != DPIA_BF16 && dt != DPIA_FP8_E4M3 && dt != DPIA_I32)
+      return fail(detail, DPIA_ERR_DTYPE, "gemv takes an F32, BF16, FP8_E4M3 or I32 matrix");
+    if (s->accum != DPIA_ACCUM_PLAIN)
+      return fail(detail, DPIA_ERR_STRATEGY, "gemv supports plain accumulation only");
+  }
+  if (op != DPIA_OP_GEMV && (s->rows_per_wg != 1 || s->row_parts != 1))
+    return fail(detail, DPIA_ERR_STRATEGY, "rows_per_wg and row_parts apply to gemv only");
+
+  Plan q{};
+  q.op = op;
+  q.dt = dt;
+  q.order = s->order;
+  q.L = s->local_size;
+  q.C = s->seq_len;
+  q.W = q.L * q.C;
+  q.combine = (q.L == 1) ? static_cast<uint32_t>(DPIA_COMBINE_SEQ) : s->wg_combine;
+  q.accum = s->accum;
+  q.final_f64 = s->final_f64 != 0;
+  q.passes = s->passes;
+  q.max_grid = s->max_grid;
+  q.row_parts = static_cast<int>(s->row_parts);
+  q.R = static_cast<int>(s->rows_per_wg);
+  q.acc_bytes = (q.accum == DPIA_ACCUM_KAHAN) ? 8 : 4;
+
+  const int cap = kVecBytes / static_cast<int>(elem_bytes(dt));
+  if (op == DPIA_OP_GEMV) {
+    int64_t k = n;
+    if (m < 0 || k < 0) return fail(detail, DPIA_ERR_SHAPE, "negative gemv size");
+    if (m % q.R) {
+      os << "m = " << m << " is not a multiple of rows_per_wg = " << q.R;
+      return fail(detail, DPIA_ERR_SHAPE, os.str());
+    }
+    if (k != q.W * q.row_parts) {
+      os << "k = " << k << " must equal seq_len * local_size * row_parts = " << q.W * q.row_parts;
+      return fail(detail, DPIA_ERR_SHAPE, os.str());
+    }
+    q.k = k;
+    q.items = m;
+  } else {
+    if (n < 0) return fail(detail, DPIA_ERR_SHAPE, "negative length");
+    if (n % q.W) {
+      os << "n = " << n << " is not a multiple of the chunk W = seq_len * local_size = " << q.W;
+      return fail(detail, DPIA_ERR_SHAPE, os.str());
+    }
+    q.items = n / q.W;
+  }
+  if (q.W >= (int64_t(1) << 31)) {
+    os << "chunk W = seq_len * local_size = " << q.W << " must be below 2^31";
+    return fail(detail, DPIA_ERR_STRATEGY, os.str());
+  }
+
+  // Vector width (semantics-free: it decides which lanes or elements one
+  // thread loads at once, never the order of any operation).
+  if (q.order == DPIA_ORDER_STRIDED) {
+    q.nv = widest_vector(cap, {q.L});
+    q.team = static_cast<int>(q.L / q.nv);
+  } else {
+    q.nv = widest_vector(cap, {q.C});
+    q.team = static_cast<int>(q.L);
+  }
+  if (q.team > 1024) {
+    os << "one chunk would need " << q.team << " threads (> 1024); reduce local_size";
+    return fail(detail, DPIA_ERR_STRATEGY, os.str());
+  }
+  if (op == DPIA_OP_GEMV) {
+    if (static_cast<int64_t>(q.team) * q.R > 1024) {
+      os << "rows_per_wg * threads per row = " << int64_t(q.team) * q.R << " > 1024";
+      return fail(detail, DPIA_ERR_STRATEGY, os.str());
+    }
+    int lg = 256 / (q.team * q.R);
+    if (lg < 1) lg = 1;
+    q.teams_per_wg = lg * q.R;
+  } else {
+    q.teams_per_wg = q.team >= 256 ? 1 : 256 / q.team;
+  }
+  q.wg_threads = q.teams_per_wg * q.team;
+
+  // LDS: lane values for a sequential combine, one value per wave for a
+  // tree wider than a wavefront, and the staging block of the final fold.
+  size_t lds = 0;
+  if (q.combine == DPIA_COMBINE_SEQ) {
+    lds = static_cast<size_t>(q.teams_per_wg) * q.L * q.acc_bytes;
+  } else if (q.team > 64) {
+    lds = static_cast<size_t>(q.teams_per_wg) * (q.team / 64) * q.acc_bytes;
+  }
+  if (op != DPIA_OP_GEMV) {
+    size_t fold = static_cast<size_t>(kFoldBlock) * q.acc_bytes;
+    if (fold > lds) lds = fold;
+  }
+  lds = round_up(lds + 16, 16);
+  if (lds > 64 * 1024) {
+    os << "strategy needs " << lds << " bytes of LDS per work-group (> 65536)";
+    return fail(detail, DPIA_ERR_STRATEGY, os.str());
+  }
+  q.lds_bytes = lds;
+
+  if (op == DPIA_OP_GEMV) {
+    q.partial_bytes = 0;
+    q.ws_bytes = 0;
+  } else {
+    q.partial_bytes = round_up(static_cast<size_t>(q.items) * q.acc_bytes, kWsAlign);
+    q.ws_bytes = q.partial_bytes + kWsAlign;   // + the arrival counter
+  }
+  *p = q;
+  return DPIA_OK;
+}
+
+}  // namespace dpia
+
+extern "C" {
+
+dpia_status dpia_strategy_check(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t m,
+                                int64_t n, size_t* ws_bytes_out) {
+  dpia::Plan p;
+  std::string detail;
+  dpia_status st = dpia::make_plan(s, op, dt, m, n, &p, &detail);
+  if (st != DPIA_OK) {
+    dpia::set_detail(detail);
+    return st;
+  }
+  dpia::clear_detail();
+  if (ws_bytes_out) *ws_bytes_out = p.ws_bytes;
+  return DPIA_OK;
+}
+
+const char* dpia_status_str(dpia_status st) {
+  switch (st) {
+    case DPIA_OK: return "ok";
+    case DPIA_ERR_NULL: return "null pointer";
+    case DPIA_ERR_SHAPE: return "shape does not fit the strategy";
+    case DPIA_ERR_STRATEGY: return "invalid strategy";
+    case DPIA_ERR_DTYPE: return "unsupported dtype";
+    case DPIA_ERR_WORKSPACE: return "workspace too small";
+    case DPIA_ERR_HIP: return "HIP error";
+    case DPIA_ERR_ABI: return "ABI version mismatch";
+  }
+  return "unknown status";
+}
+
+const char* dpia_last_error_detail(void) { return dpia::detail_cstr(); }
+
+uint32_t dpia_abi_version(void) { return DPIA_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Internal launch plan shared by the validation unit (plan.cpp, no HIP) and
+// the kernel dispatch (dpia_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "dpia.h"
+
+namespace dpia {
+
+// Bytes of one 16-byte vector load, the widest global load used.
+constexpr int kVecBytes = 16;
+// Chunk results staged through LDS per block by the final sequential fold.
+constexpr int kFoldBlock = 2048;
+// Alignment of the sections of a workspace.
+constexpr size_t kWsAlign = 256;
+
+struct Plan {
+  dpia_op op;
+  dpia_dtype dt;          // input element type (gemv: type of A)
+  uint32_t order;         // dpia_order
+  uint32_t combine;       // dpia_combine (already SEQ when L == 1)
+  uint32_t accum;         // dpia_accum
+  bool final_f64;
+  uint32_t passes;
+
+  int64_t L, C, W;        // lanes, elements per lane, elements per chunk
+  int64_t items;          // dot/asum: chunks G = n / W; gemv: rows m
+  int64_t k, lda;         // gemv only
+  int row_parts, R;       // gemv only
+
+  int nv;                 // strided: lanes per thread; contiguous: elements
+                          // per vector load of one lane
+  int team;               // threads cooperating on one chunk (P)
+  int teams_per_wg;       // chunks (rows) a hardware work-group holds at once
+  int wg_threads;         // teams_per_wg * team
+  uint32_t max_grid;      // 0 = automatic
+
+  size_t acc_bytes;       // bytes of one chunk result (8 for a Kahan pair)
+  size_t partial_bytes;   // workspace bytes for the chunk results (aligned)
+  size_t ws_bytes;        // total workspace: partials + arrival counter
+  size_t lds_bytes;       // dynamic LDS per work-group
+};
+
+size_t elem_bytes(dpia_dtype dt);
+
+// Validates and fills `p`.  On error returns the status and sets `detail`.
+dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t m,
+                      int64_t n, Plan* p, std::string* detail);
+
+// Thread-local error detail (set by every failing entry point).
+void set_detail(const std::string& d);
+void clear_detail();
+const char* detail_cstr();
+
+}  // namespace dpia

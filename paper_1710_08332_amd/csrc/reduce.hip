@@ -1,0 +1,323 @@
+// dot and asum under a DPIA strategy (blocked dot product, Sec. 2.1 eq. (2);
+// asum and dot are benchmarks of Sec. 7.1).
+//
+// Kernel 1 evaluates the mapWorkgroup level: every chunk of W = L*C elements
+// is reduced by one team (lane folds, then the work-group combine) and its
+// value is written to the workspace, partial[g] (the hoisted newGlobal
+// temporary of Sec. 6.3: one slot per parforWorkgroup iteration).  The outer
+// reduceSeq over partial[0..G) from +0 in chunk order then runs either in a
+// second kernel (2 passes) or in the last work-group to finish (1 pass:
+// release fence, integer arrival counter, acquire fence).  Both evaluate the
+// same expression and give the same bits.
+#include "device.h"
+#include "host.h"
+#include "plan.h"
+
+namespace dpia {
+
+struct TermF { float a, b; };
+struct TermA { float a; };
+struct TermU { uint32_t a, b; };
+
+// zip xs ys with lane operator lam z a. (fst z * snd z) + a
+struct DotF32 {
+  using Arith = PlainF32;
+  using T = float;
+  using Term = TermF;
+  struct View {
+    const float* x;
+    const float* y;
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      float a[NV], b[NV];
+      vload<float, NV>(x + off, a);
+      vload<float, NV>(y + off, b);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
+    }
+  };
+  const float* x;
+  const float* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+};
+
+// integers modulo 2^32, same expression
+struct DotU32 {
+  using Arith = PlainU32;
+  using T = uint32_t;
+  using Term = TermU;
+  struct View {
+    const uint32_t* x;
+    const uint32_t* y;
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      uint32_t a[NV], b[NV];
+      vload<uint32_t, NV>(x + off, a);
+      vload<uint32_t, NV>(y + off, b);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
+    }
+  };
+  const uint32_t* x;
+  const uint32_t* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+};
+
+// xs with lane operator lam x a. abs x + a
+struct AsumF32 {
+  using Arith = PlainF32;
+  using T = float;
+  using Term = TermA;
+  struct View {
+    const float* x;
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      float a[NV];
+      vload<float, NV>(x + off, a);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i]};
+    }
+  };
+  const float* x;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return fabsf(z.a) + acc; }
+};
+
+// zip xs ys with Kahan's step on acc = (s, c):
+//   y' = x*y - c ; t = s + y' ; new acc = (t, (t - s) - y')
+struct KahanDotF32 {
+  using Arith = KahanF32;
+  using T = KPair;
+  using Term = TermF;
+  using View = DotF32::View;
+  const float* x;
+  const float* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) {
+    const float yk = z.a * z.b - acc.c;
+    const float t = acc.s + yk;
+    return KPair{t, (t - acc.s) - yk};
+  }
+};
+
+enum : int { kFinalPlain = 0, kFinalKahan32 = 1, kFinalKahan64 = 2 };
+
+struct ReduceArgs {
+  int64_t items;          // G chunks
+  int64_t W;
+  int L, C, team, teams_per_wg;
+  int team_lds_elems;     // LDS elements of T per team
+  int one_pass;
+  int out_f64;            // Kahan 64 only: write a double
+  void* partials;
+  unsigned int* counter;
+  void* out;
+};
+
+// The outer reduceSeq over the G chunk values, from the literal 0, in chunk
+// order, by one thread; values are staged through LDS in blocks.
+template <class A, int FINAL>
+__device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
+                           typename A::T* buf) {
+  using T = typename A::T;
+  T acc = A::zero();
+  double acc64 = 0.0;
+  for (int64_t b = 0; b < G; b += kFoldBlock) {
+    const int cnt = static_cast<int>(G - b < kFoldBlock ? G - b : kFoldBlock);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[i] = partials[b + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if constexpr (FINAL == kFinalKahan64) {
+        for (int i = 0; i < cnt; ++i) {
+          const T e = buf[i];
+          acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
+        }
+      } else {
+        for (int i = 0; i < cnt; ++i) acc = A::add(buf[i], acc);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if constexpr (FINAL == kFinalKahan64) {
+      if (out_f64)
+        *static_cast<double*>(out) = acc64;
+      else
+        *static_cast<float*>(out) = static_cast<float>(acc64);
+    } else if constexpr (FINAL == kFinalKahan32) {
+      *static_cast<float*>(out) = acc.s - acc.c;
+    } else {
+      *static_cast<T*>(out) = acc;
+    }
+  }
+}
+
+template <class Op, int ORDER, int NV, int COMBINE, int FINAL>
+__global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
+  using T = typename Op::T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int is_last;
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const int team_id = threadIdx.x / a.team;
+  const int t = threadIdx.x - team_id * a.team;
+  T* scratch = lds + team_id * a.team_lds_elems;
+  T* partials = static_cast<T*>(a.partials);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
+  // parforWorkgroup as a grid-stride loop: every thread of a work-group
+  // runs the same iterations, so the barriers inside are uniform
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.items;
+       base += stride) {
+    const int64_t g = base + team_id;
+    const bool active = g < a.items;
+    const auto view = op.chunk(active ? g : 0, a.W);
+    const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, scratch);
+    if (active && t == 0) partials[g] = v;
+  }
+  if (a.one_pass) {
+    __threadfence();            // release this work-group's partials
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev = atomicAdd(a.counter, 1u);
+      is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+      __threadfence();          // acquire every work-group's partials
+      final_fold<typename Op::Arith, FINAL>(partials, a.items, a.out, a.out_f64, lds);
+      if (threadIdx.x == 0) atomicExch(a.counter, 0u);   // ready for the next call
+    }
+  }
+}
+
+template <class A, int FINAL>
+__global__ void __launch_bounds__(256) final_kernel(const typename A::T* partials, int64_t G,
+                                                    void* out, int out_f64) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  final_fold<A, FINAL>(partials, G, out, out_f64, reinterpret_cast<typename A::T*>(lds_raw));
+}
+
+template <class Op, int FINAL>
+hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* ws,
+                         hipStream_t stream) {
+  using T = typename Op::T;
+  ReduceArgs a{};
+  a.items = p.items;
+  a.W = p.W;
+  a.L = static_cast<int>(p.L);
+  a.C = static_cast<int>(p.C);
+  a.team = p.team;
+  a.teams_per_wg = p.teams_per_wg;
+  a.team_lds_elems = (p.combine == DPIA_COMBINE_SEQ) ? static_cast<int>(p.L)
+                                                     : (p.team > 64 ? p.team / 64 : 1);
+  a.out_f64 = out_f64;
+  a.partials = ws;
+  a.counter = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + p.partial_bytes);
+  a.out = out;
+  const bool two_pass = p.passes == 2 || p.items == 0;
+  a.one_pass = two_pass ? 0 : 1;
+
+  if (p.items > 0) {
+    const int64_t grid = grid_size(p);
+    hipError_t e = with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
+      constexpr int ORDER = decltype(ord)::value;
+      constexpr int COMBINE = decltype(comb)::value;
+      constexpr int MAXNV = kVecBytes / static_cast<int>(sizeof(float));
+      return with_nv<MAXNV>(p.nv, [&](auto nvc) {
+        constexpr int NV = decltype(nvc)::value;
+        auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL>;
+        Op op_copy = op;
+        void* args[] = {&op_copy, &a};
+        return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                               dim3(p.wg_threads), args, p.lds_bytes, stream);
+      });
+    });
+    if (e != hipSuccess) return e;
+  }
+  if (two_pass) {
+    const T* partials = static_cast<const T*>(ws);
+    int64_t G = p.items;
+    void* args[] = {&partials, &G, &out, &out_f64};
+    auto kern = final_kernel<typename Op::Arith, FINAL>;
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(1), dim3(256), args,
+                           kFoldBlock * sizeof(T), stream);
+  }
+  return hipSuccess;
+}
+
+namespace {
+
+dpia_status check_ws(const Plan& p, void* ws, size_t ws_bytes) {
+  if (ws_bytes < p.ws_bytes) {
+    return bad(DPIA_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) +
+                                       " bytes is smaller than the required " +
+                                       std::to_string(p.ws_bytes));
+  }
+  if (p.ws_bytes && !ws) return bad(DPIA_ERR_WORKSPACE, "workspace is NULL");
+  if (ws && (reinterpret_cast<uintptr_t>(ws) % kWsAlign))
+    return bad(DPIA_ERR_SHAPE, "workspace must be 256-byte aligned");
+  return DPIA_OK;
+}
+
+}  // namespace
+}  // namespace dpia
+
+using namespace dpia;
+
+extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                                const void* y, void* out, dpia_dtype out_dt, void* ws,
+                                size_t ws_bytes, dpia_stream_t stream) {
+  Plan p;
+  std::string detail;
+  dpia_status st = make_plan(s, DPIA_OP_DOT, dt, 0, n, &p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  if (!out || (n > 0 && (!x || !y))) return bad(DPIA_ERR_NULL, "x, y and out must be non-NULL");
+  if (n > 0 && (!aligned16(x) || !aligned16(y)))
+    return bad(DPIA_ERR_SHAPE, "x and y must be 16-byte aligned");
+  st = check_ws(p, ws, ws_bytes);
+  if (st != DPIA_OK) return st;
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (dt == DPIA_I32) {
+    if (out_dt != DPIA_I32) return bad(DPIA_ERR_DTYPE, "an I32 dot writes an I32 result");
+    e = launch_reduce<DotU32, kFinalPlain>(
+        p, DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)}, out, 0, ws,
+        hs);
+  } else if (p.accum == DPIA_ACCUM_KAHAN) {
+    if (out_dt != DPIA_F32 && !(out_dt == DPIA_F64 && p.final_f64))
+      return bad(DPIA_ERR_DTYPE, "a Kahan dot writes F32, or F64 with final_f64");
+    KahanDotF32 op{static_cast<const float*>(x), static_cast<const float*>(y)};
+    if (p.final_f64)
+      e = launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, out_dt == DPIA_F64, ws, hs);
+    else
+      e = launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, ws, hs);
+  } else {
+    if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
+    e = launch_reduce<DotF32, kFinalPlain>(
+        p, DotF32{static_cast<const float*>(x), static_cast<const float*>(y)}, out, 0, ws, hs);
+  }
+  if (e != hipSuccess) return hip_fail(e, "dpia_dot launch");
+  clear_detail();
+  return DPIA_OK;
+}
+
+extern "C" dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                                 void* out, dpia_dtype out_dt, void* ws, size_t ws_bytes,
+                                 dpia_stream_t stream) {
+  Plan p;
+  std::string detail;
+  dpia_status st = make_plan(s, DPIA_OP_ASUM, dt, 0, n, &p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "asum writes an F32 result");
+  if (!out || (n > 0 && !x)) return bad(DPIA_ERR_NULL, "x and out must be non-NULL");
+  if (n > 0 && !aligned16(x)) return bad(DPIA_ERR_SHAPE, "x must be 16-byte aligned");
+  st = check_ws(p, ws, ws_bytes);
+  if (st != DPIA_OK) return st;
+  hipError_t e = launch_reduce<AsumF32, kFinalPlain>(p, AsumF32{static_cast<const float*>(x)},
+                                                     out, 0, ws,
+                                                     reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "dpia_asum launch");
+  clear_detail();
+  return DPIA_OK;
+}

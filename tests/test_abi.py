@@ -1,0 +1,144 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/dpia.h declares, and validates descriptors and arguments before any
+launch (so these calls never reach HIP)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1710_08332_amd as dp
+from paper_1710_08332_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# fake, 256-byte aligned device addresses: validation must reject the call
+# before anything dereferences them
+P = ctypes.c_void_p(0x7000_0000)
+P2 = ctypes.c_void_p(0x7100_0000)
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dpia.h")).read()
+    # declarations: a return type at the start of a line, then the name
+    return sorted(set(re.findall(r"^(?:const\s+)?\w+\s*\**\s*(dpia_[a-z0-9_]+)\s*\(",
+                                 text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = header_functions()
+    assert set(names) == set(_lib.EXPORTS)
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.dpia_abi_version() == _lib.ABI_VERSION
+
+
+def test_descriptor_layout_matches_header():
+    text = open(os.path.join(ROOT, "include", "dpia.h")).read()
+    body = re.search(r"typedef struct \{(.*?)\} dpia_strategy;", text, re.S).group(1)
+    fields = re.findall(r"uint32_t\s+(\w+);", body)
+    assert fields == [f for f, _ in _lib.CStrategy._fields_]
+    assert ctypes.sizeof(_lib.CStrategy) == 4 * len(fields)
+
+
+def check(s, op, dt, m, n):
+    cs = s.c() if isinstance(s, dp.Strategy) else s
+    ws = ctypes.c_size_t(0)
+    st = _lib.lib().dpia_strategy_check(ctypes.byref(cs), op, dt, m, n, ctypes.byref(ws))
+    return st, ws.value
+
+
+BASE = dp.Strategy(seq_len=256, local_size=16)
+
+
+def test_valid_strategy_reports_workspace():
+    st, ws = check(BASE, dp.OP_DOT, dp.F32, 0, 1 << 20)
+    assert st == _lib.OK
+    # 256 chunk results of 4 bytes, then one 256-byte counter section
+    assert ws == 256 * 4 + 256
+    st, ws = check(BASE.with_(accum=dp.KAHAN), dp.OP_DOT, dp.F32, 0, 1 << 20)
+    assert st == _lib.OK and ws == 2048 + 256
+    st, ws = check(dp.Strategy(seq_len=64, local_size=128, order=dp.STRIDED, rows_per_wg=2),
+                   dp.OP_GEMV, dp.BF16, 8192, 8192)
+    assert st == _lib.OK and ws == 0
+
+
+@pytest.mark.parametrize("s,op,dt,m,n,want", [
+    (BASE, dp.OP_DOT, dp.F32, 0, (1 << 20) + 4096 - 1, _lib.ERR_SHAPE),  # n % W
+    (BASE.with_(local_size=12), dp.OP_DOT, dp.F32, 0, 12 * 256, _lib.ERR_STRATEGY),  # tree, L not 2^k
+    (BASE.with_(seq_len=0), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(passes=3), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(order=2), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(final_f64=1), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),  # needs Kahan
+    (BASE.with_(accum=dp.KAHAN), dp.OP_ASUM, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(accum=dp.KAHAN), dp.OP_DOT, dp.I32, 0, 4096, _lib.ERR_DTYPE),
+    (BASE, dp.OP_DOT, dp.BF16, 0, 4096, _lib.ERR_DTYPE),
+    (BASE, dp.OP_ASUM, dp.I32, 0, 4096, _lib.ERR_DTYPE),
+    (BASE.with_(rows_per_wg=2), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(local_size=2048, seq_len=1, wg_combine=dp.SEQ), dp.OP_DOT, dp.F32, 0, 2048,
+     _lib.ERR_STRATEGY),   # 2048 contiguous lanes > 1024 threads
+    (BASE, dp.OP_GEMV, dp.F32, 10, 4000, _lib.ERR_SHAPE),           # k != L*C
+    (BASE.with_(rows_per_wg=3), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_SHAPE),  # m % R
+    (BASE.with_(rows_per_wg=0), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(row_parts=3), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
+    (BASE, dp.OP_DOT, dp.F32, 0, -4096, _lib.ERR_SHAPE),
+])
+def test_invalid_descriptors_are_rejected(s, op, dt, m, n, want):
+    st, _ = check(s, op, dt, m, n)
+    assert st == want, (st, _lib.last_error_detail())
+    assert _lib.last_error_detail() != ""
+
+
+def test_abi_version_mismatch_and_null_descriptor():
+    cs = BASE.c()
+    cs.abi_version = 99
+    assert check(cs, dp.OP_DOT, dp.F32, 0, 4096)[0] == _lib.ERR_ABI
+    ws = ctypes.c_size_t(0)
+    assert _lib.lib().dpia_strategy_check(None, dp.OP_DOT, dp.F32, 0, 4096,
+                                          ctypes.byref(ws)) == _lib.ERR_NULL
+
+
+def test_status_strings():
+    for st in range(8):
+        assert _lib.status_str(st)
+    assert _lib.status_str(0) == "ok"
+
+
+def _dot(s, n, x=P, y=P, out=P2, out_dt=dp.F32, ws=P2, wsb=1 << 20, dt=dp.F32):
+    cs = s.c()
+    return _lib.lib().dpia_dot(ctypes.byref(cs), dt, n, x, y, out, out_dt, ws, wsb, None)
+
+
+def test_entry_points_validate_before_launching():
+    n = 1 << 20
+    assert _dot(BASE, n + 1) == _lib.ERR_SHAPE
+    assert _dot(BASE, n, out=ctypes.c_void_p(0)) == _lib.ERR_NULL
+    assert _dot(BASE, n, x=ctypes.c_void_p(0)) == _lib.ERR_NULL
+    assert _dot(BASE, n, x=ctypes.c_void_p(0x7000_0004)) == _lib.ERR_SHAPE   # misaligned
+    assert _dot(BASE, n, wsb=100) == _lib.ERR_WORKSPACE
+    assert _dot(BASE, n, ws=ctypes.c_void_p(0)) == _lib.ERR_WORKSPACE
+    assert _dot(BASE, n, ws=ctypes.c_void_p(0x7100_0010)) == _lib.ERR_SHAPE  # ws alignment
+    assert _dot(BASE, n, out_dt=dp.F64) == _lib.ERR_DTYPE
+    assert _dot(BASE, n, dt=dp.I32, out_dt=dp.F32) == _lib.ERR_DTYPE
+    cs = BASE.c()
+    L = _lib.lib()
+    assert L.dpia_asum(ctypes.byref(cs), dp.F32, n, P, P2, dp.F64, P2, 1 << 20, None) == _lib.ERR_DTYPE
+    gs = dp.Strategy(seq_len=64, local_size=64).c()
+    # FP8 without row scales; scales with a non-FP8 matrix; lda < k
+    assert L.dpia_gemv(ctypes.byref(gs), dp.FP8_E4M3, 64, 4096, 4096, P, None, P, P2, None, 0,
+                       None) == _lib.ERR_NULL
+    assert L.dpia_gemv(ctypes.byref(gs), dp.F32, 64, 4096, 4096, P, P, P, P2, None, 0,
+                       None) == _lib.ERR_DTYPE
+    assert L.dpia_gemv(ctypes.byref(gs), dp.F32, 64, 4096, 4095, P, None, P, P2, None, 0,
+                       None) == _lib.ERR_SHAPE
+    # m = 0 is a valid empty problem: nothing is launched
+    assert L.dpia_gemv(ctypes.byref(gs), dp.F32, 0, 4096, 4096, P, None, P, P2, None, 0,
+                       None) == _lib.OK
+
+
+def test_python_strategy_check_raises_with_detail():
+    with pytest.raises(dp.DpiaError) as ei:
+        dp.strategy_check(BASE, dp.OP_DOT, dp.F32, 0, 1000)
+    assert "multiple of the chunk" in str(ei.value)

@@ -1,0 +1,235 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Every comparison is bit for bit: for binary32 and integer strategies the
+strategy fixes every rounding, so the GPU must reproduce the oracle's value
+of the same DPIA expression exactly.  Inputs come from ``synthetic`` (the
+seeded generators both sides share) plus cancelling inputs on which
+different associations give different bits."""
+
+import numpy as np
+import pytest
+
+import paper_1710_08332_amd as dp
+import synthetic
+from oracle import exact, formats
+from oracle import strategies as S
+from tests.gpu_util import (assert_same_bits, discriminating, gpu_asum, gpu_dot, gpu_gemv,
+                            to_plan)
+
+pytestmark = pytest.mark.gpu
+
+C_, T_ = dp.CONTIGUOUS, dp.STRIDED
+TREE, SEQ = dp.TREE, dp.SEQ
+
+# (seq_len C, local_size L, order, combine) spanning: one lane, lanes inside
+# one thread, teams smaller than / equal to / larger than a wavefront,
+# non-power-of-two lanes (sequential combine), C not a multiple of the
+# vector width, and the config-1 strategy (C=256, L=16, contiguous, tree).
+STRATS = [
+    (256, 16, C_, TREE), (256, 16, T_, TREE), (256, 16, C_, SEQ), (256, 16, T_, SEQ),
+    (1, 1, C_, SEQ), (7, 1, C_, TREE), (3, 4, T_, TREE), (5, 2, C_, TREE), (6, 2, T_, SEQ),
+    (4, 64, C_, TREE), (4, 64, T_, TREE), (16, 256, T_, TREE), (16, 256, C_, TREE),
+    (8, 128, C_, SEQ), (8, 512, T_, TREE), (2, 1024, C_, TREE), (2, 4096, T_, TREE),
+    (3, 12, T_, SEQ), (9, 3, C_, SEQ), (64, 1024, T_, SEQ), (33, 32, C_, TREE),
+    (1024, 8, T_, TREE), (8192, 2, C_, TREE), (64, 256, T_, TREE),
+]
+
+
+def _ids(s):
+    C, L, o, c = s
+    return f"C{C}-L{L}-{'str' if o == T_ else 'con'}-{'tree' if c == TREE else 'seq'}"
+
+
+@pytest.mark.parametrize("strat", STRATS, ids=_ids)
+@pytest.mark.parametrize("passes", [1, 2])
+def test_dot_and_asum_bit_exact(strat, passes):
+    C, L, order, comb = strat
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, passes=passes)
+    W = C * L
+    G = max(1, min(37, (1 << 18) // W))         # several tiles and a ragged tail
+    n = W * G
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    plan = to_plan(s)
+    assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, plan), f"dot uniform n={n}")
+    xd, yd = discriminating(7, n)
+    assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, plan), f"dot cancelling n={n}")
+    assert_same_bits(gpu_asum(x, s), S.asum(x, plan), f"asum n={n}")
+
+
+def test_config1_dot_and_asum_at_full_size():
+    # N = 2^20, split 4096 -> mapWorkgroup (split 256 -> mapLocal reduceSeq)
+    # -> tree in local memory -> second-pass reduceSeq
+    n = 1 << 20
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    for passes in (2, 1):
+        s = dp.Strategy(seq_len=256, local_size=16, order=C_, wg_combine=TREE, passes=passes)
+        plan = to_plan(s)
+        assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, plan), "config-1 dot")
+        assert_same_bits(gpu_asum(x, s), S.asum(x, plan), "config-1 asum")
+
+
+@pytest.mark.parametrize("max_grid", [1, 2, 3, 7, 64])
+def test_physical_grid_changes_no_bits(max_grid):
+    n = 1 << 18
+    xd, yd = discriminating(11, n)
+    for passes in (1, 2):
+        base = dp.Strategy(seq_len=64, local_size=64, order=T_, passes=passes)
+        want = S.dot(xd, yd, to_plan(base))
+        assert_same_bits(gpu_dot(xd, yd, base.with_(max_grid=max_grid)), want, f"grid {max_grid}")
+
+
+def test_repeated_calls_are_bit_identical_and_reuse_the_workspace():
+    import torch
+    n = 1 << 20
+    xd, yd = discriminating(12, n)
+    s = dp.Strategy(seq_len=128, local_size=64, order=C_, passes=1)
+    want = S.dot(xd, yd, to_plan(s))
+    xt, yt = torch.from_numpy(xd).cuda(), torch.from_numpy(yd).cuda()
+    ws = dp.workspace(s, dp.OP_DOT, dp.F32, 0, n)
+    outs = [dp.dot(xt, yt, s, ws=ws) for _ in range(20)]
+    torch.cuda.synchronize()
+    for o in outs:
+        assert_same_bits(o.cpu().numpy()[0], want, "repeat")
+
+
+def test_many_chunk_results_fold_across_staging_blocks():
+    # G = 5000 chunk results > one LDS staging block of the final fold
+    s = dp.Strategy(seq_len=4, local_size=4, order=T_, wg_combine=SEQ)
+    n = 16 * 5000
+    xd, yd = discriminating(13, n)
+    for passes in (1, 2):
+        assert_same_bits(gpu_dot(xd, yd, s.with_(passes=passes)),
+                         S.dot(xd, yd, to_plan(s)), f"G=5000 passes={passes}")
+
+
+def test_empty_vector_gives_positive_zero():
+    s = dp.Strategy(seq_len=4, local_size=16)
+    for passes in (1, 2):
+        r = gpu_dot(np.zeros(0, np.float32), np.zeros(0, np.float32), s.with_(passes=passes))
+        assert r.view(np.uint32) == 0
+        assert gpu_asum(np.zeros(0, np.float32), s.with_(passes=passes)).view(np.uint32) == 0
+
+
+@pytest.mark.parametrize("strat", STRATS[:12], ids=_ids)
+def test_integer_dot_is_exact(strat):
+    C, L, order, comb = strat
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb)
+    n = C * L * 11
+    g = np.random.default_rng(5)
+    x = synthetic.integers_u32(g, n)
+    y = synthetic.integers_u32(g, n)
+    want = sum(int(a) * int(b) for a, b in zip(x.tolist(), y.tolist())) % 2 ** 32
+    got = gpu_dot(x, y, s)
+    assert int(got) == want
+    assert int(got) == int(S.dot(x, y, to_plan(s), num="u32"))
+
+
+@pytest.mark.parametrize("strat", [(256, 16, C_, TREE), (64, 256, T_, TREE), (16, 64, C_, SEQ),
+                                   (5, 4, T_, SEQ), (32, 128, T_, TREE)], ids=_ids)
+@pytest.mark.parametrize("final_f64", [0, 1])
+def test_kahan_dot_bit_exact(strat, final_f64):
+    C, L, order, comb = strat
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, accum=dp.KAHAN,
+                    final_f64=final_f64)
+    n = C * L * 19
+    x, y = synthetic.kahan_dot_inputs(n, synthetic.SEEDS["precision"])
+    want = S.dot(x, y, to_plan(s))
+    for passes in (1, 2):
+        got = gpu_dot(x, y, s.with_(passes=passes))
+        assert_same_bits(got, want, "kahan")
+    if final_f64:
+        got32 = gpu_dot(x, y, s, out_dtype=__import__("torch").float32)
+        assert_same_bits(got32, np.float32(want), "kahan f64 rounded to f32")
+    err = abs(float(want) - exact.dot_exact(x, y)) / exact.dot_abs_terms(x, y)
+    assert err < 1e-6
+
+
+GEMV_STRATS = [
+    dict(seq_len=64, local_size=16, order=T_, wg_combine=TREE, rows_per_wg=1),
+    dict(seq_len=8, local_size=128, order=C_, wg_combine=SEQ, rows_per_wg=2),
+    dict(seq_len=16, local_size=64, order=T_, wg_combine=TREE, rows_per_wg=4, row_parts=2),
+    dict(seq_len=3, local_size=5, order=C_, wg_combine=SEQ, rows_per_wg=1),
+    dict(seq_len=32, local_size=256, order=T_, wg_combine=TREE, rows_per_wg=1),
+    dict(seq_len=4, local_size=256, order=C_, wg_combine=TREE, rows_per_wg=1, row_parts=2),
+    dict(seq_len=512, local_size=2, order=T_, wg_combine=TREE, rows_per_wg=8),
+]
+
+
+@pytest.mark.parametrize("kw", GEMV_STRATS, ids=lambda k: "-".join(f"{a[:3]}{b}" for a, b in k.items()))
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8", "i32"])
+def test_gemv_bit_exact(kw, fmt):
+    s = dp.Strategy(**kw)
+    plan = to_plan(s)
+    k = s.seq_len * s.local_size * s.row_parts
+    m = s.rows_per_wg * 13
+    A, x = synthetic.gemv_inputs(m, k, synthetic.SEEDS["scale"])
+    if fmt == "f32":
+        assert_same_bits(gpu_gemv(A, x, s), S.gemv(A, x, plan), "gemv f32")
+    elif fmt == "bf16":
+        codes = synthetic.quantise_bf16(A)
+        assert_same_bits(gpu_gemv(codes, x, s, a_dtype=dp.BF16),
+                         S.gemv(codes, x, plan, a_format="bf16"), "gemv bf16")
+    elif fmt == "fp8":
+        codes, scale = synthetic.quantise_fp8_rows(A)
+        assert_same_bits(gpu_gemv(codes, x, s, a_dtype=dp.FP8_E4M3, scale=scale),
+                         S.gemv(codes, x, plan, a_format="fp8", scale=scale), "gemv fp8")
+    else:
+        g = np.random.default_rng(9)
+        Ai = synthetic.integers_u32(g, (m, k))
+        xi = synthetic.integers_u32(g, k)
+        assert_same_bits(gpu_gemv(Ai, xi, s), S.gemv(Ai, xi, plan, num="u32"), "gemv i32")
+
+
+def test_gemv_leading_dimension_larger_than_k():
+    s = dp.Strategy(seq_len=16, local_size=16, order=T_)
+    m, k, lda = 24, 256, 300
+    A, x = synthetic.gemv_inputs(m, lda, 3)
+    import torch
+    At = torch.from_numpy(A).cuda()[:, :k]
+    y = dp.gemv(At, torch.from_numpy(x[:k].copy()).cuda(), s)
+    torch.cuda.synchronize()
+    assert_same_bits(y.cpu().numpy(), S.gemv(np.ascontiguousarray(A[:, :k]), x[:k], to_plan(s)),
+                     "gemv lda")
+
+
+def test_fp8_decoding_exhaustive_through_gemv():
+    # row r holds code r in column 0 and +0 codes elsewhere, x = 1: every
+    # lane adds exact zeros to code r's value, so y[r] is the decoded value
+    s = dp.Strategy(seq_len=1, local_size=16, order=T_)
+    A = np.zeros((256, 16), np.uint8)
+    A[:, 0] = np.arange(256, dtype=np.uint8)
+    x = np.ones(16, np.float32)
+    scale = np.ones(256, np.float32)
+    y = gpu_gemv(A, x, s, a_dtype=dp.FP8_E4M3, scale=scale)
+    table = formats.FP8_E4M3_TABLE + np.float32(0)      # -0 + 0 = +0
+    nan = np.isnan(table)
+    assert np.array_equal(np.isnan(y), nan)
+    assert_same_bits(y[~nan], table[~nan], "fp8 table")
+    want = S.gemv(A, x, to_plan(s), a_format="fp8", scale=scale)
+    assert np.array_equal(np.isnan(want), nan)
+    assert_same_bits(y[~nan], want[~nan], "fp8 oracle")
+
+
+def test_bf16_decoding_exhaustive_through_gemv():
+    s = dp.Strategy(seq_len=1, local_size=16, order=T_, rows_per_wg=4)
+    A = np.zeros((65536, 16), np.uint16)
+    A[:, 0] = np.arange(65536, dtype=np.uint32).astype(np.uint16)
+    x = np.ones(16, np.float32)
+    y = gpu_gemv(A, x, s, a_dtype=dp.BF16)
+    with np.errstate(invalid="ignore"):
+        table = formats.bf16_decode(A[:, 0]) + np.float32(0)
+    nan = np.isnan(table)
+    assert np.array_equal(np.isnan(y), nan)
+    assert_same_bits(y[~nan], table[~nan], "bf16 table")
+
+
+def test_config2_dot_and_gemv_at_full_size():
+    # dot N = 2^26 and gemv 8192 x 8192, the measured workload's strategies
+    import bench
+    n = 1 << 26
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["scale"])
+    s = bench.DOT_STRATEGY
+    assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, to_plan(s)), "dot 2^26")
+    A, xv = synthetic.gemv_inputs(8192, 8192, synthetic.SEEDS["scale"])
+    g = bench.GEMV_STRATEGY
+    assert_same_bits(gpu_gemv(A, xv, g), S.gemv(A, xv, to_plan(g)), "gemv 8192^2")
