@@ -34,22 +34,25 @@ N_DOT = 1 << 26
 M_GEMV = K_GEMV = 8192
 SEED = 1712
 
-# split 65536 -> mapWorkgroup (strided rows of 256 over 1024 lanes -> mapLocal
-# reduceSeq) -> tree in local memory -> reduceSeq over 1024 chunks, 1 pass
-DOT_STRATEGY = dp.Strategy(seq_len=64, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
-                           passes=1)
+# split 262144 -> mapWorkgroup (1024 lanes, each folding a strided row of 256
+# -> mapLocal reduceSeq) -> tree in local memory; then reduceSeq over the 256
+# chunk values in a second pass
+DOT_STRATEGY = dp.Strategy(seq_len=256, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
+                           passes=2)
 # rows of 8192 = 256 lanes x 32 strided elements, tree, 4 rows per work-group
 GEMV_STRATEGY = dp.Strategy(seq_len=32, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE,
                             rows_per_wg=4)
 
 DOT_BYTES = 2 * 4 * N_DOT + 4                    # x, y read; one result written
+G_DOT = N_DOT // (DOT_STRATEGY.seq_len * DOT_STRATEGY.local_size)
+CHUNK_KERNEL_BYTES = 2 * 4 * N_DOT + 4 * G_DOT   # first pass: x, y read; G values written
 GEMV_BYTES = 4 * M_GEMV * K_GEMV + 4 * K_GEMV + 4 * M_GEMV
 
 
-def strategy_text(s: dp.Strategy) -> str:
+def strategy_text(s: dp.Strategy, gemv: bool = False) -> str:
     return (f"C={s.seq_len} L={s.local_size} {'strided' if s.order == dp.STRIDED else 'contiguous'}"
-            f" {'tree' if s.wg_combine == dp.TREE else 'seq'} passes={s.passes}"
-            + (f" R={s.rows_per_wg}" if s.rows_per_wg > 1 else ""))
+            f" {'tree' if s.wg_combine == dp.TREE else 'seq'}"
+            + (f" R={s.rows_per_wg}" if gemv else f" passes={s.passes}"))
 
 
 def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
@@ -83,6 +86,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="also launch one plain 256 MiB device-to-device copy (a kernel of "
+                         "known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -102,15 +108,26 @@ def main():
     At, xvt = torch.from_numpy(A).to(dev), torch.from_numpy(xv).to(dev)
     out = torch.empty(1, dtype=torch.float32, device=dev)
     yg = torch.empty(M_GEMV, dtype=torch.float32, device=dev)
-    ws = dp.workspace(DOT_STRATEGY, dp.OP_DOT, dp.F32, 0, N_DOT, dev)
+    chunk_vals = torch.empty(G_DOT * 4, dtype=torch.uint8, device=dev)
 
+    # one step: the dot's two passes (chunk values, then their ordered fold)
+    # and the gemv, all on torch's current stream
     def step(ev=None):
         if ev is not None:
             ev[0].record()
-        dp.dot(xt, yt, DOT_STRATEGY, out=out, ws=ws)
+        dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals)
         if ev is not None:
             ev[1].record()
+        dp.fold(dp.OP_DOT, DOT_STRATEGY, chunk_vals, N_DOT, dp.F32, out=out)
         dp.gemv(At, xvt, GEMV_STRATEGY, y=yg)
+
+    if args.profile_copy:
+        src = torch.empty(1 << 26, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)            # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -128,7 +145,7 @@ def main():
 
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
-    achieved = DOT_BYTES / dot_avg_s / 1e9
+    achieved = CHUNK_KERNEL_BYTES / dot_avg_s / 1e9
     rec = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -145,13 +162,14 @@ def main():
         "config": {
             "workload": "FP32 dot N=2^26 + FP32 gemv 8192x8192 (one step = one of each)",
             "dot_strategy": strategy_text(DOT_STRATEGY),
-            "gemv_strategy": strategy_text(GEMV_STRATEGY),
+            "gemv_strategy": strategy_text(GEMV_STRATEGY, gemv=True),
             "percent_of_hbm_peak": round(100 * value / PEAK_GBPS, 2),
             "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "reduce_kernel (dot, 1 pass)",
+            "kernel": "reduce_kernel<DotF32, strided, 4, tree> (dot first pass)",
+            "bytes_per_launch": CHUNK_KERNEL_BYTES,
             "achieved": round(achieved, 3),
             "peak": PEAK_GBPS,
             "unit": "GB/s",

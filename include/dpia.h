@@ -183,6 +183,30 @@ dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_
                       int64_t lda, const void* A, const float* row_scale, const void* x,
                       void* y, void* ws, size_t ws_bytes, dpia_stream_t stream);
 
+/*
+ * The two stages of a dot or asum strategy as separate calls.  dpia_chunks
+ * evaluates the mapWorkgroup level only: chunks[g] = value of chunk g, i.e.
+ * the work-group combine of its L lane folds (the OpenCL dot kernel of
+ * Sec. 6.2 likewise writes its per-work-group results and leaves the last
+ * reduction to a later step).  dpia_fold then computes the outer
+ * reduceSeq (+) 0 over those G = n / W values in chunk order.  Together they
+ * give the same bits as dpia_dot / dpia_asum with the same strategy, whatever
+ * its `passes`; a caller that gathers chunk values from several devices in
+ * device order can fold them the same way.
+ *   op       DPIA_OP_DOT (x and y) or DPIA_OP_ASUM (x; y ignored)
+ *   dt, n    as for dpia_dot / dpia_asum
+ *   chunks   device buffer of chunks_bytes >= G * value size, where a chunk
+ *            value is the accumulator: 4 bytes (binary32 or I32), or a pair
+ *            of binary32 (s, c), 8 bytes, for Kahan
+ *   out, out_dt  as for dpia_dot / dpia_asum
+ */
+dpia_status dpia_chunks(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t n,
+                        const void* x, const void* y, void* chunks, size_t chunks_bytes,
+                        dpia_stream_t stream);
+
+dpia_status dpia_fold(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t n,
+                      const void* chunks, void* out, dpia_dtype out_dt, dpia_stream_t stream);
+
 /* Static text for a status code. */
 const char* dpia_status_str(dpia_status st);
 

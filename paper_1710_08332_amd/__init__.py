@@ -147,3 +147,38 @@ def gemv(A, x, s: Strategy, y=None, row_scale=None, a_dtype=None, stream=None):
                                     ctypes.c_void_p(A.data_ptr()), sc, _dev(x), _dev(y),
                                     ctypes.c_void_p(0), 0, _stream(stream)), "dpia_gemv")
     return y
+
+
+def num_chunks(s: Strategy, n: int) -> int:
+    return n // (s.seq_len * s.local_size)
+
+
+def chunks(op: int, s: Strategy, x, y=None, out=None, stream=None):
+    """The mapWorkgroup level of a dot (op=OP_DOT) or asum (OP_ASUM): one
+    accumulator value per chunk (4 bytes, or 8 for a Kahan pair)."""
+    torch = _torch()
+    n = x.numel()
+    dt = _dtype_code(x)
+    vb = 8 if s.accum == KAHAN else 4
+    if out is None:
+        out = torch.empty(max(1, num_chunks(s, n)) * vb, dtype=torch.uint8, device=x.device)
+    cs = s.c()
+    yp = _dev(y) if y is not None else ctypes.c_void_p(0)
+    _lib.check(_lib.lib().dpia_chunks(ctypes.byref(cs), op, dt, n, _dev(x), yp, _dev(out),
+                                      out.numel() * out.element_size(), _stream(stream)),
+               "dpia_chunks")
+    return out
+
+
+def fold(op: int, s: Strategy, chunk_values, n: int, dtype: int, out=None, out_dtype=None,
+         stream=None):
+    """The outer reduceSeq of the strategy over chunk values from ``chunks``."""
+    torch = _torch()
+    if out is None:
+        od = out_dtype or (torch.float64 if (s.accum == KAHAN and s.final_f64) else
+                           (torch.int32 if dtype == I32 else torch.float32))
+        out = torch.empty(1, dtype=od, device=chunk_values.device)
+    cs = s.c()
+    _lib.check(_lib.lib().dpia_fold(ctypes.byref(cs), op, dtype, n, _dev(chunk_values),
+                                    _dev(out), _dtype_code(out), _stream(stream)), "dpia_fold")
+    return out

@@ -23,8 +23,8 @@ CONTIGUOUS, STRIDED = 0, 1
 TREE, SEQ = 0, 1
 PLAIN, KAHAN = 0, 1
 
-EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_status_str",
-           "dpia_last_error_detail", "dpia_abi_version")
+EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
+           "dpia_fold", "dpia_status_str", "dpia_last_error_detail", "dpia_abi_version")
 
 
 class CStrategy(ctypes.Structure):
@@ -56,7 +56,10 @@ def lib() -> ctypes.CDLL:
         L.dpia_dot.argtypes = [sp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int, vp, u64, vp]
         L.dpia_asum.argtypes = [sp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp, u64, vp]
         L.dpia_gemv.argtypes = [sp, ctypes.c_int, i64, i64, i64, vp, vp, vp, vp, vp, u64, vp]
-        for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv"):
+        L.dpia_chunks.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, u64, vp]
+        L.dpia_fold.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp]
+        for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
+                  "dpia_fold"):
             getattr(L, f).restype = ctypes.c_int
         L.dpia_status_str.argtypes = [ctypes.c_int]
         L.dpia_status_str.restype = ctypes.c_char_p

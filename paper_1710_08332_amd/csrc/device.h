@@ -27,31 +27,51 @@ enum : int { kTree = 0, kSeq = 1 };
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+#ifndef DPIA_NT_LOADS
+#define DPIA_NT_LOADS 1
+#endif
+#ifndef DPIA_DOUBLE_BUFFER
+#define DPIA_DOUBLE_BUFFER 0
+#endif
+#ifndef DPIA_BATCH_ELEMS
+#define DPIA_BATCH_ELEMS 16
+#endif
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 // Load NV consecutive elements of type E from an address aligned to
-// min(16, NV * sizeof(E)) bytes, with the widest loads that fit.
-template <typename E, int NV>
+// min(16, NV * sizeof(E)) bytes, with the widest loads that fit.  STREAM
+// marks data read once (non-temporal loads: streamed past the caches).
+template <typename E, int NV, bool STREAM = true>
 __device__ __forceinline__ void vload(const E* __restrict__ p, E (&out)[NV]) {
+  constexpr bool NT = STREAM && DPIA_NT_LOADS;
   constexpr int B = static_cast<int>(sizeof(E)) * NV;
   const char* src = reinterpret_cast<const char*>(p);
   char* dst = reinterpret_cast<char*>(out);
   if constexpr (B >= 16) {
 #pragma unroll
     for (int i = 0; i < B / 16; ++i) {
-      u32x4 r = *reinterpret_cast<const u32x4*>(src + 16 * i);
+      u32x4 r = ld<NT>(reinterpret_cast<const u32x4*>(src + 16 * i));
       __builtin_memcpy(dst + 16 * i, &r, 16);
     }
   } else if constexpr (B == 8) {
-    u32x2 r = *reinterpret_cast<const u32x2*>(src);
+    u32x2 r = ld<NT>(reinterpret_cast<const u32x2*>(src));
     __builtin_memcpy(dst, &r, 8);
   } else if constexpr (B == 4) {
-    unsigned int r = *reinterpret_cast<const unsigned int*>(src);
+    unsigned int r = ld<NT>(reinterpret_cast<const unsigned int*>(src));
     __builtin_memcpy(dst, &r, 4);
   } else if constexpr (B == 2) {
-    unsigned short r = *reinterpret_cast<const unsigned short*>(src);
+    unsigned short r = ld<NT>(reinterpret_cast<const unsigned short*>(src));
     __builtin_memcpy(dst, &r, 2);
   } else {
     static_assert(B == 1, "unsupported vector width");
-    out[0] = p[0];
+    out[0] = ld<NT>(p);
   }
 }
 
@@ -162,35 +182,85 @@ __device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL],
 // Fold the lanes of one chunk.  `view` gives element access relative to the
 // chunk start: view.template load<NV>(off, terms) loads elements off ..
 // off+NV-1 and Op::step(term, acc) is the lane operator.
+//
+// Loads are issued in batches of U steps before any of them is folded, so
+// every wavefront keeps U vector loads per operand in flight; the folds then
+// consume the batch in increasing index order.  Two batches alternate, so
+// the next one is in flight while the current one is folded.  U * NV is
+// kept near 16 elements per batch to bound register use.
+template <int NV>
+struct Batch {
+  static constexpr int E = DPIA_BATCH_ELEMS;
+  static constexpr int U = (E / NV) < 1 ? 1 : ((E / NV) > 16 ? 16 : (E / NV));
+};
+
 template <class Op, int ORDER, int NV, class View>
 __device__ __forceinline__ void lane_folds(const View& view, bool active, int t, int L, int C,
                                            typename Op::T (&acc)[ORDER == kStrided ? NV : 1]) {
   using Term = typename Op::Term;
-  if constexpr (ORDER == kStrided) {
-    // lane l = t*NV + v folds elements l, l + L, l + 2L, ...
+  constexpr int U = Batch<NV>::U;
+  constexpr int NL = (ORDER == kStrided) ? NV : 1;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = Op::Arith::zero();
-    if (!active) return;
-    int off = t * NV;
-#pragma unroll 8
-    for (int k = 0; k < C; ++k) {
-      Term z[NV];
-      view.template load<NV>(off, z);
+  for (int v = 0; v < NL; ++v) acc[v] = Op::Arith::zero();
+  if (!active) return;
+  // element offsets: strided lane l = t*NV + v takes l + k*L (one vector
+  // load covers NV lanes at the same k); contiguous lane l = t takes
+  // l*C + k (one vector load covers NV consecutive k)
+  const int start = (ORDER == kStrided) ? t * NV : t * C;
+  const int step = (ORDER == kStrided) ? L : NV;        // offset advance per load
+  const int nloads = (ORDER == kStrided) ? C : C / NV;   // loads per lane group
+  auto load_batch = [&](Term (&z)[U][NV], int j) {
+    const int o = start + j * U * step;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = Op::step(z[v], acc[v]);
-      off += L;
+    for (int u = 0; u < U; ++u) view.template load<NV>(o + u * step, z[u]);
+  };
+  auto fold_batch = [&](Term (&z)[U][NV]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if constexpr (ORDER == kStrided)
+          acc[v] = Op::step(z[u][v], acc[v]);
+        else
+          acc[0] = Op::step(z[u][v], acc[0]);
+      }
     }
-  } else {
-    // lane l = t folds elements l*C, l*C + 1, ..., NV of them per load
-    acc[0] = Op::Arith::zero();
-    if (!active) return;
-    const int base = t * C;
-#pragma unroll 4
-    for (int k = 0; k < C; k += NV) {
-      Term z[NV];
-      view.template load<NV>(base + k, z);
+  };
+  // two register batches: while one is folded the next one is in flight
+  const int nb = nloads / U;
+  if constexpr (!DPIA_DOUBLE_BUFFER) {
+    for (int j = 0; j < nb; ++j) {
+      Term za[U][NV];
+      load_batch(za, j);
+      __builtin_amdgcn_sched_barrier(0);
+      fold_batch(za);
+    }
+  } else if (nb > 0) {
+    Term za[U][NV], zb[U][NV];
+    load_batch(za, 0);
+    int j = 0;
+    for (; j + 1 < nb; j += 2) {
+      load_batch(zb, j + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      fold_batch(za);
+      if (j + 2 < nb) load_batch(za, j + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      fold_batch(zb);
+    }
+    if (j < nb) {
+      __builtin_amdgcn_sched_barrier(0);
+      fold_batch(za);
+    }
+  }
+  for (int i = nb * U; i < nloads; ++i) {
+    Term z[NV];
+    view.template load<NV>(start + i * step, z);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[0] = Op::step(z[v], acc[0]);
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (ORDER == kStrided)
+        acc[v] = Op::step(z[v], acc[v]);
+      else
+        acc[0] = Op::step(z[v], acc[0]);
     }
   }
 }

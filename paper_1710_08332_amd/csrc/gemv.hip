@@ -56,7 +56,7 @@ struct GemvF32Acc {
       E ca[NV];
       float fa[NV], b[NV];
       vload<E, NV>(a + off, ca);
-      vload<float, NV>(x + off, b);
+      vload<float, NV, false>(x + off, b);   // x is reused by every row: cached
       Decode::template run<NV>(ca, fa);
 #pragma unroll
       for (int i = 0; i < NV; ++i) z[i] = Term{fa[i], b[i]};
@@ -109,7 +109,7 @@ struct GemvU32 {
     __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
       uint32_t ca[NV], b[NV];
       vload<uint32_t, NV>(a + off, ca);
-      vload<uint32_t, NV>(x + off, b);
+      vload<uint32_t, NV, false>(x + off, b);
 #pragma unroll
       for (int i = 0; i < NV; ++i) z[i] = Term{ca[i], b[i]};
     }

@@ -117,26 +117,36 @@ struct ReduceArgs {
 };
 
 // The outer reduceSeq over the G chunk values, from the literal 0, in chunk
-// order, by one thread; values are staged through LDS in blocks.
+// order, by one thread.  The work-group stages blocks of chunk values in LDS
+// (coalesced), then thread 0 reads them back 32 at a time into registers
+// and folds them in order.
 template <class A, int FINAL>
 __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
                            typename A::T* buf) {
   using T = typename A::T;
+  constexpr int R = 32;
   T acc = A::zero();
   double acc64 = 0.0;
+  auto fold1 = [&](const T& e) {
+    if constexpr (FINAL == kFinalKahan64)
+      acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
+    else
+      acc = A::add(e, acc);
+  };
   for (int64_t b = 0; b < G; b += kFoldBlock) {
     const int cnt = static_cast<int>(G - b < kFoldBlock ? G - b : kFoldBlock);
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[i] = partials[b + i];
     __syncthreads();
     if (threadIdx.x == 0) {
-      if constexpr (FINAL == kFinalKahan64) {
-        for (int i = 0; i < cnt; ++i) {
-          const T e = buf[i];
-          acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
-        }
-      } else {
-        for (int i = 0; i < cnt; ++i) acc = A::add(buf[i], acc);
+      int i = 0;
+      for (; i + R <= cnt; i += R) {
+        T r[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) r[j] = buf[i + j];
+#pragma unroll
+        for (int j = 0; j < R; ++j) fold1(r[j]);
       }
+      for (; i < cnt; ++i) fold1(buf[i]);
     }
     __syncthreads();
   }
@@ -176,17 +186,23 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
     if (active && t == 0) partials[g] = v;
   }
   if (a.one_pass) {
-    __threadfence();            // release this work-group's partials
+    // The barrier makes this work-group's partial stores happen before
+    // thread 0's agent-scope release; the arrival counter then orders them
+    // before the last work-group's acquire, which the barrier hands on to
+    // every thread of that work-group.  One fence per work-group.
     __syncthreads();
     if (threadIdx.x == 0) {
-      const unsigned prev = atomicAdd(a.counter, 1u);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned prev =
+          __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       is_last = (prev == gridDim.x - 1);
+      if (is_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (is_last) {
-      __threadfence();          // acquire every work-group's partials
       final_fold<typename Op::Arith, FINAL>(partials, a.items, a.out, a.out_f64, lds);
-      if (threadIdx.x == 0) atomicExch(a.counter, 0u);   // ready for the next call
+      if (threadIdx.x == 0)   // leave the counter at zero for the next call
+        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -198,10 +214,9 @@ __global__ void __launch_bounds__(256) final_kernel(const typename A::T* partial
   final_fold<A, FINAL>(partials, G, out, out_f64, reinterpret_cast<typename A::T*>(lds_raw));
 }
 
-template <class Op, int FINAL>
-hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* ws,
-                         hipStream_t stream) {
-  using T = typename Op::T;
+template <class Op>
+ReduceArgs reduce_args(const Plan& p, void* partials, void* counter, void* out, int out_f64,
+                       bool one_pass) {
   ReduceArgs a{};
   a.items = p.items;
   a.W = p.W;
@@ -212,38 +227,73 @@ hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, vo
   a.team_lds_elems = (p.combine == DPIA_COMBINE_SEQ) ? static_cast<int>(p.L)
                                                      : (p.team > 64 ? p.team / 64 : 1);
   a.out_f64 = out_f64;
-  a.partials = ws;
-  a.counter = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + p.partial_bytes);
+  a.partials = partials;
+  a.counter = static_cast<unsigned int*>(counter);
   a.out = out;
-  const bool two_pass = p.passes == 2 || p.items == 0;
-  a.one_pass = two_pass ? 0 : 1;
+  a.one_pass = one_pass ? 1 : 0;
+  return a;
+}
 
-  if (p.items > 0) {
-    const int64_t grid = grid_size(p);
-    hipError_t e = with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
-      constexpr int ORDER = decltype(ord)::value;
-      constexpr int COMBINE = decltype(comb)::value;
-      constexpr int MAXNV = kVecBytes / static_cast<int>(sizeof(float));
-      return with_nv<MAXNV>(p.nv, [&](auto nvc) {
-        constexpr int NV = decltype(nvc)::value;
-        auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL>;
-        Op op_copy = op;
-        void* args[] = {&op_copy, &a};
-        return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
-                               dim3(p.wg_threads), args, p.lds_bytes, stream);
-      });
+// The mapWorkgroup level: chunk values into `partials`; with one_pass the
+// last work-group also folds them into `out`.
+template <class Op, int FINAL>
+hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
+  if (p.items == 0) return hipSuccess;
+  const int64_t grid = grid_size(p);
+  return with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
+    constexpr int ORDER = decltype(ord)::value;
+    constexpr int COMBINE = decltype(comb)::value;
+    constexpr int MAXNV = kVecBytes / static_cast<int>(sizeof(float));
+    return with_nv<MAXNV>(p.nv, [&](auto nvc) {
+      constexpr int NV = decltype(nvc)::value;
+      auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL>;
+      Op op_copy = op;
+      ReduceArgs a_copy = a;
+      void* args[] = {&op_copy, &a_copy};
+      return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                             dim3(p.wg_threads), args, p.lds_bytes, stream);
     });
-    if (e != hipSuccess) return e;
+  });
+}
+
+// The outer reduceSeq over G chunk values, as a kernel of its own.
+template <class Op, int FINAL>
+hipError_t launch_fold(int64_t G, const void* partials, void* out, int out_f64,
+                       hipStream_t stream) {
+  using T = typename Op::T;
+  const T* pp = static_cast<const T*>(partials);
+  void* args[] = {&pp, &G, &out, &out_f64};
+  auto kern = final_kernel<typename Op::Arith, FINAL>;
+  return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(1), dim3(256), args,
+                         kFoldBlock * sizeof(T), stream);
+}
+
+template <class Op, int FINAL>
+hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* ws,
+                         hipStream_t stream) {
+  const bool two_pass = p.passes == 2 || p.items == 0;
+  ReduceArgs a = reduce_args<Op>(p, ws, static_cast<char*>(ws) + p.partial_bytes, out, out_f64,
+                                 !two_pass);
+  hipError_t e = launch_chunks<Op, FINAL>(p, op, a, stream);
+  if (e != hipSuccess || !two_pass) return e;
+  return launch_fold<Op, FINAL>(p.items, ws, out, out_f64, stream);
+}
+
+// Calls f(op, final-kind constant) for the operation and accumulation of a plan.
+template <class F>
+hipError_t with_reduction(const Plan& p, const void* x, const void* y, F&& f) {
+  if (p.op == DPIA_OP_ASUM)
+    return f(AsumF32{static_cast<const float*>(x)}, ic<kFinalPlain>{});
+  if (p.dt == DPIA_I32)
+    return f(DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)},
+             ic<kFinalPlain>{});
+  if (p.accum == DPIA_ACCUM_KAHAN) {
+    KahanDotF32 op{static_cast<const float*>(x), static_cast<const float*>(y)};
+    if (p.final_f64) return f(op, ic<kFinalKahan64>{});
+    return f(op, ic<kFinalKahan32>{});
   }
-  if (two_pass) {
-    const T* partials = static_cast<const T*>(ws);
-    int64_t G = p.items;
-    void* args[] = {&partials, &G, &out, &out_f64};
-    auto kern = final_kernel<typename Op::Arith, FINAL>;
-    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(1), dim3(256), args,
-                           kFoldBlock * sizeof(T), stream);
-  }
-  return hipSuccess;
+  return f(DotF32{static_cast<const float*>(x), static_cast<const float*>(y)},
+           ic<kFinalPlain>{});
 }
 
 namespace {
@@ -318,6 +368,61 @@ extern "C" dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t 
                                                      out, 0, ws,
                                                      reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "dpia_asum launch");
+  clear_detail();
+  return DPIA_OK;
+}
+
+// The two stages of a 2-pass strategy as separate calls (see dpia.h).
+extern "C" dpia_status dpia_chunks(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t n,
+                                   const void* x, const void* y, void* chunks,
+                                   size_t chunks_bytes, dpia_stream_t stream) {
+  if (op != DPIA_OP_DOT && op != DPIA_OP_ASUM)
+    return bad(DPIA_ERR_STRATEGY, "dpia_chunks takes DPIA_OP_DOT or DPIA_OP_ASUM");
+  Plan p;
+  std::string detail;
+  dpia_status st = make_plan(s, op, dt, 0, n, &p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  const bool dot = op == DPIA_OP_DOT;
+  if (n > 0 && (!x || (dot && !y))) return bad(DPIA_ERR_NULL, "input vectors must be non-NULL");
+  if (n > 0 && (!aligned16(x) || (dot && !aligned16(y))))
+    return bad(DPIA_ERR_SHAPE, "input vectors must be 16-byte aligned");
+  const size_t need = static_cast<size_t>(p.items) * p.acc_bytes;
+  if (p.items > 0 && !chunks) return bad(DPIA_ERR_NULL, "chunks must be non-NULL");
+  if (chunks_bytes < need)
+    return bad(DPIA_ERR_WORKSPACE, "chunks holds " + std::to_string(chunks_bytes) +
+                                       " bytes, the strategy writes " + std::to_string(need));
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = with_reduction(p, x, y, [&](auto op_v, auto fin) {
+    using Op = decltype(op_v);
+    constexpr int FINAL = decltype(fin)::value;
+    ReduceArgs a = reduce_args<Op>(p, chunks, nullptr, nullptr, 0, false);
+    return launch_chunks<Op, FINAL>(p, op_v, a, hs);
+  });
+  if (e != hipSuccess) return hip_fail(e, "dpia_chunks launch");
+  clear_detail();
+  return DPIA_OK;
+}
+
+extern "C" dpia_status dpia_fold(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t n,
+                                 const void* chunks, void* out, dpia_dtype out_dt,
+                                 dpia_stream_t stream) {
+  if (op != DPIA_OP_DOT && op != DPIA_OP_ASUM)
+    return bad(DPIA_ERR_STRATEGY, "dpia_fold takes DPIA_OP_DOT or DPIA_OP_ASUM");
+  Plan p;
+  std::string detail;
+  dpia_status st = make_plan(s, op, dt, 0, n, &p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  if (!out || (p.items > 0 && !chunks)) return bad(DPIA_ERR_NULL, "chunks and out must be non-NULL");
+  const dpia_dtype want = (dt == DPIA_I32) ? DPIA_I32 : DPIA_F32;
+  if (!(out_dt == want || (out_dt == DPIA_F64 && p.final_f64)))
+    return bad(DPIA_ERR_DTYPE, "output type does not match the strategy");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = with_reduction(p, nullptr, nullptr, [&](auto op_v, auto fin) {
+    using Op = decltype(op_v);
+    constexpr int FINAL = decltype(fin)::value;
+    return launch_fold<Op, FINAL>(p.items, chunks, out, out_dt == DPIA_F64, hs);
+  });
+  if (e != hipSuccess) return hip_fail(e, "dpia_fold launch");
   clear_detail();
   return DPIA_OK;
 }

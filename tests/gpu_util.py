@@ -77,5 +77,6 @@ def discriminating(seed, n):
     g = np.random.default_rng(seed)
     v = (np.where(g.random(n // 2) < 0.5, -1, 1) * 2.0 ** g.uniform(-20, 20, n // 2)).astype(np.float32)
     w = 2 * g.random(n // 2, dtype=np.float32) - 1
+    pad = [np.zeros(n % 2, np.float32)]       # odd n: one zero product
     perm = g.permutation(n)
-    return np.concatenate([v, v])[perm], np.concatenate([w, -w])[perm]
+    return (np.concatenate([v, v] + pad)[perm], np.concatenate([w, -w] + pad)[perm])

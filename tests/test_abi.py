@@ -142,3 +142,18 @@ def test_python_strategy_check_raises_with_detail():
     with pytest.raises(dp.DpiaError) as ei:
         dp.strategy_check(BASE, dp.OP_DOT, dp.F32, 0, 1000)
     assert "multiple of the chunk" in str(ei.value)
+
+
+def test_stage_entry_points_validate_before_launching():
+    L = _lib.lib()
+    cs = BASE.c()
+    n = 1 << 20                      # G = 256 chunk values of 4 bytes
+    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, P, P2, 1023, None) == _lib.ERR_WORKSPACE
+    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, None, P2, 1024, None) == _lib.ERR_NULL
+    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_GEMV, dp.F32, n, P, P, P2, 1024, None) == _lib.ERR_STRATEGY
+    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n + 16, P, P, P2, 1 << 20, None) == _lib.ERR_SHAPE
+    ks = BASE.with_(accum=dp.KAHAN).c()
+    assert L.dpia_chunks(ctypes.byref(ks), dp.OP_DOT, dp.F32, n, P, P, P2, 2047, None) == _lib.ERR_WORKSPACE
+    assert L.dpia_fold(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, P2, dp.F64, None) == _lib.ERR_DTYPE
+    assert L.dpia_fold(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, None, P2, dp.F32, None) == _lib.ERR_NULL
+    assert L.dpia_fold(ctypes.byref(cs), dp.OP_ASUM, dp.I32, n, P, P2, dp.I32, None) == _lib.ERR_DTYPE

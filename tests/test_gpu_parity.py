@@ -233,3 +233,27 @@ def test_config2_dot_and_gemv_at_full_size():
     A, xv = synthetic.gemv_inputs(8192, 8192, synthetic.SEEDS["scale"])
     g = bench.GEMV_STRATEGY
     assert_same_bits(gpu_gemv(A, xv, g), S.gemv(A, xv, to_plan(g)), "gemv 8192^2")
+
+
+@pytest.mark.parametrize("kw", [dict(seq_len=256, local_size=1024, order=T_),
+                                dict(seq_len=64, local_size=16, order=C_, wg_combine=SEQ),
+                                dict(seq_len=32, local_size=128, order=T_, accum=dp.KAHAN),
+                                dict(seq_len=32, local_size=128, order=C_, accum=dp.KAHAN,
+                                     final_f64=1)], ids=str)
+def test_chunks_then_fold_equals_one_call(kw):
+    import torch
+    s = dp.Strategy(**kw)
+    n = s.seq_len * s.local_size * 23
+    x, y = discriminating(17, n)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    c = dp.chunks(dp.OP_DOT, s, xt, yt)
+    r = dp.fold(dp.OP_DOT, s, c, n, dp.F32)
+    torch.cuda.synchronize()
+    want = S.dot(x, y, to_plan(s))
+    assert_same_bits(r.cpu().numpy()[0], want, "chunks+fold")
+    assert_same_bits(gpu_dot(x, y, s), want, "dot")
+    if s.accum == dp.PLAIN:
+        ca = dp.chunks(dp.OP_ASUM, s, xt)
+        ra = dp.fold(dp.OP_ASUM, s, ca, n, dp.F32)
+        torch.cuda.synchronize()
+        assert_same_bits(ra.cpu().numpy()[0], S.asum(x, to_plan(s)), "asum chunks+fold")
