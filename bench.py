@@ -13,6 +13,18 @@ Prints one JSON line.  Besides the whole-job figure it reports the dominant
 kernel (the dot) against the HBM roofline, timed with HIP events on the
 stream the kernels run on, and the CPU oracle timed on this host's cores on
 the same workload (bounded to a few repetitions).
+
+Other workloads (one JSON line per measured item, not the headline):
+    --workload small      dot and asum N = 2^20 under split 4096 / 256 / tree /
+                          2 passes (cache-resident: time and parity only)
+    --workload sweep      dot N = 2^26 and gemv 16384^2 over the 24-strategy
+                          sweep each, with the autotuner's pick
+    --workload precision  gemv 16384^2 with bf16 and fp8-e4m3 (row-scaled) A,
+                          and the compensated dot at N = 2^28, with their
+                          error against the exact (binary64-correctly-rounded)
+                          value
+Oracle work (parity, exact references) runs only in the CPU-baseline leg,
+which --no-cpu-baseline skips.
 """
 
 from __future__ import annotations
@@ -49,6 +61,29 @@ CHUNK_KERNEL_BYTES = 2 * 4 * N_DOT + 4 * G_DOT   # first pass: x, y read; G valu
 GEMV_BYTES = 4 * M_GEMV * K_GEMV + 4 * K_GEMV + 4 * M_GEMV
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "dot_f32_2p26_and_gemv_f32_8192_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dot's first pass from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed since
+    the counters were taken (their hash no longer matches)."""
+    import hashlib
+    try:
+        kv = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
+                  if ": " in line and not line.startswith(("|", "-", "#", " ")))
+        h = hashlib.sha256()
+        root = os.path.dirname(os.path.abspath(__file__))
+        for f in kv["sources"].split():
+            h.update(open(os.path.join(root, f), "rb").read())
+        if h.hexdigest() != kv["source_sha256"].strip():
+            return None
+        return int(kv["dot_first_pass_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def strategy_text(s: dp.Strategy, gemv: bool = False) -> str:
     return (f"C={s.seq_len} L={s.local_size} {'strided' if s.order == dp.STRIDED else 'contiguous'}"
             f" {'tree' if s.wg_combine == dp.TREE else 'seq'}"
@@ -80,12 +115,179 @@ def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
                       f"repetitions, {el:.1f} s, numpy single thread"}, parity
 
 
+def _line(**kw):
+    print(json.dumps(kw), flush=True)
+
+
+def _gbs(nbytes, us):
+    return round(nbytes / us / 1e3, 1)
+
+
+def workload_small(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import time_us
+    n = 1 << 20
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    s = dp.Strategy(seq_len=256, local_size=16, order=dp.CONTIGUOUS, wg_combine=dp.TREE, passes=2)
+    ws = dp.workspace(s, dp.OP_DOT, dp.F32, 0, n)
+    out = torch.empty(1, device="cuda")
+    res = {}
+    for name, fn, nbytes in (("dot", lambda: dp.dot(xt, yt, s, out=out, ws=ws), 8 * n + 4),
+                             ("asum", lambda: dp.asum(xt, s, out=out, ws=ws), 4 * n + 4)):
+        med, p10, p90 = time_us(fn, reps=100)
+        fn()
+        torch.cuda.synchronize()
+        res[name] = out.cpu().numpy()[0]
+        _line(workload="small", op=name, n=n, strategy=strategy_text(s), us=round(med, 2),
+              p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
+              note="cache-resident (2^20 elements fit in L2/MALL): no HBM claim")
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        t0 = time.perf_counter()
+        d = S.dot(x, y, to_plan(s))
+        a = S.asum(x, to_plan(s))
+        el = time.perf_counter() - t0
+        _line(workload="small", cpu_baseline={"kind": "oracle", "cores": 1, "seconds": round(el, 3)},
+              parity={"dot_bit_exact": bool(np.float32(d).view(np.uint32) == np.float32(res["dot"]).view(np.uint32)),
+                      "asum_bit_exact": bool(np.float32(a).view(np.uint32) == np.float32(res["asum"]).view(np.uint32))})
+
+
+def workload_sweep(args):
+    import dataclasses
+    import torch
+    import synthetic
+    from paper_1710_08332_amd import autotune as T
+    seed = synthetic.SEEDS["sweep"]
+    n = 1 << 26
+    x, y = synthetic.dot_inputs(n, seed)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    best, table = T.tune_dot(xt, yt, reps=args.steps)
+    outs = {}
+    for row in table:
+        st = dp.Strategy(**row["strategy"])
+        _line(workload="sweep", op="dot", n=n, strategy=strategy_text(st), us=round(row["us"], 2),
+              p10=round(row["p10"], 2), p90=round(row["p90"], 2), gbs=_gbs(8 * n + 4, row["us"]),
+              pct_peak=round(100 * (8 * n + 4) / row["us"] / 1e3 / PEAK_GBPS, 1))
+        outs[st] = dp.dot(xt, yt, st).cpu().numpy()[0]
+    _line(workload="sweep", op="dot", autotuned=dataclasses.asdict(best), text=strategy_text(best))
+    del xt, yt
+    m = k = 16384
+    A, xv = synthetic.gemv_inputs(m, k, seed)
+    At, xvt = torch.from_numpy(A).cuda(), torch.from_numpy(xv).cuda()
+    gbest, gtable = T.tune_gemv(At, xvt, reps=args.steps)
+    gbytes = 4 * (m * k + m + k)
+    gouts = {}
+    for row in gtable:
+        st = dp.Strategy(**row["strategy"])
+        _line(workload="sweep", op="gemv", m=m, k=k, strategy=strategy_text(st, gemv=True)
+              + f" parts={st.row_parts}", us=round(row["us"], 2), p10=round(row["p10"], 2),
+              p90=round(row["p90"], 2), gbs=_gbs(gbytes, row["us"]),
+              pct_peak=round(100 * gbytes / row["us"] / 1e3 / PEAK_GBPS, 1))
+        gouts[st] = dp.gemv(At, xvt, st).cpu().numpy()
+    _line(workload="sweep", op="gemv", autotuned=dataclasses.asdict(gbest),
+          text=strategy_text(gbest, gemv=True))
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        t0 = time.perf_counter()
+        dot_ok = all(np.float32(S.dot(x, y, to_plan(st))).view(np.uint32) == np.float32(v).view(np.uint32)
+                     for st, v in outs.items())
+        gemv_ok = all(np.array_equal(S.gemv(A, xv, to_plan(st)).view(np.uint32), v.view(np.uint32))
+                      for st, v in gouts.items())
+        _line(workload="sweep", cpu_baseline={"kind": "oracle", "cores": 1,
+                                              "seconds": round(time.perf_counter() - t0, 1)},
+              parity={"dot_all_24_bit_exact": bool(dot_ok), "gemv_all_24_bit_exact": bool(gemv_ok)})
+
+
+PRECISION_GEMV = dp.Strategy(seq_len=64, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE,
+                             rows_per_wg=1)
+KAHAN_DOT = dp.Strategy(seq_len=256, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
+                        passes=2, accum=dp.KAHAN, final_f64=1)
+
+
+def workload_precision(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import time_us
+    seed = synthetic.SEEDS["precision"]
+    m = k = 16384
+    A, xv = synthetic.gemv_inputs(m, k, seed)
+    xvt = torch.from_numpy(xv).cuda()
+    codes16 = synthetic.quantise_bf16(A)
+    codes8, scale = synthetic.quantise_fp8_rows(A)
+    s = PRECISION_GEMV
+    results = {}
+    for name, codes, dt, sc, nbytes in (
+            ("gemv_f32", A, dp.F32, None, 4 * m * k + 4 * k + 4 * m),
+            ("gemv_bf16", codes16.view(np.int16), dp.BF16, None, 2 * m * k + 4 * k + 4 * m),
+            ("gemv_fp8", codes8, dp.FP8_E4M3, scale, m * k + 4 * k + 8 * m)):
+        At = torch.from_numpy(np.ascontiguousarray(codes)).cuda()
+        sct = torch.from_numpy(sc).cuda() if sc is not None else None
+        y = torch.empty(m, device="cuda")
+        med, p10, p90 = time_us(lambda: dp.gemv(At, xvt, s, y=y, row_scale=sct, a_dtype=dt),
+                                reps=args.steps)
+        results[name] = y.cpu().numpy()
+        _line(workload="precision", op=name, m=m, k=k, strategy=strategy_text(s, gemv=True),
+              us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
+              pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1), algorithmic_bytes=nbytes)
+        del At
+    n = 1 << 28
+    x, y = synthetic.kahan_dot_inputs(n, seed)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = dp.workspace(KAHAN_DOT, dp.OP_DOT, dp.F32, 0, n)
+    plain = KAHAN_DOT.with_(accum=dp.PLAIN, final_f64=0)
+    out32 = torch.empty(1, device="cuda")
+    for name, fn in (("dot_kahan", lambda: dp.dot(xt, yt, KAHAN_DOT, out=out, ws=ws)),
+                     ("dot_plain", lambda: dp.dot(xt, yt, plain, out=out32, ws=ws))):
+        med, p10, p90 = time_us(fn, reps=args.steps)
+        fn()
+        torch.cuda.synchronize()
+        results[name] = (out if name == "dot_kahan" else out32).cpu().numpy()[0]
+        _line(workload="precision", op=name, n=n, strategy=strategy_text(KAHAN_DOT), us=round(med, 2),
+              p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(8 * n + 8, med),
+              pct_peak=round(100 * (8 * n + 8) / med / 1e3 / PEAK_GBPS, 1))
+    if not args.no_cpu_baseline:
+        import math
+        from oracle import exact
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        t0 = time.perf_counter()
+        ex = exact.gemv_exact(A, xv)
+        absx = np.abs(A.astype(np.float64)) @ np.abs(xv.astype(np.float64))
+        p = to_plan(s)
+        ref = {"gemv_f32": S.gemv(A, xv, p), "gemv_bf16": S.gemv(codes16, xv, p, a_format="bf16"),
+               "gemv_fp8": S.gemv(codes8, xv, p, a_format="fp8", scale=scale)}
+        for name in ("gemv_f32", "gemv_bf16", "gemv_fp8"):
+            got = results[name].astype(np.float64)
+            _line(workload="precision", op=name, bit_exact_vs_oracle=bool(np.array_equal(
+                      results[name].view(np.uint32), ref[name].view(np.uint32))),
+                  max_rel_err_vs_exact_f32_A=float(np.max(np.abs(got - ex) / absx)),
+                  note="error normalised by sum |A_rk x_k| per row; includes quantisation for bf16/fp8")
+        prod = x.astype(np.float64) * y.astype(np.float64)
+        sx = math.fsum(prod)
+        sabs = math.fsum(np.abs(prod))
+        kref = S.dot(x, y, to_plan(KAHAN_DOT))
+        pref = S.dot(x, y, to_plan(plain))
+        _line(workload="precision", op="dot_kahan",
+              bit_exact_vs_oracle=bool(np.float64(kref).view(np.uint64) == np.float64(results["dot_kahan"]).view(np.uint64)),
+              rel_err_vs_exact=abs(float(results["dot_kahan"]) - sx) / sabs,
+              plain_rel_err_vs_exact=abs(float(results["dot_plain"]) - sx) / sabs,
+              plain_bit_exact_vs_oracle=bool(np.float32(pref).view(np.uint32) == np.float32(results["dot_plain"]).view(np.uint32)),
+              cpu_seconds=round(time.perf_counter() - t0, 1),
+              note="normwise: |computed - exact| / sum |x_i y_i|; exact = math.fsum of binary64 products")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="scale", choices=["scale", "small", "sweep", "precision"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -101,6 +303,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload != "scale":
+        {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision}[
+            args.workload](args)
+        return
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)
     A, xv = synthetic.gemv_inputs(M_GEMV, K_GEMV, SEED)
@@ -174,7 +380,7 @@ def main():
             "peak": PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_kernel_us": round(dot_avg_s * 1e6, 3),
         },
     }

@@ -1,0 +1,170 @@
+"""Strategy enumeration and autotuning.
+
+The paper's premise is that a strategy is chosen by exploring semantically
+equivalent expressions (Sec. 1; the stochastic search of Steuwer et al. 2015
+that it builds on).  Here the space is the strategy descriptor: every
+candidate is a valid DPIA strategy for the problem, each gives its own
+(fixed) rounding, and the tuner times them on the device and keeps the
+fastest per operation, element type and size class.  The bits each candidate
+produces are checked against the CPU oracle by the test suite, not here: this
+module only measures.
+
+Cache: a JSON file (``DPIA_TUNE_CACHE``, default ``~/.cache/dpia/tune.json``)
+mapping "device|op|dtype|shape" to the chosen descriptor.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+import statistics
+from typing import Callable, Dict, List, Sequence, Tuple
+
+from . import (CONTIGUOUS, F32, OP_ASUM, OP_DOT, OP_GEMV, STRIDED, TREE, Strategy,
+               strategy_check)
+from ._lib import DpiaError
+
+SEQ_LENS = (64, 128, 256, 512, 1024, 8192)
+ORDERS = (CONTIGUOUS, STRIDED)
+
+
+def sweep_dot(n: int, local_size: int = 256) -> List[Strategy]:
+    """The 24 dot / asum strategies of the sweep: C in SEQ_LENS x {contiguous,
+    strided} x {1 pass, 2 passes}, L lanes, tree combine; candidates whose
+    chunk does not divide n are dropped."""
+    out = []
+    for C in SEQ_LENS:
+        for order in ORDERS:
+            for passes in (1, 2):
+                s = Strategy(seq_len=C, local_size=local_size, order=order, wg_combine=TREE,
+                             passes=passes)
+                if n % (C * local_size) == 0:
+                    out.append(s)
+    return out
+
+
+def sweep_gemv(m: int, k: int, max_lanes: int = 256) -> List[Strategy]:
+    """The 24 gemv strategies: C in SEQ_LENS x {contiguous, strided} x {1, 2
+    row parts}; L = min(max_lanes, k / (C * parts)) lanes per row part, tree
+    combine, R = max(1, 256 / team threads) rows per work-group (whole rows
+    of y per work-group; R never changes a result)."""
+    out = []
+    for C in SEQ_LENS:
+        for order in ORDERS:
+            for parts in (1, 2):
+                if k % (C * parts):
+                    continue
+                L = min(max_lanes, k // (C * parts))
+                if L < 1 or C * L * parts != k or (L & (L - 1)):
+                    continue
+                team = L // 4 if order == STRIDED and L % 4 == 0 else L
+                R = max(1, 256 // max(1, team))
+                while m % R:
+                    R //= 2
+                s = Strategy(seq_len=C, local_size=L, order=order, wg_combine=TREE,
+                             rows_per_wg=R, row_parts=parts)
+                out.append(s)
+    return out
+
+
+def valid(s: Strategy, op: int, dtype: int, m: int, n: int) -> bool:
+    try:
+        strategy_check(s, op, dtype, m, n)
+        return True
+    except DpiaError:
+        return False
+
+
+def time_us(fn: Callable[[], object], reps: int = 20, warmup: int = 3) -> Tuple[float, float, float]:
+    """(median, p10, p90) in microseconds of ``fn`` on torch's current stream,
+    with HIP events around each call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    q = statistics.quantiles(ts, n=10) if len(ts) >= 2 else [ts[0]] * 9
+    return statistics.median(ts), q[0], q[-1]
+
+
+def tune(candidates: Sequence[Strategy], run: Callable[[Strategy], Callable[[], object]],
+         reps: int = 20) -> Tuple[Strategy, List[Dict]]:
+    """Times ``run(s)`` for every candidate; returns the fastest and the table."""
+    table = []
+    for s in candidates:
+        med, p10, p90 = time_us(run(s), reps=reps)
+        table.append({"strategy": dataclasses.asdict(s), "us": med, "p10": p10, "p90": p90})
+    best = min(range(len(table)), key=lambda i: table[i]["us"])
+    return candidates[best], table
+
+
+# ------------------------------------------------------------ cache
+
+def cache_path() -> str:
+    return os.environ.get("DPIA_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "dpia", "tune.json"))
+
+
+def _key(device: str, op: int, dtype: int, shape: Tuple[int, ...]) -> str:
+    return f"{device}|{op}|{dtype}|{'x'.join(str(v) for v in shape)}"
+
+
+def load_cache() -> Dict[str, Dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def store(device: str, op: int, dtype: int, shape: Tuple[int, ...], s: Strategy) -> None:
+    c = load_cache()
+    c[_key(device, op, dtype, shape)] = dataclasses.asdict(s)
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(device: str, op: int, dtype: int, shape: Tuple[int, ...]):
+    d = load_cache().get(_key(device, op, dtype, shape))
+    return Strategy(**d) if d else None
+
+
+# ------------------------------------------------------------ convenience
+
+def tune_dot(x, y, candidates=None, reps: int = 20, op: int = OP_DOT):
+    """Tunes a dot (or asum, op=OP_ASUM, y ignored) on the given device tensors."""
+    from . import asum, dot, workspace
+    n = x.numel()
+    cands = [s for s in (candidates or sweep_dot(n)) if valid(s, op, F32, 0, n)]
+    out = __import__("torch").empty(1, device=x.device)
+
+    def run(s):
+        ws = workspace(s, op, F32, 0, n, x.device)
+        if op == OP_ASUM:
+            return lambda: asum(x, s, out=out, ws=ws)
+        return lambda: dot(x, y, s, out=out, ws=ws)
+    return tune(cands, run, reps)
+
+
+def tune_gemv(A, x, candidates=None, reps: int = 20, a_dtype: int = None):
+    from . import gemv
+    m, k = A.shape
+    dt = F32 if a_dtype is None else a_dtype
+    cands = [s for s in (candidates or sweep_gemv(m, k)) if valid(s, OP_GEMV, dt, m, k)]
+    y = __import__("torch").empty(m, device=A.device)
+
+    def run(s):
+        return lambda: gemv(A, x, s, y=y, a_dtype=a_dtype)
+    return tune(cands, run, reps)

@@ -257,3 +257,28 @@ def test_chunks_then_fold_equals_one_call(kw):
         ra = dp.fold(dp.OP_ASUM, s, ca, n, dp.F32)
         torch.cuda.synchronize()
         assert_same_bits(ra.cpu().numpy()[0], S.asum(x, to_plan(s)), "asum chunks+fold")
+
+
+def test_sweep_strategies_bit_exact_at_full_size():
+    # the 24-strategy sweeps the autotuner chooses from: dot N = 2^26 and
+    # gemv 16384 x 16384, every candidate bit-exact against the oracle
+    import torch
+    from paper_1710_08332_amd import autotune as T
+    seed = synthetic.SEEDS["sweep"]
+    n = 1 << 26
+    x, y = synthetic.dot_inputs(n, seed)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    cands = T.sweep_dot(n)
+    assert len(cands) == 24
+    for s in cands:
+        got = dp.dot(xt, yt, s).cpu().numpy()[0]
+        assert_same_bits(got, S.dot(x, y, to_plan(s)), f"sweep dot {s}")
+    del xt, yt
+    m = k = 16384
+    A, xv = synthetic.gemv_inputs(m, k, seed)
+    At, xvt = torch.from_numpy(A).cuda(), torch.from_numpy(xv).cuda()
+    gc = T.sweep_gemv(m, k)
+    assert len(gc) == 24
+    for s in gc:
+        got = dp.gemv(At, xvt, s).cpu().numpy()
+        assert_same_bits(got, S.gemv(A, xv, to_plan(s)), f"sweep gemv {s}")
