@@ -215,18 +215,51 @@ def gemv_expr(m: int, k: int, plan: Plan, a_format: str = "f32") -> str:
 
 
 # ------------------------------------------------------------------ running
+#
+# Lengths that the strategy's split does not divide.  Fig. 5a types split so
+# that its argument's length is a multiple of the row length.  For a vector
+# (or row) whose length is not a multiple of the chunk, the reading taken is
+# that the strategy applies to the input extended with zeros up to the next
+# multiple of the chunk (for gemv: of W * row parts).  For the plain
+# operators this cannot change a result: a zero element contributes
+# (0 * 0) + a or |0| + a, which equals a for every accumulator a a fold from
+# +0 can hold (never -0).  Compensated (Kahan) accumulation is changed by
+# extra zeros, so it is only defined for lengths the chunk divides.
+
+def _zero_extend(v: np.ndarray, length: int, axis: int = -1) -> np.ndarray:
+    v = np.asarray(v)
+    pad = length - v.shape[axis]
+    if pad == 0:
+        return v
+    if pad < 0:
+        raise ValueError("cannot extend to a shorter length")
+    width = [(0, 0)] * v.ndim
+    width[axis] = (0, pad)
+    return np.pad(v, width)
+
+
+def extended_length(n: int, chunk: int) -> int:
+    return -(-n // chunk) * chunk
+
 
 def dot(xs: np.ndarray, ys: np.ndarray, plan: Plan, num: str = "f32"):
-    return evaluate(dot_expr(len(xs), plan), {"xs": xs, "ys": ys}, num)
+    n = extended_length(len(xs), plan.chunk)
+    if n != len(xs) and plan.accum != "plain":
+        raise ValueError("compensated accumulation needs n to be a multiple of the chunk")
+    return evaluate(dot_expr(n, plan), {"xs": _zero_extend(xs, n), "ys": _zero_extend(ys, n)}, num)
 
 
 def asum(xs: np.ndarray, plan: Plan, num: str = "f32"):
-    return evaluate(asum_expr(len(xs), plan), {"xs": xs}, num)
+    n = extended_length(len(xs), plan.chunk)
+    return evaluate(asum_expr(n, plan), {"xs": _zero_extend(xs, n)}, num)
 
 
 def gemv(A: np.ndarray, x: np.ndarray, plan: Plan, a_format: str = "f32",
          scale: np.ndarray = None, num: str = "f32"):
-    inputs = {"A": A, "x": x}
+    k = plan.chunk * plan.row_parts
+    if A.shape[1] > k:
+        raise ValueError(f"rows of {A.shape[1]} exceed W * row_parts = {k}")
+    inputs = {"A": _zero_extend(A, k, axis=1), "x": _zero_extend(x, k)}
     if a_format == "fp8":
         inputs["scale"] = scale
-    return evaluate(gemv_expr(A.shape[0], A.shape[1], plan, a_format), inputs, num)
+    return evaluate(gemv_expr(A.shape[0], k, plan, a_format), inputs, num)

@@ -30,9 +30,6 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #ifndef DPIA_NT_LOADS
 #define DPIA_NT_LOADS 1
 #endif
-#ifndef DPIA_DOUBLE_BUFFER
-#define DPIA_DOUBLE_BUFFER 0
-#endif
 #ifndef DPIA_BATCH_ELEMS
 #define DPIA_BATCH_ELEMS 16
 #endif
@@ -185,17 +182,23 @@ __device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL],
 //
 // Loads are issued in batches of U steps before any of them is folded, so
 // every wavefront keeps U vector loads per operand in flight; the folds then
-// consume the batch in increasing index order.  Two batches alternate, so
-// the next one is in flight while the current one is folded.  U * NV is
-// kept near 16 elements per batch to bound register use.
+// consume the batch in increasing index order.  U * NV is kept near 16
+// elements per batch: a second, alternating batch was measured slower
+// (register pressure lowered occupancy).
 template <int NV>
 struct Batch {
   static constexpr int E = DPIA_BATCH_ELEMS;
   static constexpr int U = (E / NV) < 1 ? 1 : ((E / NV) > 16 ? 16 : (E / NV));
 };
 
+// `limit` is the number of chunk elements that exist (W for a full chunk).
+// A chunk past the end of the data is the zero-extended chunk of the
+// expression; a missing element would contribute (0 * 0) + acc = acc (or
+// |0| + acc), which leaves every accumulator unchanged because folds from
+// +0 never hold -0, so missing elements are simply not folded.
 template <class Op, int ORDER, int NV, class View>
 __device__ __forceinline__ void lane_folds(const View& view, bool active, int t, int L, int C,
+                                           int limit,
                                            typename Op::T (&acc)[ORDER == kStrided ? NV : 1]) {
   using Term = typename Op::Term;
   constexpr int U = Batch<NV>::U;
@@ -203,75 +206,79 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
 #pragma unroll
   for (int v = 0; v < NL; ++v) acc[v] = Op::Arith::zero();
   if (!active) return;
-  // element offsets: strided lane l = t*NV + v takes l + k*L (one vector
-  // load covers NV lanes at the same k); contiguous lane l = t takes
-  // l*C + k (one vector load covers NV consecutive k)
-  const int start = (ORDER == kStrided) ? t * NV : t * C;
-  const int step = (ORDER == kStrided) ? L : NV;        // offset advance per load
-  const int nloads = (ORDER == kStrided) ? C : C / NV;   // loads per lane group
-  auto load_batch = [&](Term (&z)[U][NV], int j) {
-    const int o = start + j * U * step;
+  auto fold_vec = [&](Term (&z)[NV], int nvalid) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) view.template load<NV>(o + u * step, z[u]);
-  };
-  auto fold_batch = [&](Term (&z)[U][NV]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if constexpr (ORDER == kStrided)
-          acc[v] = Op::step(z[u][v], acc[v]);
-        else
-          acc[0] = Op::step(z[u][v], acc[0]);
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (ORDER == kStrided) {
+        if (v < nvalid) acc[v] = Op::step(z[v], acc[v]);
+      } else {
+        if (v < nvalid) acc[0] = Op::step(z[v], acc[0]);
       }
     }
   };
-  // two register batches: while one is folded the next one is in flight
-  const int nb = nloads / U;
-  if constexpr (!DPIA_DOUBLE_BUFFER) {
-    for (int j = 0; j < nb; ++j) {
-      Term za[U][NV];
-      load_batch(za, j);
-      __builtin_amdgcn_sched_barrier(0);
-      fold_batch(za);
-    }
-  } else if (nb > 0) {
-    Term za[U][NV], zb[U][NV];
-    load_batch(za, 0);
-    int j = 0;
-    for (; j + 1 < nb; j += 2) {
-      load_batch(zb, j + 1);
-      __builtin_amdgcn_sched_barrier(0);
-      fold_batch(za);
-      if (j + 2 < nb) load_batch(za, j + 2);
-      __builtin_amdgcn_sched_barrier(0);
-      fold_batch(zb);
-    }
-    if (j < nb) {
-      __builtin_amdgcn_sched_barrier(0);
-      fold_batch(za);
-    }
+  // element offsets: strided lane l = t*NV + v takes l + k*L (one vector
+  // load covers NV lanes at the same k); contiguous lane l = t takes
+  // l*C + k (one vector load covers NV consecutive k)
+  int start, step, nfull;
+  if constexpr (ORDER == kStrided) {
+    start = t * NV;
+    step = L;
+    const int rows = limit / L;                 // rows k whose L elements all exist
+    nfull = rows < C ? rows : C;
+  } else {
+    start = t * C;
+    step = NV;
+    int have = limit - t * C;                   // elements of this lane that exist
+    have = have < 0 ? 0 : (have > C ? C : have);
+    nfull = have / NV;
   }
-  for (int i = nb * U; i < nloads; ++i) {
+  const int nb = nfull / U;
+  for (int j = 0; j < nb; ++j) {
+    Term z[U][NV];
+    const int o = start + j * U * step;
+#pragma unroll
+    for (int u = 0; u < U; ++u) view.template load<NV>(o + u * step, z[u]);
+    __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
+#pragma unroll
+    for (int u = 0; u < U; ++u) fold_vec(z[u], NV);
+  }
+  for (int i = nb * U; i < nfull; ++i) {
     Term z[NV];
     view.template load<NV>(start + i * step, z);
+    fold_vec(z, NV);
+  }
+  // the last, partly existing row (strided) or the last elements of a lane
+  // (contiguous), one element at a time
+  if constexpr (ORDER == kStrided) {
+    if (nfull < C) {
+      const int o = start + nfull * step;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if constexpr (ORDER == kStrided)
-        acc[v] = Op::step(z[v], acc[v]);
-      else
-        acc[0] = Op::step(z[v], acc[0]);
+      for (int v = 0; v < NV; ++v) {
+        if (o + v < limit) {
+          Term z[1];
+          view.template load<1>(o + v, z);
+          acc[v] = Op::step(z[0], acc[v]);
+        }
+      }
+    }
+  } else {
+    int have = limit - t * C;
+    have = have < 0 ? 0 : (have > C ? C : have);
+    for (int k = nfull * NV; k < have; ++k) {
+      Term z[1];
+      view.template load<1>(start + k, z);
+      acc[0] = Op::step(z[0], acc[0]);
     }
   }
 }
 
 template <class Op, int ORDER, int NV, int COMBINE, class View>
 __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool active, int t,
-                                                      int team, int L, int C,
+                                                      int team, int L, int C, int limit,
                                                       typename Op::T* scratch) {
   constexpr int NL = (ORDER == kStrided) ? NV : 1;
   typename Op::T acc[NL];
-  lane_folds<Op, ORDER, NV>(view, active, t, L, C, acc);
+  lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
   return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
 }
 

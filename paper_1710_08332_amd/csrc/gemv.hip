@@ -127,6 +127,7 @@ struct GemvU32 {
 
 struct GemvArgs {
   int64_t m;
+  int64_t k;
   int64_t lda;
   int W, L, C, team, teams_per_wg, team_lds_elems, parts;
 };
@@ -146,11 +147,16 @@ __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
     const int64_t row = base + team_id;
     const bool active = row < a.m;
     const int64_t r = active ? row : 0;
+    // elements of each row part that exist (k may stop short of W * parts:
+    // the row is zero-extended)
+    const int lim0 = static_cast<int>(a.k < a.W ? a.k : a.W);
     T v = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 0, a.lda, a.W), active, t, a.team,
-                                              a.L, a.C, scratch);
+                                              a.L, a.C, lim0, scratch);
     if (a.parts == 2) {
+      const int lim1 = static_cast<int>(a.k - a.W);
       const T h1 = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 1, a.lda, a.W), active, t,
-                                                       a.team, a.L, a.C, scratch);
+                                                       a.team, a.L, a.C, lim1 > 0 ? lim1 : 0,
+                                                       scratch);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
     if (active && t == 0) op.store(row, v);
@@ -161,6 +167,7 @@ template <class Op, int MAXNV>
 hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipStream_t stream) {
   GemvArgs a{};
   a.m = m;
+  a.k = p.k;
   a.lda = lda;
   a.W = static_cast<int>(p.W);
   a.L = static_cast<int>(p.L);

@@ -118,19 +118,26 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
       os << "m = " << m << " is not a multiple of rows_per_wg = " << q.R;
       return fail(detail, DPIA_ERR_SHAPE, os.str());
     }
-    if (k != q.W * q.row_parts) {
-      os << "k = " << k << " must equal seq_len * local_size * row_parts = " << q.W * q.row_parts;
+    // rows shorter than W * row_parts are zero-extended (no partial
+    // product of a missing element changes a fold from +0)
+    if (k < 1 || k > q.W * q.row_parts) {
+      os << "k = " << k << " must be in [1, seq_len * local_size * row_parts = "
+         << q.W * q.row_parts << "]";
       return fail(detail, DPIA_ERR_SHAPE, os.str());
     }
     q.k = k;
     q.items = m;
   } else {
     if (n < 0) return fail(detail, DPIA_ERR_SHAPE, "negative length");
-    if (n % q.W) {
-      os << "n = " << n << " is not a multiple of the chunk W = seq_len * local_size = " << q.W;
+    // A length that is not a multiple of W is zero-extended to the next
+    // multiple; that leaves plain folds unchanged but not compensated ones.
+    if (n % q.W && q.accum == DPIA_ACCUM_KAHAN) {
+      os << "n = " << n << " is not a multiple of the chunk W = seq_len * local_size = " << q.W
+         << " (required for Kahan accumulation, which zero-extension would change)";
       return fail(detail, DPIA_ERR_SHAPE, os.str());
     }
-    q.items = n / q.W;
+    q.n = n;
+    q.items = (n + q.W - 1) / q.W;
   }
   if (q.W >= (int64_t(1) << 31)) {
     os << "chunk W = seq_len * local_size = " << q.W << " must be below 2^31";

@@ -27,7 +27,8 @@ struct Plan {
   uint32_t passes;
 
   int64_t L, C, W;        // lanes, elements per lane, elements per chunk
-  int64_t items;          // dot/asum: chunks G = n / W; gemv: rows m
+  int64_t items;          // dot/asum: chunks G = ceil(n / W); gemv: rows m
+  int64_t n;              // dot/asum: vector length
   int64_t k, lda;         // gemv only
   int row_parts, R;       // gemv only
 

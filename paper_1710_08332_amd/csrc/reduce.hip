@@ -106,6 +106,7 @@ enum : int { kFinalPlain = 0, kFinalKahan32 = 1, kFinalKahan64 = 2 };
 
 struct ReduceArgs {
   int64_t items;          // G chunks
+  int64_t n;              // elements; the last chunk may be partly beyond n
   int64_t W;
   int L, C, team, teams_per_wg;
   int team_lds_elems;     // LDS elements of T per team
@@ -182,7 +183,10 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
     const int64_t g = base + team_id;
     const bool active = g < a.items;
     const auto view = op.chunk(active ? g : 0, a.W);
-    const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, scratch);
+    const int64_t rest = a.n - g * a.W;
+    const int limit = static_cast<int>(rest < a.W ? rest : a.W);
+    const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, limit,
+                                                    scratch);
     if (active && t == 0) partials[g] = v;
   }
   if (a.one_pass) {
@@ -219,6 +223,7 @@ ReduceArgs reduce_args(const Plan& p, void* partials, void* counter, void* out, 
                        bool one_pass) {
   ReduceArgs a{};
   a.items = p.items;
+  a.n = p.n;
   a.W = p.W;
   a.L = static_cast<int>(p.L);
   a.C = static_cast<int>(p.C);

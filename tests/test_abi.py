@@ -53,6 +53,14 @@ def check(s, op, dt, m, n):
 BASE = dp.Strategy(seq_len=256, local_size=16)
 
 
+def test_ragged_lengths_are_zero_extended():
+    # plain strategies accept any n (G = ceil(n / W)) and gemv rows up to W
+    st, ws = check(BASE, dp.OP_DOT, dp.F32, 0, (1 << 20) + 1)
+    assert st == _lib.OK and ws == 257 * 4 + 256 + (256 - 257 * 4 % 256) % 256
+    assert check(BASE, dp.OP_GEMV, dp.F32, 10, 4000)[0] == _lib.OK
+    assert check(BASE.with_(row_parts=2), dp.OP_GEMV, dp.F32, 10, 4097)[0] == _lib.OK
+
+
 def test_valid_strategy_reports_workspace():
     st, ws = check(BASE, dp.OP_DOT, dp.F32, 0, 1 << 20)
     assert st == _lib.OK
@@ -66,7 +74,7 @@ def test_valid_strategy_reports_workspace():
 
 
 @pytest.mark.parametrize("s,op,dt,m,n,want", [
-    (BASE, dp.OP_DOT, dp.F32, 0, (1 << 20) + 4096 - 1, _lib.ERR_SHAPE),  # n % W
+    (BASE.with_(accum=dp.KAHAN), dp.OP_DOT, dp.F32, 0, (1 << 20) + 5, _lib.ERR_SHAPE),  # n % W, Kahan
     (BASE.with_(local_size=12), dp.OP_DOT, dp.F32, 0, 12 * 256, _lib.ERR_STRATEGY),  # tree, L not 2^k
     (BASE.with_(seq_len=0), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
     (BASE.with_(passes=3), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
@@ -79,7 +87,7 @@ def test_valid_strategy_reports_workspace():
     (BASE.with_(rows_per_wg=2), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
     (BASE.with_(local_size=2048, seq_len=1, wg_combine=dp.SEQ), dp.OP_DOT, dp.F32, 0, 2048,
      _lib.ERR_STRATEGY),   # 2048 contiguous lanes > 1024 threads
-    (BASE, dp.OP_GEMV, dp.F32, 10, 4000, _lib.ERR_SHAPE),           # k != L*C
+    (BASE, dp.OP_GEMV, dp.F32, 10, 4097, _lib.ERR_SHAPE),           # k > L*C
     (BASE.with_(rows_per_wg=3), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_SHAPE),  # m % R
     (BASE.with_(rows_per_wg=0), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
     (BASE.with_(row_parts=3), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
@@ -113,7 +121,7 @@ def _dot(s, n, x=P, y=P, out=P2, out_dt=dp.F32, ws=P2, wsb=1 << 20, dt=dp.F32):
 
 def test_entry_points_validate_before_launching():
     n = 1 << 20
-    assert _dot(BASE, n + 1) == _lib.ERR_SHAPE
+    assert _dot(BASE.with_(accum=dp.KAHAN), n + 1) == _lib.ERR_SHAPE
     assert _dot(BASE, n, out=ctypes.c_void_p(0)) == _lib.ERR_NULL
     assert _dot(BASE, n, x=ctypes.c_void_p(0)) == _lib.ERR_NULL
     assert _dot(BASE, n, x=ctypes.c_void_p(0x7000_0004)) == _lib.ERR_SHAPE   # misaligned
@@ -140,7 +148,7 @@ def test_entry_points_validate_before_launching():
 
 def test_python_strategy_check_raises_with_detail():
     with pytest.raises(dp.DpiaError) as ei:
-        dp.strategy_check(BASE, dp.OP_DOT, dp.F32, 0, 1000)
+        dp.strategy_check(BASE.with_(accum=dp.KAHAN), dp.OP_DOT, dp.F32, 0, 1000)
     assert "multiple of the chunk" in str(ei.value)
 
 
@@ -151,7 +159,7 @@ def test_stage_entry_points_validate_before_launching():
     assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, P, P2, 1023, None) == _lib.ERR_WORKSPACE
     assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, None, P2, 1024, None) == _lib.ERR_NULL
     assert L.dpia_chunks(ctypes.byref(cs), dp.OP_GEMV, dp.F32, n, P, P, P2, 1024, None) == _lib.ERR_STRATEGY
-    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, n + 16, P, P, P2, 1 << 20, None) == _lib.ERR_SHAPE
+    assert L.dpia_chunks(ctypes.byref(cs), dp.OP_DOT, dp.F32, -1, P, P, P2, 1 << 20, None) == _lib.ERR_SHAPE
     ks = BASE.with_(accum=dp.KAHAN).c()
     assert L.dpia_chunks(ctypes.byref(ks), dp.OP_DOT, dp.F32, n, P, P, P2, 2047, None) == _lib.ERR_WORKSPACE
     assert L.dpia_fold(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, P2, dp.F64, None) == _lib.ERR_DTYPE

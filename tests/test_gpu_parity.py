@@ -282,3 +282,48 @@ def test_sweep_strategies_bit_exact_at_full_size():
     for s in gc:
         got = dp.gemv(At, xvt, s).cpu().numpy()
         assert_same_bits(got, S.gemv(A, xv, to_plan(s)), f"sweep gemv {s}")
+
+
+RAGGED = [(256, 16, C_, TREE), (64, 256, T_, TREE), (5, 4, T_, SEQ), (8, 128, C_, SEQ),
+          (33, 32, C_, TREE), (16, 1024, T_, TREE)]
+
+
+@pytest.mark.parametrize("strat", RAGGED, ids=_ids)
+@pytest.mark.parametrize("extra", [1, 3, 37, 4095])
+def test_ragged_lengths_are_zero_extended(strat, extra):
+    C, L, order, comb = strat
+    W = C * L
+    n = W * 3 + (extra % W if extra % W else 1)
+    for passes in (1, 2):
+        s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, passes=passes)
+        x, y = discriminating(19 + extra, n)
+        assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, to_plan(s)), f"ragged dot n={n}")
+        assert_same_bits(gpu_asum(x, s), S.asum(x, to_plan(s)), f"ragged asum n={n}")
+
+
+def test_short_vectors_smaller_than_one_chunk():
+    s = dp.Strategy(seq_len=64, local_size=256, order=T_)
+    for n in (1, 2, 5, 255, 257, 1000):
+        x, y = discriminating(23, n)
+        assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, to_plan(s)), f"short n={n}")
+
+
+@pytest.mark.parametrize("kw", [dict(seq_len=4, local_size=256, order=T_),
+                                dict(seq_len=4, local_size=256, order=C_, wg_combine=SEQ),
+                                dict(seq_len=2, local_size=256, order=T_, row_parts=2, rows_per_wg=4),
+                                dict(seq_len=16, local_size=64, order=C_, row_parts=2)], ids=str)
+@pytest.mark.parametrize("k", [1, 37, 1000, 1001, 1023])
+def test_gemv_ragged_rows(kw, k):
+    import torch
+    s = dp.Strategy(**kw)
+    if k > s.seq_len * s.local_size * s.row_parts:
+        pytest.skip("row longer than the strategy")
+    m = 4 * s.rows_per_wg * 3
+    lda = -(-k // 4) * 4                         # rows 16-byte aligned
+    A, x = synthetic.gemv_inputs(m, lda, 29)
+    At = torch.from_numpy(A).cuda()[:, :k]
+    xt = torch.from_numpy(np.ascontiguousarray(x[:k])).cuda()
+    y = dp.gemv(At, xt, s)
+    torch.cuda.synchronize()
+    assert_same_bits(y.cpu().numpy(), S.gemv(np.ascontiguousarray(A[:, :k]), x[:k], to_plan(s)),
+                     f"gemv k={k}")

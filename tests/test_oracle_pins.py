@@ -657,3 +657,28 @@ def test_golden_paper_index_maps():
     for i in range(3):
         for j in (0, 5, 1023):
             assert joined[eval(maps["hoisted_tmp"], {"i": i, "j": j})] == w[i, j]
+
+
+def test_zero_extension_is_invisible_to_plain_folds():
+    # A ragged length is read as the input extended with zeros.  Pin: the
+    # extended evaluation equals the same strategy evaluated on the same
+    # values placed in a longer zero-filled vector by hand, and the
+    # extension adds exactly nothing (integer-valued data: exact sums).
+    g = np.random.default_rng(35)
+    for n in (1, 7, 100, 1000, 4097):
+        x = g.integers(-8, 9, n).astype(np.float32)
+        y = g.integers(-8, 9, n).astype(np.float32)
+        for p in (S.Plan(seq=16, lanes=16), S.Plan(seq=5, lanes=3, combine="seq", order="strided")):
+            m = S.extended_length(n, p.chunk)
+            xz = np.zeros(m, np.float32)
+            yz = np.zeros(m, np.float32)
+            xz[:n], yz[:n] = x, y
+            assert same_bits(S.dot(x, y, p), S.dot(xz, yz, p))
+            assert float(S.dot(x, y, p)) == float(np.dot(x.astype(np.int64), y.astype(np.int64)))
+            assert same_bits(S.asum(x, p), S.asum(xz, p))
+    # the padding never yields -0 even when every product is -0
+    x = -np.ones(10, np.float32)
+    y = np.zeros(10, np.float32)
+    assert np.float32(S.dot(x, y, S.Plan(seq=4, lanes=4))).view(np.uint32) == 0
+    with pytest.raises(ValueError):
+        S.dot(np.ones(10, np.float32), np.ones(10, np.float32), S.Plan(seq=4, lanes=4, accum="kahan"))
