@@ -23,6 +23,11 @@ Other workloads (one JSON line per measured item, not the headline):
                           and the compensated dot at N = 2^28, with their
                           error against the exact (binary64-correctly-rounded)
                           value
+    --workload batch      4096 dot / asum instances (n log-uniform in
+                          [2^8, 2^20]) and 512 gemvs (m, k in [64, 4096]),
+                          strategies tuned per size class: per-instance
+                          launches (eager, graph) against one batched run
+                          (eager, graph)
 Oracle work (parity, exact references) runs only in the CPU-baseline leg,
 which --no-cpu-baseline skips.
 """
@@ -281,13 +286,142 @@ def workload_precision(args):
               note="normwise: |computed - exact| / sum |x_i y_i|; exact = math.fsum of binary64 products")
 
 
+def batch_instances(seed: int, n_red: int = 4096, n_gemv: int = 512):
+    """Config 5: n_red dot / asum instances (seeded coin) with n = floor(2^U(8, 20))
+    and n_gemv gemvs with m, k uniform in {64..4096}; all data uniform in
+    [-1, 1].  Returns (instances, host copies, algorithmic bytes)."""
+    import torch
+    import synthetic
+    g = synthetic.rng(seed)
+    insts, host, nbytes = [], [], 0
+    for _ in range(n_red):
+        op = dp.OP_DOT if g.random() < 0.5 else dp.OP_ASUM
+        n = int(2 ** g.uniform(8, 20))
+        x = synthetic.uniform_pm1(g, n)
+        d = {"op": op, "x": torch.from_numpy(x).cuda(), "out": torch.empty(1, device="cuda")}
+        y = None
+        if op == dp.OP_DOT:
+            y = synthetic.uniform_pm1(g, n)
+            d["y"] = torch.from_numpy(y).cuda()
+            nbytes += 8 * n + 4
+        else:
+            nbytes += 4 * n + 4
+        insts.append(d)
+        host.append((op, x, y))
+    for _ in range(n_gemv):
+        m, k = int(g.integers(64, 4097)), int(g.integers(64, 4097))
+        lda = -(-k // 4) * 4
+        A = torch.empty((m, lda), dtype=torch.float32, device="cuda")
+        Ah = synthetic.uniform_pm1(g, (m, k))
+        A[:, :k].copy_(torch.from_numpy(Ah))
+        x = synthetic.uniform_pm1(g, k)
+        insts.append({"op": dp.OP_GEMV, "A": A[:, :k], "x": torch.from_numpy(x).cuda(),
+                      "out": torch.empty(m, device="cuda")})
+        host.append((dp.OP_GEMV, Ah, x))
+        nbytes += 4 * (m * k + k + m)
+    return insts, host, nbytes
+
+
+def workload_batch(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd import autotune as T
+    from paper_1710_08332_amd.autotune import time_us
+    t0 = time.perf_counter()
+    insts, host, nbytes = batch_instances(synthetic.SEEDS["batch"])
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    strategies, assign, table = T.tune_batch(insts, reps=5)
+    tune_s = time.perf_counter() - t0
+    for i, d in enumerate(insts):
+        d["strategy"] = assign[i]
+    plan = dp.BatchPlan(insts, strategies)
+    ws = plan.workspace()
+    plan.upload(ws)
+
+    # per-instance calls, each with its class's strategy (2 passes), one
+    # shared workspace (calls are ordered on the stream)
+    big = max(dp.strategy_check(strategies[assign[i]], d["op"], dp.F32, 0, d["x"].numel())
+              for i, d in enumerate(insts) if d["op"] != dp.OP_GEMV)
+    ws1 = torch.zeros(big, dtype=torch.uint8, device="cuda")
+
+    def per_instance():
+        for i, d in enumerate(insts):
+            s = strategies[assign[i]]
+            if d["op"] == dp.OP_DOT:
+                dp.dot(d["x"], d["y"], s, out=d["out"], ws=ws1)
+            elif d["op"] == dp.OP_ASUM:
+                dp.asum(d["x"], s, out=d["out"], ws=ws1)
+            else:
+                dp.gemv(d["A"], d["x"], s, y=d["out"])
+
+    def graphed(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            fn()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(gr, stream=side):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        return gr
+
+    reps = max(3, min(args.steps, 20))
+    rows = {}
+    per_us, _, _ = time_us(per_instance, reps=3, warmup=1)
+    per_out = [d["out"].clone() for d in insts]
+    rows["per_instance_eager"] = per_us
+    g1 = graphed(per_instance)
+    rows["per_instance_graph"] = time_us(g1.replay, reps=reps, warmup=1)[0]
+    rows["batched_eager"] = time_us(lambda: plan.run(ws), reps=reps, warmup=1)[0]
+    g2 = graphed(lambda: plan.run(ws))
+    rows["batched_graph"] = time_us(g2.replay, reps=reps, warmup=1)[0]
+    plan.run(ws)
+    torch.cuda.synchronize()
+    same = all(np.array_equal(d["out"].cpu().numpy().view(np.uint32), p.cpu().numpy().view(np.uint32))
+               for d, p in zip(insts, per_out))
+    for name, us in rows.items():
+        _line(workload="batch", mode=name, instances=len(insts), us=round(us, 1),
+              gbs=_gbs(nbytes, us), pct_peak=round(100 * nbytes / us / 1e3 / PEAK_GBPS, 1),
+              speedup_vs_per_instance_graph=round(rows["per_instance_graph"] / us, 2))
+    _line(workload="batch", algorithmic_bytes=nbytes, batched_equals_per_instance_bitwise=bool(same),
+          strategies=[strategy_text(s) for s in strategies], size_classes=len(table),
+          tune_seconds=round(tune_s, 1), generate_seconds=round(gen_s, 1),
+          note="one batched run = 2 launches; per-instance = one call per instance (2 kernels "
+               "per reduction), the same strategies")
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        g = np.random.default_rng(5)
+        sample = sorted(g.choice(len(insts), size=64, replace=False).tolist())
+        ok = True
+        t0 = time.perf_counter()
+        for i in sample:
+            op, a, b = host[i]
+            p = to_plan(strategies[assign[i]])
+            got = insts[i]["out"].cpu().numpy()
+            if op == dp.OP_GEMV:
+                want = S.gemv(a, b, p)
+            elif op == dp.OP_DOT:
+                want = np.atleast_1d(S.dot(a, b, p))
+            else:
+                want = np.atleast_1d(S.asum(a, p))
+            ok = ok and np.array_equal(got.view(np.uint32), np.asarray(want, np.float32).view(np.uint32))
+        _line(workload="batch", cpu_baseline={"kind": "oracle", "cores": 1, "sample": "64 random instances",
+                                              "seconds": round(time.perf_counter() - t0, 1)},
+              parity={"sample_bit_exact": bool(ok)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="scale", choices=["scale", "small", "sweep", "precision"])
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "small", "sweep", "precision", "batch"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -304,8 +438,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.workload != "scale":
-        {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision}[
-            args.workload](args)
+        {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision,
+         "batch": workload_batch}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)

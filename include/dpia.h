@@ -207,6 +207,63 @@ dpia_status dpia_chunks(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64
 dpia_status dpia_fold(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t n,
                       const void* chunks, void* out, dpia_dtype out_dt, dpia_stream_t stream);
 
+/*
+ * Batched execution: many independent dot / asum / gemv instances, each with
+ * its own strategy, in two launches (a persistent kernel over a table of
+ * tiles, then one work-group per reduction instance folding its chunk values
+ * in order).  Each instance's result has exactly the bits of the single call
+ * (dpia_dot / dpia_asum / dpia_gemv) with the same strategy.  This is the
+ * strategy-per-size-class execution that the paper's strategy search
+ * (Sec. 1, building on Steuwer et al. 2015) produces, for workloads of many
+ * small problems.
+ *
+ * Restrictions: F32 data, plain accumulation, strategies whose vector width
+ * is 16 bytes (strided: local_size, contiguous: seq_len a multiple of 4) and
+ * whose threads per chunk divide 256; 16-byte aligned operands; gemv lda a
+ * multiple of 4; dot/asum n >= 1 (ragged n is zero-extended as for the
+ * single calls).
+ */
+typedef struct {
+  uint32_t op;        /* dpia_op */
+  uint32_t dtype;     /* DPIA_F32 */
+  uint32_t strategy;  /* index into the plan's strategy array */
+  uint32_t reserved;  /* 0 */
+  int64_t m;          /* gemv rows (ignored for dot / asum) */
+  int64_t n;          /* dot / asum: length; gemv: k */
+  int64_t lda;        /* gemv leading dimension (ignored for dot / asum) */
+  const void* a;      /* dot / asum: x; gemv: A (device) */
+  const void* b;      /* dot: y; gemv: x; asum: NULL (device) */
+  void* out;          /* dot / asum: one float; gemv: y, m floats (device) */
+} dpia_instance;
+
+typedef struct dpia_batch_plan dpia_batch_plan;
+
+/*
+ * Validates every instance against its strategy and builds the tile tables
+ * on the host (largest tiles first).  The plan copies what it needs; the
+ * arrays passed in may be freed afterwards.  Destroy with
+ * dpia_batch_plan_destroy.  The device pointers inside the instances must
+ * stay valid for every run.
+ */
+dpia_status dpia_batch_plan_create(const dpia_instance* inst, int32_t count,
+                                   const dpia_strategy* strategies, int32_t nstrat,
+                                   dpia_batch_plan** out);
+
+/* Device workspace bytes a run needs (tables + chunk values). */
+size_t dpia_batch_workspace_bytes(const dpia_batch_plan* plan);
+
+/* Copies the plan's tables into `ws` (256-byte aligned) and waits for the
+ * copy; call once per workspace before the first run. */
+dpia_status dpia_batch_upload(const dpia_batch_plan* plan, void* ws, size_t ws_bytes,
+                              dpia_stream_t stream);
+
+/* Runs every instance: two kernel launches on `stream`, no allocation, no
+ * memset, no synchronisation (may be captured in a graph and replayed). */
+dpia_status dpia_batch_run(const dpia_batch_plan* plan, void* ws, size_t ws_bytes,
+                           dpia_stream_t stream);
+
+void dpia_batch_plan_destroy(dpia_batch_plan* plan);
+
 /* Static text for a status code. */
 const char* dpia_status_str(dpia_status st);
 

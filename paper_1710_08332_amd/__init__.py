@@ -182,3 +182,64 @@ def fold(op: int, s: Strategy, chunk_values, n: int, dtype: int, out=None, out_d
     _lib.check(_lib.lib().dpia_fold(ctypes.byref(cs), op, dtype, n, _dev(chunk_values),
                                     _dev(out), _dtype_code(out), _stream(stream)), "dpia_fold")
     return out
+
+
+# ------------------------------------------------------------ batched
+
+class BatchPlan:
+    """Many dot / asum / gemv instances, each with its own strategy, run as
+    two kernel launches (see dpia_batch_* in include/dpia.h).
+
+    ``instances``: list of dicts with keys ``op`` (OP_DOT / OP_ASUM /
+    OP_GEMV), ``strategy`` (index into ``strategies``), and tensors ``x``,
+    ``y`` (dot), ``A``, ``x`` (gemv), ``out`` (a 1-element float32 tensor for
+    dot / asum, the m-element y for gemv).  The tensors must stay alive while
+    the plan is used.
+    """
+
+    def __init__(self, instances, strategies):
+        L = _lib.lib()
+        n = len(instances)
+        arr = (_lib.CInstance * max(1, n))()
+        for i, d in enumerate(instances):
+            c = arr[i]
+            c.op, c.dtype, c.strategy, c.reserved = d["op"], F32, d["strategy"], 0
+            if d["op"] == OP_GEMV:
+                A = d["A"]
+                if A.stride(1) != 1:
+                    raise ValueError("A must be row-major")
+                c.m, c.n, c.lda = A.shape[0], A.shape[1], A.stride(0)
+                c.a, c.b = A.data_ptr(), _dev(d["x"]).value
+            else:
+                c.m, c.n, c.lda = 0, d["x"].numel(), 0
+                c.a = _dev(d["x"]).value
+                c.b = _dev(d["y"]).value if d["op"] == OP_DOT else None
+            c.out = _dev(d["out"]).value
+        cs = (_lib.CStrategy * max(1, len(strategies)))(*[s.c() for s in strategies])
+        h = ctypes.c_void_p(0)
+        _lib.check(L.dpia_batch_plan_create(arr, n, cs, len(strategies), ctypes.byref(h)),
+                   "dpia_batch_plan_create")
+        self._h = h
+        self.workspace_bytes = L.dpia_batch_workspace_bytes(h)
+
+    def workspace(self, device="cuda"):
+        return _torch().zeros(max(256, self.workspace_bytes), dtype=_torch().uint8, device=device)
+
+    def upload(self, ws, stream=None):
+        _lib.check(_lib.lib().dpia_batch_upload(self._h, _dev(ws), ws.numel(), _stream(stream)),
+                   "dpia_batch_upload")
+
+    def run(self, ws, stream=None):
+        _lib.check(_lib.lib().dpia_batch_run(self._h, _dev(ws), ws.numel(), _stream(stream)),
+                   "dpia_batch_run")
+
+    def close(self):
+        if self._h:
+            _lib.lib().dpia_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,13 +24,22 @@ TREE, SEQ = 0, 1
 PLAIN, KAHAN = 0, 1
 
 EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
-           "dpia_fold", "dpia_status_str", "dpia_last_error_detail", "dpia_abi_version")
+           "dpia_fold", "dpia_batch_plan_create", "dpia_batch_workspace_bytes",
+           "dpia_batch_upload", "dpia_batch_run", "dpia_batch_plan_destroy", "dpia_status_str",
+           "dpia_last_error_detail", "dpia_abi_version")
 
 
 class CStrategy(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "abi_version", "seq_len", "local_size", "order", "wg_combine", "passes", "accum",
         "final_f64", "rows_per_wg", "row_parts", "max_grid")]
+
+
+class CInstance(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("dtype", ctypes.c_uint32), ("strategy", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
 
 
 class DpiaError(RuntimeError):
@@ -58,8 +67,17 @@ def lib() -> ctypes.CDLL:
         L.dpia_gemv.argtypes = [sp, ctypes.c_int, i64, i64, i64, vp, vp, vp, vp, vp, u64, vp]
         L.dpia_chunks.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, u64, vp]
         L.dpia_fold.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp]
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.dpia_batch_plan_create.argtypes = [ctypes.POINTER(CInstance), ctypes.c_int32, sp,
+                                             ctypes.c_int32, pp]
+        L.dpia_batch_workspace_bytes.argtypes = [vp]
+        L.dpia_batch_workspace_bytes.restype = u64
+        L.dpia_batch_upload.argtypes = [vp, vp, u64, vp]
+        L.dpia_batch_run.argtypes = [vp, vp, u64, vp]
+        L.dpia_batch_plan_destroy.argtypes = [vp]
+        L.dpia_batch_plan_destroy.restype = None
         for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
-                  "dpia_fold"):
+                  "dpia_fold", "dpia_batch_plan_create", "dpia_batch_upload", "dpia_batch_run"):
             getattr(L, f).restype = ctypes.c_int
         L.dpia_status_str.argtypes = [ctypes.c_int]
         L.dpia_status_str.restype = ctypes.c_char_p

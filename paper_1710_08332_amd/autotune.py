@@ -168,3 +168,65 @@ def tune_gemv(A, x, candidates=None, reps: int = 20, a_dtype: int = None):
     def run(s):
         return lambda: gemv(A, x, s, y=y, a_dtype=a_dtype)
     return tune(cands, run, reps)
+
+
+# ------------------------------------------------------------ batched
+
+def size_class(inst) -> Tuple[str, int]:
+    """Reductions are classed by floor(log2 n), gemvs by floor(log2 k)."""
+    import math
+    if inst["op"] == OP_GEMV:
+        return ("gemv", int(math.floor(math.log2(max(1, inst["A"].shape[1])))))
+    return ("red", int(math.floor(math.log2(max(1, inst["x"].numel())))))
+
+
+def batch_candidates(cls: Tuple[str, int]) -> List[Strategy]:
+    """Batch-eligible strategies (16-byte loads, threads per chunk dividing
+    256) for a size class."""
+    kind, c = cls
+    out = []
+    if kind == "red":
+        for L in (64, 256, 1024):
+            for C in (4, 16, 64, 256):
+                if C * L <= 4 * (2 ** (c + 1)):        # at most 4x zero extension
+                    out.append(Strategy(seq_len=C, local_size=L, order=STRIDED, wg_combine=TREE))
+        if not out:
+            out.append(Strategy(seq_len=4, local_size=64, order=STRIDED, wg_combine=TREE))
+    else:
+        kmax = 2 ** (c + 1)                           # every k of the class fits
+        for L in (16, 64, 256):
+            C = max(1, -(-kmax // L))
+            out.append(Strategy(seq_len=C, local_size=L, order=STRIDED, wg_combine=TREE))
+    return out
+
+
+def tune_batch(instances, reps: int = 5):
+    """Picks a strategy per size class by timing batched runs of that class's
+    instances under each candidate.  Returns (strategies, assignment) where
+    assignment[i] indexes strategies for instance i, and the timing table."""
+    from . import BatchPlan
+    classes: Dict[Tuple[str, int], List[int]] = {}
+    for i, d in enumerate(instances):
+        classes.setdefault(size_class(d), []).append(i)
+    strategies: List[Strategy] = []
+    assignment = [0] * len(instances)
+    table = []
+    for cls in sorted(classes):
+        members = classes[cls]
+        sub = [dict(instances[i], strategy=0) for i in members]
+        best, best_us = None, float("inf")
+        for cand in batch_candidates(cls):
+            plan = BatchPlan(sub, [cand])
+            ws = plan.workspace()
+            plan.upload(ws)
+            med, _, _ = time_us(lambda: plan.run(ws), reps=reps, warmup=1)
+            table.append({"class": f"{cls[0]}:{cls[1]}", "members": len(members),
+                          "strategy": dataclasses.asdict(cand), "us": med})
+            plan.close()
+            if med < best_us:
+                best, best_us = cand, med
+        if best not in strategies:
+            strategies.append(best)
+        for i in members:
+            assignment[i] = strategies.index(best)
+    return strategies, assignment, table

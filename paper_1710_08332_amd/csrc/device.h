@@ -17,6 +17,8 @@
 
 #include <cstdint>
 
+#include "plan.h"
+
 #pragma clang fp contract(off)
 
 namespace dpia {
@@ -272,12 +274,92 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
   }
 }
 
+// ------------------------------------------------------------ LDS staging
+// Contiguous order through LDS.  In the contiguous order lane l folds the
+// elements l*C .. l*C + C-1 of the chunk, so the lanes of a wavefront read
+// 64 different rows at once.  Here the team instead loads a tile of kStage
+// elements of every lane's row with coalesced 16-byte loads (4 threads read
+// one row's 64 contiguous bytes), writes it to LDS, and every lane then
+// reads its own kStage elements back and folds them in increasing index:
+// the same operands in the same order as the direct path.  Elements at or
+// past `limit` are read as zeros, which fold as the identity (see
+// lane_folds), so partial chunks take the same path and every team of the
+// work-group runs the same barriers.
+constexpr int kStageVec = kStage / 4;      // 16-byte vectors per lane row
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 load4_masked(const float* p, int rem) {
+  if (rem >= 4) return ld<DPIA_NT_LOADS != 0>(reinterpret_cast<const f32x4*>(p));
+  f32x4 r = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < rem; ++i) r[i] = p[i];
+  return r;
+}
+
+template <class Op, class View>
+__device__ __forceinline__ void contiguous_staged(const View& view, bool active, int t, int L,
+                                                  int C, int limit, typename Op::T& acc,
+                                                  float* stage) {
+  constexpr int NOPS = View::kOps;
+  acc = Op::Arith::zero();
+  const int ntiles = C / kStage;
+  f32x4 regs[NOPS][kStageVec];
+  auto gload = [&](int tile) {
+#pragma unroll
+    for (int i = 0; i < kStageVec; ++i) {
+      const int q = i * L + t;
+      const int lane = q / kStageVec;
+      const int part = q - lane * kStageVec;
+      const int e = lane * C + tile * kStage + part * 4;
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        regs[o][i] = active ? load4_masked(view.operand(o) + e, limit - e)
+                            : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  };
+  gload(0);
+  for (int tile = 0; tile < ntiles; ++tile) {
+#pragma unroll
+    for (int i = 0; i < kStageVec; ++i) {
+      const int q = i * L + t;
+      const int lane = q / kStageVec;
+      const int part = q - lane * kStageVec;
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        *reinterpret_cast<f32x4*>(stage + (o * L + lane) * kStageRow + part * 4) = regs[o][i];
+    }
+    __syncthreads();
+    if (tile + 1 < ntiles) gload(tile + 1);   // in flight while this tile is folded
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < kStageVec; ++j) {
+        f32x4 v[NOPS];
+#pragma unroll
+        for (int o = 0; o < NOPS; ++o)
+          v[o] = *reinterpret_cast<const f32x4*>(stage + (o * L + t) * kStageRow + j * 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc = Op::step(View::term(v, i), acc);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// `stage`: this team's LDS staging region (contiguous order, stageable
+// views) or nullptr for direct loads.  The choice is uniform per launch.
 template <class Op, int ORDER, int NV, int COMBINE, class View>
 __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool active, int t,
                                                       int team, int L, int C, int limit,
-                                                      typename Op::T* scratch) {
+                                                      typename Op::T* scratch,
+                                                      float* stage = nullptr) {
   constexpr int NL = (ORDER == kStrided) ? NV : 1;
   typename Op::T acc[NL];
+  if constexpr (ORDER == kContiguous && View::kStageable) {
+    if (stage != nullptr) {
+      contiguous_staged<Op>(view, active, t, L, C, limit, acc[0], stage);
+      return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
+    }
+  }
   lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
   return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
 }

@@ -8,129 +8,128 @@
 // multiply; fp8 rows are scaled after the reduction: y[r] = scale[r] * sum.
 // No cross-work-group step: each team owns whole rows of y.
 #include "device.h"
+#include "ops.h"
 #include "host.h"
 #include "plan.h"
 
 namespace dpia {
-
-struct GTerm { float a, b; };
-struct GTermU { uint32_t a, b; };
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t c) {
-  return __uint_as_float(static_cast<uint32_t>(c) << 16);
-}
-
-// Decode NV fp8-e4m3 codes with the hardware converter (OCP E4M3 on gfx950;
-// checked against the format definition over all 256 codes by the tests).
-template <int NV>
-__device__ __forceinline__ void fp8_to_f32(const uint8_t (&c)[NV], float (&f)[NV]) {
-  if constexpr (NV == 1) {
-    f[0] = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(c[0]), 0);
-  } else {
-#pragma unroll
-    for (int i = 0; i < NV; i += 4) {
-      int w = 0;
-      __builtin_memcpy(&w, &c[i], (NV - i) < 4 ? (NV - i) : 4);
-      auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
-      f[i] = lo[0];
-      f[i + 1] = lo[1];
-      if constexpr (NV >= 4) {
-        auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
-        f[i + 2] = hi[0];
-        f[i + 3] = hi[1];
-      }
-    }
-  }
-}
-
-template <typename E, class Decode>
-struct GemvF32Acc {
-  using Arith = PlainF32;
-  using T = float;
-  using Term = GTerm;
-  struct View {
-    const E* a;
-    const float* x;
-    template <int NV>
-    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      E ca[NV];
-      float fa[NV], b[NV];
-      vload<E, NV>(a + off, ca);
-      vload<float, NV, false>(x + off, b);   // x is reused by every row: cached
-      Decode::template run<NV>(ca, fa);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{fa[i], b[i]};
-    }
-  };
-  const E* A;
-  const float* x;
-  const float* scale;   // fp8 only
-  float* y;
-  __device__ View part(int64_t r, int p, int64_t lda, int W) const {
-    return View{A + r * lda + static_cast<int64_t>(p) * W, x + static_cast<int64_t>(p) * W};
-  }
-  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
-  __device__ void store(int64_t r, T v) const { y[r] = scale ? scale[r] * v : v; }
-};
-
-struct DecodeF32 {
-  template <int NV>
-  __device__ static void run(const float (&c)[NV], float (&f)[NV]) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) f[i] = c[i];
-  }
-};
-struct DecodeBF16 {
-  template <int NV>
-  __device__ static void run(const uint16_t (&c)[NV], float (&f)[NV]) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) f[i] = bf16_to_f32(c[i]);
-  }
-};
-struct DecodeFP8 {
-  template <int NV>
-  __device__ static void run(const uint8_t (&c)[NV], float (&f)[NV]) {
-    fp8_to_f32<NV>(c, f);
-  }
-};
-
-using GemvF32 = GemvF32Acc<float, DecodeF32>;
-using GemvBF16 = GemvF32Acc<uint16_t, DecodeBF16>;
-using GemvFP8 = GemvF32Acc<uint8_t, DecodeFP8>;
-
-struct GemvU32 {
-  using Arith = PlainU32;
-  using T = uint32_t;
-  using Term = GTermU;
-  struct View {
-    const uint32_t* a;
-    const uint32_t* x;
-    template <int NV>
-    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      uint32_t ca[NV], b[NV];
-      vload<uint32_t, NV>(a + off, ca);
-      vload<uint32_t, NV, false>(x + off, b);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{ca[i], b[i]};
-    }
-  };
-  const uint32_t* A;
-  const uint32_t* x;
-  const float* scale;
-  uint32_t* y;
-  __device__ View part(int64_t r, int p, int64_t lda, int W) const {
-    return View{A + r * lda + static_cast<int64_t>(p) * W, x + static_cast<int64_t>(p) * W};
-  }
-  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
-  __device__ void store(int64_t r, T v) const { y[r] = v; }
-};
 
 struct GemvArgs {
   int64_t m;
   int64_t k;
   int64_t lda;
   int W, L, C, team, teams_per_wg, team_lds_elems, parts;
+  int stage_off;          // byte offset of the LDS staging region, -1: none
 };
+
+// Strided lane folds of RB rows at once: thread t holds lanes t*NV ..
+// t*NV + NV-1 of each of the RB rows, so every x load serves RB rows.  Each
+// row's lanes fold their own elements in increasing index, exactly as with
+// one row per team.  `limit`: elements of the row part that exist.
+template <class Op, int NV, int RB>
+__device__ __forceinline__ void row_block_folds(const Op& op, const int64_t (&row)[RB],
+                                                const bool (&act)[RB], int64_t lda, int64_t col0,
+                                                int t, int L, int C, int limit,
+                                                float (&acc)[RB][NV]) {
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[b][v] = 0.0f;
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) any = any || act[b];
+  if (!any) return;
+  constexpr int U = Batch<NV>::U;
+  const int rows = limit / L;
+  const int nfull = rows < C ? rows : C;
+  const int start = t * NV;
+  int k = 0;
+  for (; k + U <= nfull; k += U) {
+    float xv[U][NV], av[U][RB][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = col0 + start + static_cast<int64_t>(k + u) * L;
+      op.template load_x<NV>(c, xv[u]);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) op.template load_a<NV>(row[b], lda, c, av[u][b]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[b][v] = Op::step(typename Op::Term{av[u][b][v], xv[u][v]}, acc[b][v]);
+  }
+  for (; k < nfull; ++k) {
+    const int64_t c = col0 + start + static_cast<int64_t>(k) * L;
+    float xv[NV];
+    op.template load_x<NV>(c, xv);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      float av[NV];
+      op.template load_a<NV>(row[b], lda, c, av);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[b][v] = Op::step(typename Op::Term{av[v], xv[v]}, acc[b][v]);
+    }
+  }
+  if (nfull < C) {   // the last, partly existing row of the part
+    const int o = start + nfull * L;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (o + v < limit) {
+        const float xv = op.x[col0 + o + v];
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          acc[b][v] = Op::step(typename Op::Term{op.load_a1(row[b], lda, col0 + o + v), xv},
+                               acc[b][v]);
+      }
+    }
+  }
+}
+
+template <class Op, int NV, int COMBINE, int RB>
+__global__ void __launch_bounds__(256) gemv_block_kernel(Op op, GemvArgs a) {
+  using T = float;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const int team_id = threadIdx.x / a.team;
+  const int t = threadIdx.x - team_id * a.team;
+  T* scratch = lds + team_id * a.team_lds_elems;
+  const int64_t per_wg = static_cast<int64_t>(a.teams_per_wg) * RB;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * per_wg; base < a.m;
+       base += static_cast<int64_t>(gridDim.x) * per_wg) {
+    int64_t row[RB];
+    bool act[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int64_t r = base + static_cast<int64_t>(team_id) * RB + b;
+      act[b] = r < a.m;
+      row[b] = act[b] ? r : 0;
+    }
+    float acc[RB][NV];
+    T v[RB];
+    const int lim0 = static_cast<int>(a.k < a.W ? a.k : a.W);
+    row_block_folds<Op, NV, RB>(op, row, act, a.lda, 0, t, a.L, a.C, lim0, acc);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) v[b] = combine_lanes<PlainF32, NV, COMBINE>(acc[b], t, a.team, a.L, scratch);
+    if (a.parts == 2) {
+      const int lim1 = static_cast<int>(a.k - a.W);
+      row_block_folds<Op, NV, RB>(op, row, act, a.lda, a.W, t, a.L, a.C, lim1 > 0 ? lim1 : 0, acc);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const T h1 = combine_lanes<PlainF32, NV, COMBINE>(acc[b], t, a.team, a.L, scratch);
+        v[b] = tree_node<PlainF32>(v[b], h1);   // reduceSeq (+) 0 [h0, h1]
+      }
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if (act[b]) op.store(row[b], v[b]);
+    }
+  }
+}
 
 template <class Op, int ORDER, int NV, int COMBINE>
 __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
@@ -141,6 +140,9 @@ __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
   const int team_id = threadIdx.x / a.team;
   const int t = threadIdx.x - team_id * a.team;
   T* scratch = lds + team_id * a.team_lds_elems;
+  float* stage = a.stage_off < 0 ? nullptr
+                                 : reinterpret_cast<float*>(lds_raw + a.stage_off) +
+                                       team_id * stage_floats(a.L);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.m;
        base += stride) {
@@ -151,12 +153,12 @@ __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
     // the row is zero-extended)
     const int lim0 = static_cast<int>(a.k < a.W ? a.k : a.W);
     T v = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 0, a.lda, a.W), active, t, a.team,
-                                              a.L, a.C, lim0, scratch);
+                                              a.L, a.C, lim0, scratch, stage);
     if (a.parts == 2) {
       const int lim1 = static_cast<int>(a.k - a.W);
       const T h1 = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 1, a.lda, a.W), active, t,
                                                        a.team, a.L, a.C, lim1 > 0 ? lim1 : 0,
-                                                       scratch);
+                                                       scratch, stage);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
     if (active && t == 0) op.store(row, v);
@@ -164,7 +166,8 @@ __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
 }
 
 template <class Op, int MAXNV>
-hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipStream_t stream) {
+hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipStream_t stream,
+                       int rb = 1) {
   GemvArgs a{};
   a.m = m;
   a.k = p.k;
@@ -177,6 +180,30 @@ hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipS
   a.team_lds_elems = (p.combine == DPIA_COMBINE_SEQ) ? static_cast<int>(p.L)
                                                      : (p.team > 64 ? p.team / 64 : 1);
   a.parts = p.row_parts;
+  a.stage_off = p.stage ? static_cast<int>(p.stage_off) : -1;
+  if constexpr (Op::kRowBlockable) {
+  if (rb > 1 && p.order == DPIA_ORDER_STRIDED && p.nv == MAXNV && p.wg_threads <= 256) {
+    // row blocking: each team reduces rb rows at once (see row_block_folds)
+    const int64_t per_wg = static_cast<int64_t>(p.teams_per_wg) * rb;
+    const int64_t need = (m + per_wg - 1) / per_wg;
+    const int64_t cap = p.max_grid ? static_cast<int64_t>(p.max_grid)
+                                   : static_cast<int64_t>(device_cus()) *
+                                         (2048 / p.wg_threads > 0 ? 2048 / p.wg_threads : 1);
+    const int64_t grid = need < cap ? need : cap;
+    auto go = [&](auto comb, auto rbc) {
+      constexpr int COMBINE = decltype(comb)::value;
+      constexpr int RB = decltype(rbc)::value;
+      auto kern = gemv_block_kernel<Op, MAXNV, COMBINE, RB>;
+      Op op_copy = op;
+      void* args[] = {&op_copy, &a};
+      return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                             dim3(p.wg_threads), args, p.lds_bytes, stream);
+    };
+    if (p.combine == DPIA_COMBINE_TREE)
+      return rb == 4 ? go(ic<0>{}, ic<4>{}) : go(ic<0>{}, ic<2>{});
+    return rb == 4 ? go(ic<1>{}, ic<4>{}) : go(ic<1>{}, ic<2>{});
+  }
+  }
   const int64_t grid = grid_size(p);
   return with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
     constexpr int ORDER = decltype(ord)::value;
@@ -195,6 +222,14 @@ hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipS
 }  // namespace dpia
 
 using namespace dpia;
+
+#ifndef DPIA_ROW_BLOCK
+#define DPIA_ROW_BLOCK 4
+#endif
+// Rows one team reduces at once for bf16 / fp8 matrices (1 = no blocking):
+// with narrow A elements the x operand, reloaded per row, would otherwise
+// dominate the traffic through the vector caches.
+static constexpr int kRowBlock = DPIA_ROW_BLOCK;
 
 extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
                                  int64_t lda, const void* A, const float* row_scale,
@@ -233,13 +268,13 @@ extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_
       e = launch_gemv<GemvBF16, 8>(
           p, GemvBF16{static_cast<const uint16_t*>(A), static_cast<const float*>(x), nullptr,
                       static_cast<float*>(y)},
-          m, lda, hs);
+          m, lda, hs, kRowBlock);
       break;
     case DPIA_FP8_E4M3:
       e = launch_gemv<GemvFP8, 16>(
           p, GemvFP8{static_cast<const uint8_t*>(A), static_cast<const float*>(x), row_scale,
                      static_cast<float*>(y)},
-          m, lda, hs);
+          m, lda, hs, kRowBlock);
       break;
     case DPIA_I32:
       e = launch_gemv<GemvU32, 4>(

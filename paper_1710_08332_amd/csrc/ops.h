@@ -1,0 +1,253 @@
+// The operations a strategy can fold: each provides the lane operator
+// (step), the accumulator arithmetic (Arith) and a view of one chunk or row
+// part of its operands (element loads relative to the chunk start).
+#pragma once
+
+#include <type_traits>
+
+#include "device.h"
+
+namespace dpia {
+
+// ---------------------------------------------------------------- dot, asum
+
+struct TermF { float a, b; };
+struct TermA { float a; };
+struct TermU { uint32_t a, b; };
+
+// zip xs ys with lane operator lam z a. (fst z * snd z) + a
+struct DotF32 {
+  using Arith = PlainF32;
+  using T = float;
+  using Term = TermF;
+  struct View {
+    static constexpr bool kStageable = true;
+    static constexpr int kOps = 2;
+    const float* x;
+    const float* y;
+    __device__ const float* operand(int o) const { return o == 0 ? x : y; }
+    __device__ static Term term(const f32x4 (&v)[2], int i) { return Term{v[0][i], v[1][i]}; }
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      float a[NV], b[NV];
+      vload<float, NV>(x + off, a);
+      vload<float, NV>(y + off, b);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
+    }
+  };
+  const float* x;
+  const float* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+};
+
+// integers modulo 2^32, same expression
+struct DotU32 {
+  using Arith = PlainU32;
+  using T = uint32_t;
+  using Term = TermU;
+  struct View {
+    static constexpr bool kStageable = false;
+    const uint32_t* x;
+    const uint32_t* y;
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      uint32_t a[NV], b[NV];
+      vload<uint32_t, NV>(x + off, a);
+      vload<uint32_t, NV>(y + off, b);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
+    }
+  };
+  const uint32_t* x;
+  const uint32_t* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+};
+
+// xs with lane operator lam x a. abs x + a
+struct AsumF32 {
+  using Arith = PlainF32;
+  using T = float;
+  using Term = TermA;
+  struct View {
+    static constexpr bool kStageable = true;
+    static constexpr int kOps = 1;
+    const float* x;
+    __device__ const float* operand(int) const { return x; }
+    __device__ static Term term(const f32x4 (&v)[1], int i) { return Term{v[0][i]}; }
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      float a[NV];
+      vload<float, NV>(x + off, a);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{a[i]};
+    }
+  };
+  const float* x;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W}; }
+  __device__ static T step(const Term& z, T acc) { return fabsf(z.a) + acc; }
+};
+
+// zip xs ys with Kahan's step on acc = (s, c):
+//   y' = x*y - c ; t = s + y' ; new acc = (t, (t - s) - y')
+struct KahanDotF32 {
+  using Arith = KahanF32;
+  using T = KPair;
+  using Term = TermF;
+  using View = DotF32::View;
+  const float* x;
+  const float* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) {
+    const float yk = z.a * z.b - acc.c;
+    const float t = acc.s + yk;
+    return KPair{t, (t - acc.s) - yk};
+  }
+};
+
+
+// ---------------------------------------------------------------- gemv rows
+
+struct GTerm { float a, b; };
+struct GTermU { uint32_t a, b; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t c) {
+  return __uint_as_float(static_cast<uint32_t>(c) << 16);
+}
+
+// Decode NV fp8-e4m3 codes with the hardware converter (OCP E4M3 on gfx950;
+// checked against the format definition over all 256 codes by the tests).
+template <int NV>
+__device__ __forceinline__ void fp8_to_f32(const uint8_t (&c)[NV], float (&f)[NV]) {
+  if constexpr (NV == 1) {
+    f[0] = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(c[0]), 0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; i += 4) {
+      int w = 0;
+      __builtin_memcpy(&w, &c[i], (NV - i) < 4 ? (NV - i) : 4);
+      auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+      f[i] = lo[0];
+      f[i + 1] = lo[1];
+      if constexpr (NV >= 4) {
+        auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+        f[i + 2] = hi[0];
+        f[i + 3] = hi[1];
+      }
+    }
+  }
+}
+
+template <typename E, class Decode>
+struct GemvF32Acc {
+  using Arith = PlainF32;
+  using T = float;
+  using Term = GTerm;
+  struct View {
+    static constexpr bool kStageable = std::is_same<E, float>::value;
+    static constexpr int kOps = 2;
+    const E* a;
+    const float* x;
+    __device__ const float* operand(int o) const {
+      return o == 0 ? reinterpret_cast<const float*>(a) : x;
+    }
+    __device__ static Term term(const f32x4 (&v)[2], int i) { return Term{v[0][i], v[1][i]}; }
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      E ca[NV];
+      float fa[NV], b[NV];
+      vload<E, NV>(a + off, ca);
+      vload<float, NV, false>(x + off, b);   // x is reused by every row: cached
+      Decode::template run<NV>(ca, fa);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{fa[i], b[i]};
+    }
+  };
+  static constexpr bool kRowBlockable = true;
+  // Row blocking: NV decoded elements of row `r` (part p, offset off), and
+  // NV elements of x at the same offset, loaded separately so that one x
+  // load can serve several rows.
+  template <int NV>
+  __device__ __forceinline__ void load_a(int64_t r, int64_t lda, int64_t col,
+                                         float (&f)[NV]) const {
+    E c[NV];
+    vload<E, NV>(A + r * lda + col, c);
+    Decode::template run<NV>(c, f);
+  }
+  template <int NV>
+  __device__ __forceinline__ void load_x(int64_t col, float (&f)[NV]) const {
+    vload<float, NV, false>(x + col, f);
+  }
+  __device__ float load_a1(int64_t r, int64_t lda, int64_t col) const {
+    float f[1];
+    load_a<1>(r, lda, col, f);
+    return f[0];
+  }
+  const E* A;
+  const float* x;
+  const float* scale;   // fp8 only
+  float* y;
+  __device__ View part(int64_t r, int p, int64_t lda, int W) const {
+    return View{A + r * lda + static_cast<int64_t>(p) * W, x + static_cast<int64_t>(p) * W};
+  }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+  __device__ void store(int64_t r, T v) const { y[r] = scale ? scale[r] * v : v; }
+};
+
+struct DecodeF32 {
+  template <int NV>
+  __device__ static void run(const float (&c)[NV], float (&f)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) f[i] = c[i];
+  }
+};
+struct DecodeBF16 {
+  template <int NV>
+  __device__ static void run(const uint16_t (&c)[NV], float (&f)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) f[i] = bf16_to_f32(c[i]);
+  }
+};
+struct DecodeFP8 {
+  template <int NV>
+  __device__ static void run(const uint8_t (&c)[NV], float (&f)[NV]) {
+    fp8_to_f32<NV>(c, f);
+  }
+};
+
+using GemvF32 = GemvF32Acc<float, DecodeF32>;
+using GemvBF16 = GemvF32Acc<uint16_t, DecodeBF16>;
+using GemvFP8 = GemvF32Acc<uint8_t, DecodeFP8>;
+
+struct GemvU32 {
+  static constexpr bool kRowBlockable = false;
+  using Arith = PlainU32;
+  using T = uint32_t;
+  using Term = GTermU;
+  struct View {
+    static constexpr bool kStageable = false;
+    const uint32_t* a;
+    const uint32_t* x;
+    template <int NV>
+    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+      uint32_t ca[NV], b[NV];
+      vload<uint32_t, NV>(a + off, ca);
+      vload<uint32_t, NV, false>(x + off, b);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{ca[i], b[i]};
+    }
+  };
+  const uint32_t* A;
+  const uint32_t* x;
+  const float* scale;
+  uint32_t* y;
+  __device__ View part(int64_t r, int p, int64_t lda, int W) const {
+    return View{A + r * lda + static_cast<int64_t>(p) * W, x + static_cast<int64_t>(p) * W};
+  }
+  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
+  __device__ void store(int64_t r, T v) const { y[r] = v; }
+};
+
+}  // namespace dpia

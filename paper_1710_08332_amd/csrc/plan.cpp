@@ -178,6 +178,16 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   } else if (q.team > 64) {
     lds = static_cast<size_t>(q.teams_per_wg) * (q.team / 64) * q.acc_bytes;
   }
+  // The contiguous order with binary32 operands is staged through LDS when
+  // every lane holds whole tiles and the work-group has at most 256 threads.
+  q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 &&
+            q.C % kStage == 0 && q.wg_threads <= 256;
+  q.stage_off = 0;
+  if (q.stage) {
+    q.stage_off = round_up(lds, 16);
+    lds = q.stage_off + static_cast<size_t>(q.teams_per_wg) * stage_floats(static_cast<int>(q.L)) *
+                            sizeof(float);
+  }
   if (op != DPIA_OP_GEMV) {
     size_t fold = static_cast<size_t>(kFoldBlock) * q.acc_bytes;
     if (fold > lds) lds = fold;

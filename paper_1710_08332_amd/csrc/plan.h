@@ -16,6 +16,12 @@ constexpr int kVecBytes = 16;
 constexpr int kFoldBlock = 2048;
 // Alignment of the sections of a workspace.
 constexpr size_t kWsAlign = 256;
+// LDS staging of the contiguous order: elements per lane per tile, and the
+// LDS row stride in floats (80 bytes: an odd number of 16-byte units).
+constexpr int kStage = 16;
+constexpr int kStageRow = kStage + 4;
+// LDS floats one team needs for staging: two operands x L rows.
+constexpr int stage_floats(int L) { return 2 * L * kStageRow; }
 
 struct Plan {
   dpia_op op;
@@ -43,6 +49,8 @@ struct Plan {
   size_t partial_bytes;   // workspace bytes for the chunk results (aligned)
   size_t ws_bytes;        // total workspace: partials + arrival counter
   size_t lds_bytes;       // dynamic LDS per work-group
+  bool stage;             // contiguous order staged through LDS
+  size_t stage_off;       // byte offset of the staging region in the LDS
 };
 
 size_t elem_bytes(dpia_dtype dt);

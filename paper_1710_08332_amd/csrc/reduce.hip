@@ -10,99 +10,12 @@
 // release fence, integer arrival counter, acquire fence).  Both evaluate the
 // same expression and give the same bits.
 #include "device.h"
+#include "fold.h"
+#include "ops.h"
 #include "host.h"
 #include "plan.h"
 
 namespace dpia {
-
-struct TermF { float a, b; };
-struct TermA { float a; };
-struct TermU { uint32_t a, b; };
-
-// zip xs ys with lane operator lam z a. (fst z * snd z) + a
-struct DotF32 {
-  using Arith = PlainF32;
-  using T = float;
-  using Term = TermF;
-  struct View {
-    const float* x;
-    const float* y;
-    template <int NV>
-    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      float a[NV], b[NV];
-      vload<float, NV>(x + off, a);
-      vload<float, NV>(y + off, b);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
-    }
-  };
-  const float* x;
-  const float* y;
-  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
-  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
-};
-
-// integers modulo 2^32, same expression
-struct DotU32 {
-  using Arith = PlainU32;
-  using T = uint32_t;
-  using Term = TermU;
-  struct View {
-    const uint32_t* x;
-    const uint32_t* y;
-    template <int NV>
-    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      uint32_t a[NV], b[NV];
-      vload<uint32_t, NV>(x + off, a);
-      vload<uint32_t, NV>(y + off, b);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{a[i], b[i]};
-    }
-  };
-  const uint32_t* x;
-  const uint32_t* y;
-  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
-  __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
-};
-
-// xs with lane operator lam x a. abs x + a
-struct AsumF32 {
-  using Arith = PlainF32;
-  using T = float;
-  using Term = TermA;
-  struct View {
-    const float* x;
-    template <int NV>
-    __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      float a[NV];
-      vload<float, NV>(x + off, a);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{a[i]};
-    }
-  };
-  const float* x;
-  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W}; }
-  __device__ static T step(const Term& z, T acc) { return fabsf(z.a) + acc; }
-};
-
-// zip xs ys with Kahan's step on acc = (s, c):
-//   y' = x*y - c ; t = s + y' ; new acc = (t, (t - s) - y')
-struct KahanDotF32 {
-  using Arith = KahanF32;
-  using T = KPair;
-  using Term = TermF;
-  using View = DotF32::View;
-  const float* x;
-  const float* y;
-  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
-  __device__ static T step(const Term& z, T acc) {
-    const float yk = z.a * z.b - acc.c;
-    const float t = acc.s + yk;
-    return KPair{t, (t - acc.s) - yk};
-  }
-};
-
-enum : int { kFinalPlain = 0, kFinalKahan32 = 1, kFinalKahan64 = 2 };
 
 struct ReduceArgs {
   int64_t items;          // G chunks
@@ -110,60 +23,13 @@ struct ReduceArgs {
   int64_t W;
   int L, C, team, teams_per_wg;
   int team_lds_elems;     // LDS elements of T per team
+  int stage_off;          // byte offset of the LDS staging region, -1: none
   int one_pass;
   int out_f64;            // Kahan 64 only: write a double
   void* partials;
   unsigned int* counter;
   void* out;
 };
-
-// The outer reduceSeq over the G chunk values, from the literal 0, in chunk
-// order, by one thread.  The work-group stages blocks of chunk values in LDS
-// (coalesced), then thread 0 reads them back 32 at a time into registers
-// and folds them in order.
-template <class A, int FINAL>
-__device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
-                           typename A::T* buf) {
-  using T = typename A::T;
-  constexpr int R = 32;
-  T acc = A::zero();
-  double acc64 = 0.0;
-  auto fold1 = [&](const T& e) {
-    if constexpr (FINAL == kFinalKahan64)
-      acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
-    else
-      acc = A::add(e, acc);
-  };
-  for (int64_t b = 0; b < G; b += kFoldBlock) {
-    const int cnt = static_cast<int>(G - b < kFoldBlock ? G - b : kFoldBlock);
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[i] = partials[b + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int i = 0;
-      for (; i + R <= cnt; i += R) {
-        T r[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) r[j] = buf[i + j];
-#pragma unroll
-        for (int j = 0; j < R; ++j) fold1(r[j]);
-      }
-      for (; i < cnt; ++i) fold1(buf[i]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if constexpr (FINAL == kFinalKahan64) {
-      if (out_f64)
-        *static_cast<double*>(out) = acc64;
-      else
-        *static_cast<float*>(out) = static_cast<float>(acc64);
-    } else if constexpr (FINAL == kFinalKahan32) {
-      *static_cast<float*>(out) = acc.s - acc.c;
-    } else {
-      *static_cast<T*>(out) = acc;
-    }
-  }
-}
 
 template <class Op, int ORDER, int NV, int COMBINE, int FINAL>
 __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
@@ -174,6 +40,9 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
   const int team_id = threadIdx.x / a.team;
   const int t = threadIdx.x - team_id * a.team;
   T* scratch = lds + team_id * a.team_lds_elems;
+  float* stage = a.stage_off < 0 ? nullptr
+                                 : reinterpret_cast<float*>(lds_raw + a.stage_off) +
+                                       team_id * stage_floats(a.L);
   T* partials = static_cast<T*>(a.partials);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
   // parforWorkgroup as a grid-stride loop: every thread of a work-group
@@ -186,7 +55,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
     const int64_t rest = a.n - g * a.W;
     const int limit = static_cast<int>(rest < a.W ? rest : a.W);
     const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, limit,
-                                                    scratch);
+                                                    scratch, stage);
     if (active && t == 0) partials[g] = v;
   }
   if (a.one_pass) {
@@ -231,6 +100,7 @@ ReduceArgs reduce_args(const Plan& p, void* partials, void* counter, void* out, 
   a.teams_per_wg = p.teams_per_wg;
   a.team_lds_elems = (p.combine == DPIA_COMBINE_SEQ) ? static_cast<int>(p.L)
                                                      : (p.team > 64 ? p.team / 64 : 1);
+  a.stage_off = p.stage ? static_cast<int>(p.stage_off) : -1;
   a.out_f64 = out_f64;
   a.partials = partials;
   a.counter = static_cast<unsigned int*>(counter);

@@ -165,3 +165,55 @@ def test_stage_entry_points_validate_before_launching():
     assert L.dpia_fold(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, P, P2, dp.F64, None) == _lib.ERR_DTYPE
     assert L.dpia_fold(ctypes.byref(cs), dp.OP_DOT, dp.F32, n, None, P2, dp.F32, None) == _lib.ERR_NULL
     assert L.dpia_fold(ctypes.byref(cs), dp.OP_ASUM, dp.I32, n, P, P2, dp.I32, None) == _lib.ERR_DTYPE
+
+
+def _inst(op, n, strategy=0, a=P, b=P, out=P2, m=0, lda=0, dtype=dp.F32):
+    c = _lib.CInstance()
+    c.op, c.dtype, c.strategy, c.reserved = op, dtype, strategy, 0
+    c.m, c.n, c.lda = m, n, lda
+    c.a, c.b, c.out = a.value, (b.value if b is not None else None), out.value
+    return c
+
+
+def _plan(insts, strategies):
+    arr = (_lib.CInstance * len(insts))(*insts)
+    cs = (_lib.CStrategy * len(strategies))(*[s.c() for s in strategies])
+    h = ctypes.c_void_p(0)
+    st = _lib.lib().dpia_batch_plan_create(arr, len(insts), cs, len(strategies), ctypes.byref(h))
+    return st, h
+
+
+def test_batch_plan_validation_is_host_only():
+    L = _lib.lib()
+    good = dp.Strategy(seq_len=16, local_size=256, order=dp.STRIDED)
+    st, h = _plan([_inst(dp.OP_DOT, 100000), _inst(dp.OP_ASUM, 300, b=None),
+                   _inst(dp.OP_GEMV, 4000, m=10, lda=4000)], [good])
+    assert st == _lib.OK, _lib.last_error_detail()
+    # tables: 3 instances (256 B), tiles, 2 reduction indices, chunk values
+    assert L.dpia_batch_workspace_bytes(h) > 0
+    L.dpia_batch_plan_destroy(h)
+    bad_cases = [
+        ([_inst(dp.OP_DOT, 1000, strategy=1)], [good], _lib.ERR_STRATEGY),        # index
+        ([_inst(dp.OP_DOT, 1000, dtype=dp.I32)], [good], _lib.ERR_DTYPE),
+        ([_inst(dp.OP_DOT, 1000)], [good.with_(accum=dp.KAHAN)], _lib.ERR_STRATEGY),
+        ([_inst(dp.OP_DOT, 1000)], [good.with_(local_size=254, wg_combine=dp.SEQ)],
+         _lib.ERR_STRATEGY),                                                      # 16-byte loads
+        ([_inst(dp.OP_DOT, 1000)], [good.with_(local_size=4096)], _lib.ERR_STRATEGY),  # > 256 threads
+        ([_inst(dp.OP_DOT, 1000)], [good.with_(local_size=12, wg_combine=dp.SEQ)],
+         _lib.ERR_STRATEGY),                                                      # 3 threads
+        ([_inst(dp.OP_DOT, 1000, b=None)], [good], _lib.ERR_NULL),
+        ([_inst(dp.OP_DOT, 1000, a=ctypes.c_void_p(0x7000_0008))], [good], _lib.ERR_SHAPE),
+        ([_inst(dp.OP_GEMV, 4000, m=10, lda=4002)], [good], _lib.ERR_SHAPE),      # lda % 4
+        ([_inst(dp.OP_GEMV, 5000, m=10, lda=5000)], [good], _lib.ERR_SHAPE),      # k > W
+        ([_inst(dp.OP_DOT, 0)], [good], _lib.ERR_SHAPE),
+    ]
+    for insts, strats, want in bad_cases:
+        st, h = _plan(insts, strats)
+        assert st == want, (st, _lib.last_error_detail())
+        assert not h.value
+    # workspace checks happen before any copy or launch
+    st, h = _plan([_inst(dp.OP_DOT, 100000)], [good])
+    assert L.dpia_batch_upload(h, P2, 10, None) == _lib.ERR_WORKSPACE
+    assert L.dpia_batch_run(h, P2, 10, None) == _lib.ERR_WORKSPACE
+    assert L.dpia_batch_run(None, P2, 1 << 20, None) == _lib.ERR_NULL
+    L.dpia_batch_plan_destroy(h)

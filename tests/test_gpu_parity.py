@@ -152,6 +152,8 @@ GEMV_STRATS = [
     dict(seq_len=32, local_size=256, order=T_, wg_combine=TREE, rows_per_wg=1),
     dict(seq_len=4, local_size=256, order=C_, wg_combine=TREE, rows_per_wg=1, row_parts=2),
     dict(seq_len=512, local_size=2, order=T_, wg_combine=TREE, rows_per_wg=8),
+    dict(seq_len=32, local_size=128, order=C_, wg_combine=TREE, rows_per_wg=2),   # LDS staged
+    dict(seq_len=16, local_size=64, order=C_, wg_combine=SEQ, rows_per_wg=1, row_parts=2),
 ]
 
 
@@ -327,3 +329,96 @@ def test_gemv_ragged_rows(kw, k):
     torch.cuda.synchronize()
     assert_same_bits(y.cpu().numpy(), S.gemv(np.ascontiguousarray(A[:, :k]), x[:k], to_plan(s)),
                      f"gemv k={k}")
+
+
+def _batch_instances(seed, count_red, count_gemv, max_log_n=14, max_mk=300):
+    """Seeded instances: dot or asum (coin) with log-uniform lengths, and
+    gemvs with uniform m, k; plus the strategy list they index."""
+    import torch
+    g = np.random.default_rng(seed)
+    strategies = [dp.Strategy(seq_len=16, local_size=256, order=T_),
+                  dp.Strategy(seq_len=4, local_size=64, order=C_, wg_combine=SEQ),
+                  dp.Strategy(seq_len=64, local_size=1024, order=T_),
+                  dp.Strategy(seq_len=8, local_size=16, order=C_),
+                  dp.Strategy(seq_len=20, local_size=16, order=T_, wg_combine=SEQ),
+                  dp.Strategy(seq_len=4, local_size=64, order=T_, row_parts=2)]
+    insts, host = [], []
+    for _ in range(count_red):
+        n = int(2 ** g.uniform(8, max_log_n))
+        op = dp.OP_DOT if g.random() < 0.5 else dp.OP_ASUM
+        si = int(g.integers(0, 5))
+        x = (g.standard_normal(n) * 2.0 ** g.uniform(-10, 10, n)).astype(np.float32)
+        y = synthetic.uniform_pm1(g, n)
+        d = {"op": op, "strategy": si, "x": torch.from_numpy(x).cuda(),
+             "out": torch.empty(1, device="cuda")}
+        if op == dp.OP_DOT:
+            d["y"] = torch.from_numpy(y).cuda()
+        insts.append(d)
+        host.append((op, si, x, y))
+    for _ in range(count_gemv):
+        m, k = int(g.integers(1, max_mk)), int(g.integers(1, max_mk))
+        si = int(g.choice([0, 1, 3, 5]))
+        s = strategies[si]
+        if k > s.seq_len * s.local_size * s.row_parts:
+            si = 0
+        lda = -(-k // 4) * 4
+        A = np.zeros((m, lda), np.float32)
+        A[:, :k] = synthetic.normal(g, (m, k))
+        x = synthetic.uniform_pm1(g, k)
+        At = torch.from_numpy(A).cuda()[:, :k]
+        insts.append({"op": dp.OP_GEMV, "strategy": si, "A": At, "x": torch.from_numpy(x).cuda(),
+                      "out": torch.empty(m, device="cuda")})
+        host.append((dp.OP_GEMV, si, np.ascontiguousarray(A[:, :k]), x))
+    return insts, host, strategies
+
+
+def test_batched_instances_equal_single_calls_and_the_oracle():
+    import torch
+    insts, host, strategies = _batch_instances(31, 150, 40)
+    plan = dp.BatchPlan(insts, strategies)
+    ws = plan.workspace()
+    plan.upload(ws)
+    plan.run(ws)
+    torch.cuda.synchronize()
+    for d, (op, si, a, b) in zip(insts, host):
+        s = strategies[si]
+        got = d["out"].cpu().numpy()
+        if op == dp.OP_GEMV:
+            single = dp.gemv(d["A"], d["x"], s).cpu().numpy()
+            want = S.gemv(a, b, to_plan(s))
+        elif op == dp.OP_DOT:
+            single = dp.dot(d["x"], d["y"], s).cpu().numpy()
+            want = np.atleast_1d(S.dot(a, b, to_plan(s)))
+        else:
+            single = dp.asum(d["x"], s).cpu().numpy()
+            want = np.atleast_1d(S.asum(a, to_plan(s)))
+        assert_same_bits(got, single, f"batched vs single op={op} s={si}")
+        assert_same_bits(got, want, f"batched vs oracle op={op} s={si}")
+
+
+def test_batched_run_in_a_graph_replays_exactly():
+    import torch
+    insts, host, strategies = _batch_instances(37, 60, 20)
+    plan = dp.BatchPlan(insts, strategies)
+    ws = plan.workspace()
+    plan.upload(ws)
+    plan.run(ws)
+    torch.cuda.synchronize()
+    eager = [d["out"].clone() for d in insts]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        for d in insts:
+            d["out"].fill_(-1.0)
+        with torch.cuda.graph(graph, stream=side):
+            plan.run(ws)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        for d in insts:
+            d["out"].fill_(float(rep) + 7.0)          # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for d, e in zip(insts, eager):
+            assert_same_bits(d["out"].cpu().numpy(), e.cpu().numpy(), f"replay {rep}")
