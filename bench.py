@@ -275,15 +275,22 @@ def workload_precision(args):
         prod = x.astype(np.float64) * y.astype(np.float64)
         sx = math.fsum(prod)
         sabs = math.fsum(np.abs(prod))
+        # exact sum of the binary32-rounded products: what a perfect
+        # accumulator of the kernel's products would return
+        s32 = math.fsum((x * y).astype(np.float64))
         kref = S.dot(x, y, to_plan(KAHAN_DOT))
         pref = S.dot(x, y, to_plan(plain))
         _line(workload="precision", op="dot_kahan",
               bit_exact_vs_oracle=bool(np.float64(kref).view(np.uint64) == np.float64(results["dot_kahan"]).view(np.uint64)),
               rel_err_vs_exact=abs(float(results["dot_kahan"]) - sx) / sabs,
               plain_rel_err_vs_exact=abs(float(results["dot_plain"]) - sx) / sabs,
+              accumulation_err=abs(float(results["dot_kahan"]) - s32) / sabs,
+              plain_accumulation_err=abs(float(results["dot_plain"]) - s32) / sabs,
               plain_bit_exact_vs_oracle=bool(np.float32(pref).view(np.uint32) == np.float32(results["dot_plain"]).view(np.uint32)),
               cpu_seconds=round(time.perf_counter() - t0, 1),
-              note="normwise: |computed - exact| / sum |x_i y_i|; exact = math.fsum of binary64 products")
+              note="normwise: |computed - exact| / sum |x_i y_i|; exact = math.fsum of binary64 "
+                   "products; accumulation_err uses the exact sum of the binary32-rounded "
+                   "products instead (rounding of the accumulation alone)")
 
 
 def batch_instances(seed: int, n_red: int = 4096, n_gemv: int = 512):
@@ -387,7 +394,8 @@ def workload_batch(args):
               gbs=_gbs(nbytes, us), pct_peak=round(100 * nbytes / us / 1e3 / PEAK_GBPS, 1),
               speedup_vs_per_instance_graph=round(rows["per_instance_graph"] / us, 2))
     _line(workload="batch", algorithmic_bytes=nbytes, batched_equals_per_instance_bitwise=bool(same),
-          strategies=[strategy_text(s) for s in strategies], size_classes=len(table),
+          strategies=[strategy_text(s) for s in strategies],
+          size_classes=len({row["class"] for row in table}), tuning_runs=len(table),
           tune_seconds=round(tune_s, 1), generate_seconds=round(gen_s, 1),
           note="one batched run = 2 launches; per-instance = one call per instance (2 kernels "
                "per reduction), the same strategies")

@@ -224,7 +224,7 @@ hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipS
 using namespace dpia;
 
 #ifndef DPIA_ROW_BLOCK
-#define DPIA_ROW_BLOCK 4
+#define DPIA_ROW_BLOCK 2
 #endif
 // Rows one team reduces at once for bf16 / fp8 matrices (1 = no blocking):
 // with narrow A elements the x operand, reloaded per row, would otherwise
