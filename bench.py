@@ -207,15 +207,18 @@ def workload_sweep(args):
               parity={"dot_all_24_bit_exact": bool(dot_ok), "gemv_all_24_bit_exact": bool(gemv_ok)})
 
 
-PRECISION_GEMV = dp.Strategy(seq_len=64, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE,
-                             rows_per_wg=1)
 KAHAN_DOT = dp.Strategy(seq_len=256, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
                         passes=2, accum=dp.KAHAN, final_f64=1)
 
 
+PRECISION_CANDIDATES = [(64, 256), (128, 128), (32, 512), (16, 1024), (8, 2048)]
+
+
 def workload_precision(args):
+    import dataclasses
     import torch
     import synthetic
+    from paper_1710_08332_amd import autotune as T
     from paper_1710_08332_amd.autotune import time_us
     seed = synthetic.SEEDS["precision"]
     m = k = 16384
@@ -223,8 +226,9 @@ def workload_precision(args):
     xvt = torch.from_numpy(xv).cuda()
     codes16 = synthetic.quantise_bf16(A)
     codes8, scale = synthetic.quantise_fp8_rows(A)
-    s = PRECISION_GEMV
-    results = {}
+    results, chosen = {}, {}
+    cands = [dp.Strategy(seq_len=C, local_size=L, order=dp.STRIDED, wg_combine=dp.TREE)
+             for C, L in PRECISION_CANDIDATES]
     for name, codes, dt, sc, nbytes in (
             ("gemv_f32", A, dp.F32, None, 4 * m * k + 4 * k + 4 * m),
             ("gemv_bf16", codes16.view(np.int16), dp.BF16, None, 2 * m * k + 4 * k + 4 * m),
@@ -232,12 +236,18 @@ def workload_precision(args):
         At = torch.from_numpy(np.ascontiguousarray(codes)).cuda()
         sct = torch.from_numpy(sc).cuda() if sc is not None else None
         y = torch.empty(m, device="cuda")
+        # the strategy for this format: autotuned over the candidate tilings
+        s, table = T.tune(cands, lambda st: (lambda: dp.gemv(At, xvt, st, y=y, row_scale=sct,
+                                                             a_dtype=dt)), reps=10)
+        chosen[name] = s
         med, p10, p90 = time_us(lambda: dp.gemv(At, xvt, s, y=y, row_scale=sct, a_dtype=dt),
                                 reps=args.steps)
         results[name] = y.cpu().numpy()
         _line(workload="precision", op=name, m=m, k=k, strategy=strategy_text(s, gemv=True),
               us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
-              pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1), algorithmic_bytes=nbytes)
+              pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1), algorithmic_bytes=nbytes,
+              tuned_over=[f"C={r['strategy']['seq_len']} L={r['strategy']['local_size']}: "
+                          f"{r['us']:.1f} us" for r in table])
         del At
     n = 1 << 28
     x, y = synthetic.kahan_dot_inputs(n, seed)
@@ -263,9 +273,10 @@ def workload_precision(args):
         t0 = time.perf_counter()
         ex = exact.gemv_exact(A, xv)
         absx = np.abs(A.astype(np.float64)) @ np.abs(xv.astype(np.float64))
-        p = to_plan(s)
-        ref = {"gemv_f32": S.gemv(A, xv, p), "gemv_bf16": S.gemv(codes16, xv, p, a_format="bf16"),
-               "gemv_fp8": S.gemv(codes8, xv, p, a_format="fp8", scale=scale)}
+        ref = {"gemv_f32": S.gemv(A, xv, to_plan(chosen["gemv_f32"])),
+               "gemv_bf16": S.gemv(codes16, xv, to_plan(chosen["gemv_bf16"]), a_format="bf16"),
+               "gemv_fp8": S.gemv(codes8, xv, to_plan(chosen["gemv_fp8"]), a_format="fp8",
+                                  scale=scale)}
         for name in ("gemv_f32", "gemv_bf16", "gemv_fp8"):
             got = results[name].astype(np.float64)
             _line(workload="precision", op=name, bit_exact_vs_oracle=bool(np.array_equal(
