@@ -187,10 +187,20 @@ __device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL],
 // consume the batch in increasing index order.  U * NV is kept near 16
 // elements per batch: a second, alternating batch was measured slower
 // (register pressure lowered occupancy).
-template <int NV>
+template <int NV, int E = DPIA_BATCH_ELEMS>
 struct Batch {
-  static constexpr int E = DPIA_BATCH_ELEMS;
   static constexpr int U = (E / NV) < 1 ? 1 : ((E / NV) > 16 ? 16 : (E / NV));
+};
+
+// Elements per lane group that one batch of loads covers: operations may
+// choose their own (Op::kBatchElems); the default is DPIA_BATCH_ELEMS.
+template <class Op, class = void>
+struct OpBatch {
+  static constexpr int E = DPIA_BATCH_ELEMS;
+};
+template <class Op>
+struct OpBatch<Op, decltype(void(Op::kBatchElems))> {
+  static constexpr int E = Op::kBatchElems;
 };
 
 // `limit` is the number of chunk elements that exist (W for a full chunk).
@@ -203,7 +213,7 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
                                            int limit,
                                            typename Op::T (&acc)[ORDER == kStrided ? NV : 1]) {
   using Term = typename Op::Term;
-  constexpr int U = Batch<NV>::U;
+  constexpr int U = Batch<NV, OpBatch<Op>::E>::U;
   constexpr int NL = (ORDER == kStrided) ? NV : 1;
 #pragma unroll
   for (int v = 0; v < NL; ++v) acc[v] = Op::Arith::zero();

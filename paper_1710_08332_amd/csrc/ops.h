@@ -145,6 +145,12 @@ struct GemvF32Acc {
   using Arith = PlainF32;
   using T = float;
   using Term = GTerm;
+  // Measured on MI355X for binary32 rows: larger load batches and cached
+  // loads of A stream faster than the dot's settings (16 elements,
+  // non-temporal); the narrow formats keep those (row-blocked kernel).
+  static constexpr bool kF32 = std::is_same<E, float>::value;
+  static constexpr int kBatchElems = kF32 ? 32 : 16;
+  static constexpr bool kStreamA = !kF32;
   struct View {
     static constexpr bool kStageable = std::is_same<E, float>::value;
     static constexpr int kOps = 2;
@@ -158,7 +164,7 @@ struct GemvF32Acc {
     __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
       E ca[NV];
       float fa[NV], b[NV];
-      vload<E, NV>(a + off, ca);
+      vload<E, NV, kStreamA>(a + off, ca);
       vload<float, NV, false>(x + off, b);   // x is reused by every row: cached
       Decode::template run<NV>(ca, fa);
 #pragma unroll
