@@ -28,6 +28,8 @@ Other workloads (one JSON line per measured item, not the headline):
                           strategies tuned per size class: per-instance
                           launches (eager, graph) against one batched run
                           (eager, graph)
+    --workload scal       scal y = alpha x, N = 2^26, under strided and
+                          contiguous strategies, out of place and in place
 Oracle work (parity, exact references) runs only in the CPU-baseline leg,
 which --no-cpu-baseline skips.
 """
@@ -433,6 +435,42 @@ def workload_batch(args):
               parity={"sample_bit_exact": bool(ok)})
 
 
+def workload_scal(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import time_us
+    n = 1 << 26
+    x, _ = synthetic.dot_inputs(n, synthetic.SEEDS["scale"])
+    alpha = np.float32(-1.3)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.empty_like(xt)
+    strategies = [dp.Strategy(seq_len=C, local_size=L, order=o)
+                  for C, L, o in ((16, 1024, dp.STRIDED), (64, 1024, dp.STRIDED),
+                                  (256, 1024, dp.STRIDED), (16, 256, dp.CONTIGUOUS),
+                                  (64, 256, dp.CONTIGUOUS))]
+    for s in strategies:
+        for place in ("out", "in"):
+            dst = yt if place == "out" else xt
+            med, p10, p90 = time_us(lambda: dp.scal(float(alpha), xt, s, y=dst), reps=40)
+            _line(workload="scal", n=n, strategy=strategy_text(s), place=place,
+                  us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2),
+                  gbs=_gbs(8 * n, med), pct_peak=round(100 * 8 * n / med / 1e3 / PEAK_GBPS, 1))
+    xt.copy_(torch.from_numpy(x))
+    dp.scal(float(alpha), xt, strategies[0], y=yt)
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        m = 1 << 22                                  # a 4 Mi-element prefix: ~1 s of oracle work
+        t0 = time.perf_counter()
+        want = S.scal(alpha, x[:m])
+        el = time.perf_counter() - t0
+        got = yt[:m].cpu().numpy()
+        _line(workload="scal", cpu_baseline={"kind": "oracle", "cores": 1, "sample": f"first {m} elements",
+                                             "gbs": _gbs(8 * m, el * 1e6)},
+              parity={"bit_exact_prefix": bool(np.array_equal(got.view(np.uint32),
+                                                              np.asarray(want, np.float32).view(np.uint32)))})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +478,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "small", "sweep", "precision", "batch"])
+                    choices=["scale", "small", "sweep", "precision", "batch", "scal"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -458,7 +496,7 @@ def main():
         sys.exit(1)
     if args.workload != "scale":
         {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision,
-         "batch": workload_batch}[args.workload](args)
+         "batch": workload_batch, "scal": workload_scal}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)

@@ -73,7 +73,7 @@ typedef enum {
   DPIA_FP8_E4M3 = 4        /* OCP fp8 E4M3 storage (max 448, no inf)         */
 } dpia_dtype;
 
-typedef enum { DPIA_OP_DOT = 0, DPIA_OP_ASUM = 1, DPIA_OP_GEMV = 2 } dpia_op;
+typedef enum { DPIA_OP_DOT = 0, DPIA_OP_ASUM = 1, DPIA_OP_GEMV = 2, DPIA_OP_SCAL = 3 } dpia_op;
 
 typedef enum {
   DPIA_ORDER_CONTIGUOUS = 0, /* ROWS ch = split C ch                          */
@@ -173,8 +173,10 @@ dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const vo
  * combine), R rows per work-group.
  *   a_dt       DPIA_F32, DPIA_BF16, DPIA_FP8_E4M3 (binary32 accumulation of
  *              decoded values) or DPIA_I32 (then x, y are I32 too)
- *   m, k, lda  A is m x k row-major with leading dimension lda >= k;
- *              k = seq_len * local_size * row_parts, m a multiple of R
+ *   m, k, lda  A is m x k row-major with leading dimension lda >= k (a
+ *              multiple of the strategy's vector width); m a multiple of R;
+ *              1 <= k <= seq_len * local_size * row_parts, shorter rows
+ *              being read as extended with zeros (which no plain fold sees)
  *   row_scale  FP8 only (else NULL): y[r] = row_scale[r] * (row r . x)
  *   x, y       k and m elements (binary32, or I32 with an I32 A)
  *   ws         unused (pass NULL, 0)
@@ -182,6 +184,29 @@ dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const vo
 dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
                       int64_t lda, const void* A, const float* row_scale, const void* x,
                       void* y, void* ws, size_t ws_bytes, dpia_stream_t stream);
+
+/*
+ * BLAS form y := alpha * (A x) + beta * y of the Sec. 7.1 gemv benchmark.
+ * Row r's value v is exactly dpia_gemv's (for FP8, row_scale[r] times the
+ * row reduction); then y[r] = (alpha * v) + (beta * y[r]) with each
+ * operation rounded once to binary32.  When beta == 0 (either sign) the old
+ * y is not read, so it need not hold numbers, and y[r] = alpha * v.
+ * Arguments as for dpia_gemv; a_dt is DPIA_F32, DPIA_BF16 or DPIA_FP8_E4M3
+ * (DPIA_ERR_DTYPE otherwise).  No workspace.
+ */
+dpia_status dpia_gemv_blas(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
+                           int64_t lda, float alpha, const void* A, const float* row_scale,
+                           const float* x, float beta, float* y, dpia_stream_t stream);
+
+/*
+ * y[i] = alpha * x[i] for i < n (the scal benchmark of Sec. 7.1; BLAS sscal
+ * when y == x).  A map: each element is one binary32 product, whatever the
+ * strategy, which only places elements on work-groups (chunks of W) and
+ * lanes (C elements each, contiguous or strided); wg_combine, passes and
+ * accum are ignored.  dt = DPIA_F32; x and y 16-byte aligned; y may equal x.
+ */
+dpia_status dpia_scal(const dpia_strategy* s, dpia_dtype dt, int64_t n, float alpha,
+                      const void* x, void* y, dpia_stream_t stream);
 
 /*
  * The two stages of a dot or asum strategy as separate calls.  dpia_chunks

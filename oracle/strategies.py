@@ -178,6 +178,14 @@ def asum_expr(n: int, plan: Plan) -> str:
     return _reduction(n, "xs", plan, ABS_ADD)
 
 
+def scal_expr() -> str:
+    """scal (Sec. 7.1 benchmark): every element times the scalar input
+    ``alpha``.  A map has no association to fix: whichever strategy places the
+    elements on work-groups and work-items, element i is ``alpha * xs[i]``
+    rounded once (the map law of Sec. 5.3), so the oracle is that map."""
+    return "(map (lam (e) (* alpha e)) xs)"
+
+
 def gemv_expr(m: int, k: int, plan: Plan, a_format: str = "f32") -> str:
     """y = A x under ``plan``; inputs ``A`` (m rows of k), ``x`` (k) and, for
     fp8, ``scale`` (m): row r is ``scale[r] * (row r of decoded A) . x``."""
@@ -212,6 +220,21 @@ def gemv_expr(m: int, k: int, plan: Plan, a_format: str = "f32") -> str:
     else:
         raise ValueError(f"bad a_format {a_format!r}")
     return f"(join (mapWorkgroup (lam (rows) {body}) (split {plan.rows} {src})))"
+
+
+def gemv_blas_expr(m: int, k: int, plan: Plan, a_format: str = "f32",
+                   beta_zero: bool = False) -> str:
+    """The BLAS form y := alpha * (A x) + beta * y of the gemv benchmark
+    (Sec. 7.1): a map over the rows' values zipped with the old ``y``, so
+    every element is ``(alpha * v) + (beta * y)`` with each operation rounded
+    once, where v is the row value of ``gemv_expr``.  When beta is zero the
+    old y is not an input at all (the BLAS convention: y need not hold
+    numbers then) and the element is ``alpha * v``."""
+    rows = gemv_expr(m, k, plan, a_format)
+    if beta_zero:
+        return f"(map (lam (v) (* alpha v)) {rows})"
+    return (f"(map (lam (p) (+ (* alpha (fst p)) (* beta (snd p)))) "
+            f"(zip {rows} yin))")
 
 
 # ------------------------------------------------------------------ running
@@ -254,6 +277,11 @@ def asum(xs: np.ndarray, plan: Plan, num: str = "f32"):
     return evaluate(asum_expr(n, plan), {"xs": _zero_extend(xs, n)}, num)
 
 
+def scal(alpha, xs: np.ndarray, num: str = "f32"):
+    return evaluate(scal_expr(), {"alpha": np.asarray(alpha, np.float32 if num == "f32" else None),
+                                  "xs": xs}, num)
+
+
 def gemv(A: np.ndarray, x: np.ndarray, plan: Plan, a_format: str = "f32",
          scale: np.ndarray = None, num: str = "f32"):
     k = plan.chunk * plan.row_parts
@@ -263,3 +291,20 @@ def gemv(A: np.ndarray, x: np.ndarray, plan: Plan, a_format: str = "f32",
     if a_format == "fp8":
         inputs["scale"] = scale
     return evaluate(gemv_expr(A.shape[0], k, plan, a_format), inputs, num)
+
+
+def gemv_blas(alpha, A: np.ndarray, x: np.ndarray, beta, y: np.ndarray, plan: Plan,
+              a_format: str = "f32", scale: np.ndarray = None, num: str = "f32"):
+    k = plan.chunk * plan.row_parts
+    if A.shape[1] > k:
+        raise ValueError(f"rows of {A.shape[1]} exceed W * row_parts = {k}")
+    ft = np.float32 if num == "f32" else None
+    beta_zero = float(beta) == 0.0
+    inputs = {"A": _zero_extend(A, k, axis=1), "x": _zero_extend(x, k),
+              "alpha": np.asarray(alpha, ft)}
+    if not beta_zero:
+        inputs["beta"] = np.asarray(beta, ft)
+        inputs["yin"] = y
+    if a_format == "fp8":
+        inputs["scale"] = scale
+    return evaluate(gemv_blas_expr(A.shape[0], k, plan, a_format, beta_zero), inputs, num)

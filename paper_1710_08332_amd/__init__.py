@@ -13,7 +13,7 @@ from dataclasses import dataclass, replace
 
 from . import _lib
 from ._lib import (BF16, CONTIGUOUS, F32, F64, FP8_E4M3, I32, KAHAN, OP_ASUM, OP_DOT,  # noqa: F401
-                   OP_GEMV, PLAIN, SEQ, STRIDED, TREE, DpiaError, last_error_detail)
+                   OP_GEMV, OP_SCAL, PLAIN, SEQ, STRIDED, TREE, DpiaError, last_error_detail)
 
 
 @dataclass(frozen=True)
@@ -146,6 +146,32 @@ def gemv(A, x, s: Strategy, y=None, row_scale=None, a_dtype=None, stream=None):
     _lib.check(_lib.lib().dpia_gemv(ctypes.byref(cs), adt, m, k, lda,
                                     ctypes.c_void_p(A.data_ptr()), sc, _dev(x), _dev(y),
                                     ctypes.c_void_p(0), 0, _stream(stream)), "dpia_gemv")
+    return y
+
+
+def gemv_blas(alpha: float, A, x, beta: float, y, s: Strategy, row_scale=None, a_dtype=None,
+              stream=None):
+    """y := alpha * (A x) + beta * y in place (y is not read when beta == 0).
+    ``A`` as for ``gemv`` (float32, bf16 or fp8 codes)."""
+    m, k = A.shape
+    adt = a_dtype if a_dtype is not None else _dtype_code(A)
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major")
+    cs = s.c()
+    sc = _dev(row_scale) if row_scale is not None else ctypes.c_void_p(0)
+    _lib.check(_lib.lib().dpia_gemv_blas(ctypes.byref(cs), adt, m, k, A.stride(0), float(alpha),
+                                         ctypes.c_void_p(A.data_ptr()), sc, _dev(x), float(beta),
+                                         _dev(y), _stream(stream)), "dpia_gemv_blas")
+    return y
+
+
+def scal(alpha: float, x, s: Strategy, y=None, stream=None):
+    """y = alpha * x (y may be x: in place)."""
+    if y is None:
+        y = _torch().empty_like(x)
+    cs = s.c()
+    _lib.check(_lib.lib().dpia_scal(ctypes.byref(cs), _dtype_code(x), x.numel(), float(alpha),
+                                    _dev(x), _dev(y), _stream(stream)), "dpia_scal")
     return y
 
 

@@ -17,13 +17,14 @@ OK, ERR_NULL, ERR_SHAPE, ERR_STRATEGY, ERR_DTYPE, ERR_WORKSPACE, ERR_HIP, ERR_AB
 # dpia_dtype
 F32, F64, I32, BF16, FP8_E4M3 = range(5)
 # dpia_op
-OP_DOT, OP_ASUM, OP_GEMV = range(3)
+OP_DOT, OP_ASUM, OP_GEMV, OP_SCAL = range(4)
 # dpia_order, dpia_combine, dpia_accum
 CONTIGUOUS, STRIDED = 0, 1
 TREE, SEQ = 0, 1
 PLAIN, KAHAN = 0, 1
 
-EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
+EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
+           "dpia_scal", "dpia_chunks",
            "dpia_fold", "dpia_batch_plan_create", "dpia_batch_workspace_bytes",
            "dpia_batch_upload", "dpia_batch_run", "dpia_batch_plan_destroy", "dpia_status_str",
            "dpia_last_error_detail", "dpia_abi_version")
@@ -65,6 +66,9 @@ def lib() -> ctypes.CDLL:
         L.dpia_dot.argtypes = [sp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int, vp, u64, vp]
         L.dpia_asum.argtypes = [sp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp, u64, vp]
         L.dpia_gemv.argtypes = [sp, ctypes.c_int, i64, i64, i64, vp, vp, vp, vp, vp, u64, vp]
+        L.dpia_scal.argtypes = [sp, ctypes.c_int, i64, ctypes.c_float, vp, vp, vp]
+        L.dpia_gemv_blas.argtypes = [sp, ctypes.c_int, i64, i64, i64, ctypes.c_float, vp, vp, vp,
+                                     ctypes.c_float, vp, vp]
         L.dpia_chunks.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, u64, vp]
         L.dpia_fold.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp]
         pp = ctypes.POINTER(ctypes.c_void_p)
@@ -76,8 +80,9 @@ def lib() -> ctypes.CDLL:
         L.dpia_batch_run.argtypes = [vp, vp, u64, vp]
         L.dpia_batch_plan_destroy.argtypes = [vp]
         L.dpia_batch_plan_destroy.restype = None
-        for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_chunks",
-                  "dpia_fold", "dpia_batch_plan_create", "dpia_batch_upload", "dpia_batch_run"):
+        for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
+                  "dpia_scal", "dpia_chunks", "dpia_fold", "dpia_batch_plan_create",
+                  "dpia_batch_upload", "dpia_batch_run"):
             getattr(L, f).restype = ctypes.c_int
         L.dpia_status_str.argtypes = [ctypes.c_int]
         L.dpia_status_str.restype = ctypes.c_char_p

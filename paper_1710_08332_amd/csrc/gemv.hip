@@ -231,12 +231,12 @@ using namespace dpia;
 // dominate the traffic through the vector caches.
 static constexpr int kRowBlock = DPIA_ROW_BLOCK;
 
-extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
-                                 int64_t lda, const void* A, const float* row_scale,
-                                 const void* x, void* y, void* ws, size_t ws_bytes,
-                                 dpia_stream_t stream) {
-  (void)ws;
-  (void)ws_bytes;
+namespace {
+
+// Shared body of dpia_gemv (blas = false) and dpia_gemv_blas.
+dpia_status gemv_impl(const char* name, const dpia_strategy* s, dpia_dtype a_dt, int64_t m,
+                      int64_t k, int64_t lda, const void* A, const float* row_scale, bool blas,
+                      float alpha, const void* x, float beta, void* y, dpia_stream_t stream) {
   Plan p;
   std::string detail;
   dpia_status st = make_plan(s, DPIA_OP_GEMV, a_dt, m, k, &p, &detail);
@@ -248,6 +248,8 @@ extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_
     return bad(DPIA_ERR_NULL, "an FP8 matrix needs row_scale");
   if (a_dt != DPIA_FP8_E4M3 && row_scale)
     return bad(DPIA_ERR_DTYPE, "row_scale applies to FP8 matrices only");
+  if (blas && a_dt == DPIA_I32)
+    return bad(DPIA_ERR_DTYPE, "the alpha / beta form takes F32, BF16 or FP8 matrices");
   if (m == 0) {
     clear_detail();
     return DPIA_OK;
@@ -257,23 +259,31 @@ extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_
     return bad(DPIA_ERR_SHAPE, "A and x must be 16-byte aligned");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipErrorInvalidValue;
+  auto with_epilogue = [&](auto op) {
+    op.blas = blas;
+    op.alpha = alpha;
+    op.beta = beta;
+    op.beta_zero = beta == 0.0f;
+    return op;
+  };
   switch (a_dt) {
     case DPIA_F32:
       e = launch_gemv<GemvF32, 4>(
-          p, GemvF32{static_cast<const float*>(A), static_cast<const float*>(x), nullptr,
-                     static_cast<float*>(y)},
+          p, with_epilogue(GemvF32{static_cast<const float*>(A), static_cast<const float*>(x),
+                                   nullptr, static_cast<float*>(y)}),
           m, lda, hs);
       break;
     case DPIA_BF16:
       e = launch_gemv<GemvBF16, 8>(
-          p, GemvBF16{static_cast<const uint16_t*>(A), static_cast<const float*>(x), nullptr,
-                      static_cast<float*>(y)},
+          p, with_epilogue(GemvBF16{static_cast<const uint16_t*>(A),
+                                    static_cast<const float*>(x), nullptr,
+                                    static_cast<float*>(y)}),
           m, lda, hs, kRowBlock);
       break;
     case DPIA_FP8_E4M3:
       e = launch_gemv<GemvFP8, 16>(
-          p, GemvFP8{static_cast<const uint8_t*>(A), static_cast<const float*>(x), row_scale,
-                     static_cast<float*>(y)},
+          p, with_epilogue(GemvFP8{static_cast<const uint8_t*>(A), static_cast<const float*>(x),
+                                   row_scale, static_cast<float*>(y)}),
           m, lda, hs, kRowBlock);
       break;
     case DPIA_I32:
@@ -285,7 +295,27 @@ extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_
     default:
       return bad(DPIA_ERR_DTYPE, "unsupported matrix type");
   }
-  if (e != hipSuccess) return hip_fail(e, "dpia_gemv launch");
+  if (e != hipSuccess) return hip_fail(e, name);
   clear_detail();
   return DPIA_OK;
+}
+
+}  // namespace
+
+extern "C" dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,
+                                 int64_t lda, const void* A, const float* row_scale,
+                                 const void* x, void* y, void* ws, size_t ws_bytes,
+                                 dpia_stream_t stream) {
+  (void)ws;
+  (void)ws_bytes;
+  return gemv_impl("dpia_gemv launch", s, a_dt, m, k, lda, A, row_scale, false, 1.0f, x, 0.0f,
+                   y, stream);
+}
+
+extern "C" dpia_status dpia_gemv_blas(const dpia_strategy* s, dpia_dtype a_dt, int64_t m,
+                                      int64_t k, int64_t lda, float alpha, const void* A,
+                                      const float* row_scale, const float* x, float beta,
+                                      float* y, dpia_stream_t stream) {
+  return gemv_impl("dpia_gemv_blas launch", s, a_dt, m, k, lda, A, row_scale, true, alpha, x,
+                   beta, y, stream);
 }

@@ -1,0 +1,106 @@
+// scal: y[i] = alpha * x[i] (the scal benchmark of Sec. 7.1), under the same
+// strategy descriptor as the reductions.  A map has no association: the
+// strategy only decides which work-group (chunk of W elements) and which
+// lane (its C elements, contiguous or strided) produces each element, and
+// every element is one binary32 product.  y may be x (in place): each
+// element is read and written by the same thread.
+#include "device.h"
+#include "host.h"
+#include "plan.h"
+
+namespace dpia {
+
+struct MapArgs {
+  int64_t n, W, items;
+  int L, C, team, teams_per_wg;
+};
+
+template <int NV>
+__device__ __forceinline__ void scal_vec(float alpha, const float* x, float* y,
+                                         int64_t off, int64_t limit) {
+  if (off + NV <= limit) {
+    float v[NV];
+    vload<float, NV>(x + off, v);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = alpha * v[i];
+    if constexpr (NV == 4) {
+      f32x4 w = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(y + off));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) y[off + i] = v[i];
+    }
+  } else {
+    for (int64_t i = off; i < limit && i < off + NV; ++i) y[i] = alpha * x[i];
+  }
+}
+
+template <int ORDER, int NV>
+__global__ void __launch_bounds__(1024) scal_kernel(float alpha, const float* x, float* y,
+                                                    MapArgs a) {
+  const int team_id = threadIdx.x / a.team;
+  const int t = threadIdx.x - team_id * a.team;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.items;
+       base += stride) {
+    const int64_t g = base + team_id;
+    if (g >= a.items) continue;       // no barriers in this kernel
+    const int64_t c0 = g * a.W;
+    const int64_t rest = a.n - c0;
+    const int64_t limit = c0 + (rest < a.W ? rest : a.W);
+    constexpr int U = 4;              // vectors in flight per thread
+    if constexpr (ORDER == kStrided) {
+      // lane l = t*NV + v maps elements l, l + L, ...
+      int k = 0;
+      for (; k + U <= a.C; k += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          scal_vec<NV>(alpha, x, y, c0 + static_cast<int64_t>(k + u) * a.L + t * NV, limit);
+      }
+      for (; k < a.C; ++k)
+        scal_vec<NV>(alpha, x, y, c0 + static_cast<int64_t>(k) * a.L + t * NV, limit);
+    } else {
+      // lane l = t maps elements l*C .. l*C + C-1
+      const int64_t s = c0 + static_cast<int64_t>(t) * a.C;
+      for (int k = 0; k < a.C; k += NV) scal_vec<NV>(alpha, x, y, s + k, limit);
+    }
+  }
+}
+
+}  // namespace dpia
+
+using namespace dpia;
+
+extern "C" dpia_status dpia_scal(const dpia_strategy* s, dpia_dtype dt, int64_t n, float alpha,
+                                 const void* x, void* y, dpia_stream_t stream) {
+  Plan p;
+  std::string detail;
+  dpia_status st = make_plan(s, DPIA_OP_SCAL, dt, 0, n, &p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  if (n > 0 && (!x || !y)) return bad(DPIA_ERR_NULL, "x and y must be non-NULL");
+  if (n > 0 && (!aligned16(x) || !aligned16(y)))
+    return bad(DPIA_ERR_SHAPE, "x and y must be 16-byte aligned");
+  if (p.items == 0) {
+    clear_detail();
+    return DPIA_OK;
+  }
+  MapArgs a{p.n, p.W, p.items, static_cast<int>(p.L), static_cast<int>(p.C), p.team,
+            p.teams_per_wg};
+  const int64_t grid = grid_size(p);
+  const float* xp = static_cast<const float*>(x);
+  float* yp = static_cast<float*>(y);
+  hipError_t e = with_order_combine(p.order, DPIA_COMBINE_TREE, [&](auto ord, auto) {
+    constexpr int ORDER = decltype(ord)::value;
+    return with_nv<4>(p.nv, [&](auto nvc) {
+      constexpr int NV = decltype(nvc)::value;
+      auto kern = scal_kernel<ORDER, NV>;
+      void* args[] = {&alpha, &xp, &yp, &a};
+      return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                             dim3(p.wg_threads), args, 0,
+                             reinterpret_cast<hipStream_t>(stream));
+    });
+  });
+  if (e != hipSuccess) return hip_fail(e, "dpia_scal launch");
+  clear_detail();
+  return DPIA_OK;
+}

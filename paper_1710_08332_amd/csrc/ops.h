@@ -195,11 +195,20 @@ struct GemvF32Acc {
   const float* x;
   const float* scale;   // fp8 only
   float* y;
+  // BLAS form y := alpha * v + beta * y (off: y := v).  With beta == 0 the
+  // old y is never read.
+  bool blas = false;
+  bool beta_zero = true;
+  float alpha = 1.0f, beta = 0.0f;
   __device__ View part(int64_t r, int p, int64_t lda, int W) const {
     return View{A + r * lda + static_cast<int64_t>(p) * W, x + static_cast<int64_t>(p) * W};
   }
   __device__ static T step(const Term& z, T acc) { return z.a * z.b + acc; }
-  __device__ void store(int64_t r, T v) const { y[r] = scale ? scale[r] * v : v; }
+  __device__ void store(int64_t r, T v) const {
+    float w = scale ? scale[r] * v : v;
+    if (blas) w = beta_zero ? alpha * w : alpha * w + beta * y[r];
+    y[r] = w;
+  }
 };
 
 struct DecodeF32 {

@@ -56,7 +56,7 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     os << "descriptor abi_version " << s->abi_version << " != library " << DPIA_ABI_VERSION;
     return fail(detail, DPIA_ERR_ABI, os.str());
   }
-  if (op != DPIA_OP_DOT && op != DPIA_OP_ASUM && op != DPIA_OP_GEMV)
+  if (op != DPIA_OP_DOT && op != DPIA_OP_ASUM && op != DPIA_OP_GEMV && op != DPIA_OP_SCAL)
     return fail(detail, DPIA_ERR_STRATEGY, "unknown operation");
   if (s->seq_len < 1 || s->local_size < 1)
     return fail(detail, DPIA_ERR_STRATEGY, "seq_len and local_size must be >= 1");
@@ -81,6 +81,10 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
       return fail(detail, DPIA_ERR_DTYPE, "dot takes F32 or I32 vectors");
     if (s->accum == DPIA_ACCUM_KAHAN && dt != DPIA_F32)
       return fail(detail, DPIA_ERR_DTYPE, "Kahan accumulation is defined for F32 only");
+  } else if (op == DPIA_OP_SCAL) {
+    if (dt != DPIA_F32) return fail(detail, DPIA_ERR_DTYPE, "scal takes F32 vectors");
+    if (s->accum != DPIA_ACCUM_PLAIN)
+      return fail(detail, DPIA_ERR_STRATEGY, "scal has no accumulation");
   } else if (op == DPIA_OP_ASUM) {
     if (dt != DPIA_F32) return fail(detail, DPIA_ERR_DTYPE, "asum takes F32 vectors");
     if (s->accum != DPIA_ACCUM_PLAIN)
@@ -188,18 +192,25 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     lds = q.stage_off + static_cast<size_t>(q.teams_per_wg) * stage_floats(static_cast<int>(q.L)) *
                             sizeof(float);
   }
-  if (op != DPIA_OP_GEMV) {
+  if (op == DPIA_OP_SCAL) {
+    lds = 0;                 // a map: no combine, no fold, no staging
+    q.stage = false;
+  }
+  if (op == DPIA_OP_DOT || op == DPIA_OP_ASUM) {
     size_t fold = static_cast<size_t>(kFoldBlock) * q.acc_bytes;
     if (fold > lds) lds = fold;
   }
   lds = round_up(lds + 16, 16);
-  if (lds > 64 * 1024) {
-    os << "strategy needs " << lds << " bytes of LDS per work-group (> 65536)";
+#ifndef DPIA_LDS_CAP
+#define DPIA_LDS_CAP (64 * 1024)
+#endif
+  if (lds > DPIA_LDS_CAP) {
+    os << "strategy needs " << lds << " bytes of LDS per work-group (> " << DPIA_LDS_CAP << ")";
     return fail(detail, DPIA_ERR_STRATEGY, os.str());
   }
   q.lds_bytes = lds;
 
-  if (op == DPIA_OP_GEMV) {
+  if (op == DPIA_OP_GEMV || op == DPIA_OP_SCAL) {
     q.partial_bytes = 0;
     q.ws_bytes = 0;
   } else {

@@ -18,7 +18,10 @@ constexpr int kFoldBlock = 2048;
 constexpr size_t kWsAlign = 256;
 // LDS staging of the contiguous order: elements per lane per tile, and the
 // LDS row stride in floats (80 bytes: an odd number of 16-byte units).
-constexpr int kStage = 16;
+#ifndef DPIA_STAGE
+#define DPIA_STAGE 16
+#endif
+constexpr int kStage = DPIA_STAGE;
 constexpr int kStageRow = kStage + 4;
 // LDS floats one team needs for staging: two operands x L rows.
 constexpr int stage_floats(int L) { return 2 * L * kStageRow; }

@@ -217,3 +217,26 @@ def test_batch_plan_validation_is_host_only():
     assert L.dpia_batch_run(h, P2, 10, None) == _lib.ERR_WORKSPACE
     assert L.dpia_batch_run(None, P2, 1 << 20, None) == _lib.ERR_NULL
     L.dpia_batch_plan_destroy(h)
+
+
+def test_scal_validates_before_launching():
+    L = _lib.lib()
+    cs = dp.Strategy(seq_len=16, local_size=256, order=dp.STRIDED).c()
+    assert L.dpia_scal(ctypes.byref(cs), dp.I32, 4096, 2.0, P, P2, None) == _lib.ERR_DTYPE
+    assert L.dpia_scal(ctypes.byref(cs), dp.F32, 4096, 2.0, None, P2, None) == _lib.ERR_NULL
+    assert L.dpia_scal(ctypes.byref(cs), dp.F32, 4096, 2.0, ctypes.c_void_p(0x7000_0004), P2,
+                       None) == _lib.ERR_SHAPE
+    assert L.dpia_scal(ctypes.byref(cs), dp.F32, 0, 2.0, None, None, None) == _lib.OK
+    ks = dp.Strategy(seq_len=16, local_size=256, accum=dp.KAHAN).c()
+    assert L.dpia_scal(ctypes.byref(ks), dp.F32, 4096, 2.0, P, P2, None) == _lib.ERR_STRATEGY
+
+
+def test_gemv_blas_validates_before_launching():
+    L = _lib.lib()
+    cs = dp.Strategy(seq_len=16, local_size=16).c()
+    args = (256, 256, 1.0, P, None, P2, 0.5, P2, None)
+    assert L.dpia_gemv_blas(ctypes.byref(cs), dp.I32, 4, *args) == _lib.ERR_DTYPE
+    assert L.dpia_gemv_blas(ctypes.byref(cs), dp.FP8_E4M3, 4, *args) == _lib.ERR_NULL
+    assert L.dpia_gemv_blas(ctypes.byref(cs), dp.F32, 4, 256, 255, 1.0, P, None, P2, 0.5, P2,
+                            None) == _lib.ERR_SHAPE
+    assert L.dpia_gemv_blas(ctypes.byref(cs), dp.F32, 0, *args) == _lib.OK

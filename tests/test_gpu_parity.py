@@ -422,3 +422,57 @@ def test_batched_run_in_a_graph_replays_exactly():
         torch.cuda.synchronize()
         for d, e in zip(insts, eager):
             assert_same_bits(d["out"].cpu().numpy(), e.cpu().numpy(), f"replay {rep}")
+
+
+
+@pytest.mark.parametrize("kw", [dict(seq_len=16, local_size=256, order=T_),
+                                dict(seq_len=64, local_size=64, order=C_),
+                                dict(seq_len=3, local_size=5, order=T_),
+                                dict(seq_len=1, local_size=1, order=C_)], ids=str)
+@pytest.mark.parametrize("n", [1, 1000, 4097, (1 << 20) + 3])
+def test_scal_bit_exact_and_in_place(kw, n):
+    import torch
+    s = dp.Strategy(**kw)
+    g = np.random.default_rng(41)
+    x = (g.standard_normal(n) * 2.0 ** g.uniform(-30, 30, n)).astype(np.float32)
+    a = np.float32(-1.3)
+    xt = torch.from_numpy(x).cuda()
+    y = dp.scal(float(a), xt, s)
+    torch.cuda.synchronize()
+    want = S.scal(a, x)
+    assert_same_bits(y.cpu().numpy(), want, "scal")
+    dp.scal(float(a), xt, s, y=xt)          # in place
+    torch.cuda.synchronize()
+    assert_same_bits(xt.cpu().numpy(), want, "scal in place")
+
+
+@pytest.mark.parametrize("kw", [GEMV_STRATS[0], GEMV_STRATS[2], GEMV_STRATS[5]],
+                         ids=lambda k: "-".join(f"{a[:3]}{b}" for a, b in k.items()))
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (-0.75, 0.0), (1.3, -2.1), (0.5, 1.0)])
+def test_gemv_blas_bit_exact(kw, fmt, alpha, beta):
+    import torch
+    s = dp.Strategy(**kw)
+    plan = to_plan(s)
+    k = s.seq_len * s.local_size * s.row_parts - 3            # ragged rows too
+    m = s.rows_per_wg * 11
+    A, x = synthetic.gemv_inputs(m, k, synthetic.SEEDS["scale"])
+    y0 = np.random.default_rng(12).standard_normal(m).astype(np.float32)
+    scale = None
+    if fmt == "f32":
+        src, adt = A, dp.F32
+    elif fmt == "bf16":
+        src, adt = synthetic.quantise_bf16(A), dp.BF16
+    else:
+        (src, scale), adt = synthetic.quantise_fp8_rows(A), dp.FP8_E4M3
+    lda = -(-k // 16) * 16
+    Ap = np.zeros((m, lda), src.dtype)
+    Ap[:, :k] = src
+    At = torch.from_numpy(Ap.view(np.int16) if Ap.dtype == np.uint16 else Ap).cuda()[:, :k]
+    # beta == 0: the old y is never read, so NaN there must not show
+    yt = torch.from_numpy(y0 if beta != 0 else np.full(m, np.nan, np.float32)).cuda()
+    st = torch.from_numpy(scale).cuda() if scale is not None else None
+    dp.gemv_blas(alpha, At, torch.from_numpy(x).cuda(), beta, yt, s, row_scale=st, a_dtype=adt)
+    torch.cuda.synchronize()
+    want = S.gemv_blas(alpha, src, x, beta, y0, plan, a_format=fmt, scale=scale)
+    assert_same_bits(yt.cpu().numpy(), want, f"gemv_blas {fmt}")

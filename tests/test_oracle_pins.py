@@ -682,3 +682,52 @@ def test_zero_extension_is_invisible_to_plain_folds():
     assert np.float32(S.dot(x, y, S.Plan(seq=4, lanes=4))).view(np.uint32) == 0
     with pytest.raises(ValueError):
         S.dot(np.ones(10, np.float32), np.ones(10, np.float32), S.Plan(seq=4, lanes=4, accum="kahan"))
+
+
+def test_scal_is_one_rounded_product_per_element():
+    # scal maps alpha * x over the vector: each element is one binary32
+    # product (numpy's own binary32 multiply), for both evaluators
+    g = np.random.default_rng(36)
+    x = (g.standard_normal(500) * 2.0 ** g.uniform(-30, 30, 500)).astype(np.float32)
+    a = np.float32(1.7)
+    assert same_bits(S.scal(a, x), a * x)
+    assert same_bits(eval_scalar.evaluate(S.scal_expr(), {"alpha": a, "xs": x[:50]}), a * x[:50])
+    assert same_bits(S.scal(np.float32(1), x), x)
+    assert same_bits(S.scal(np.float32(-2), x), np.float32(-2) * x)
+
+
+def test_blas_gemv_reduces_to_gemv_and_to_exact_integers():
+    # y := alpha A x + beta y.  (1) alpha = 1, beta = 0 is the plain gemv
+    # (1 * v = v exactly).  (2) alpha = -2 scales exactly (power of two, no
+    # overflow).  (3) With small integers every product and sum is exactly
+    # representable, so the result equals the integer arithmetic.  (4) beta = 0
+    # never reads y: NaN in y does not reach the result.
+    g = np.random.default_rng(37)
+    m, k = 8, 96
+    p = S.Plan(seq=3, lanes=16, rows=2, row_parts=2)
+    A = g.standard_normal((m, k)).astype(np.float32)
+    x = g.standard_normal(k).astype(np.float32)
+    y0 = g.standard_normal(m).astype(np.float32)
+    plain = S.gemv(A, x, p)
+    assert same_bits(S.gemv_blas(1.0, A, x, 0.0, y0, p), plain)
+    assert same_bits(S.gemv_blas(-2.0, A, x, 0.0, y0, p), np.float32(-2) * plain)
+    nan_y = np.full(m, np.nan, np.float32)
+    assert same_bits(S.gemv_blas(1.5, A, x, 0.0, nan_y, p), S.gemv_blas(1.5, A, x, 0.0, y0, p))
+    Ai = g.integers(-8, 9, (m, k))
+    xi = g.integers(-8, 9, k)
+    yi = g.integers(-100, 101, m)
+    want = 3 * (Ai @ xi) - 5 * yi
+    got = S.gemv_blas(3.0, Ai.astype(np.float32), xi.astype(np.float32), -5.0,
+                      yi.astype(np.float32), p)
+    assert np.array_equal(np.asarray(got, np.float64), want.astype(np.float64))
+    # both evaluators, fp8 rows: alpha * (scale * rowsum) + beta * y
+    codes8 = g.integers(0, 256, (m, k)).astype(np.uint8)
+    codes8[(codes8 & 0x7F) == 0x7F] = 0x38
+    scale = g.random(m, dtype=np.float32) + np.float32(0.5)
+    r8 = S.gemv(codes8, x, p, a_format="fp8", scale=scale)
+    a, b = np.float32(0.7), np.float32(-1.3)
+    y8 = S.gemv_blas(a, codes8, x, b, y0, p, a_format="fp8", scale=scale)
+    assert same_bits(y8, (a * r8) + (b * y0))
+    e = S.gemv_blas_expr(m, k, p, "fp8")
+    assert same_bits(eval_scalar.evaluate(e, {"A": codes8, "x": x, "scale": scale, "alpha": a,
+                                              "beta": b, "yin": y0}), y8)
