@@ -23,6 +23,15 @@ Primitives and arities (``F`` marks a function argument):
     Sec. 6.1: mapGlobal, mapWorkgroup, mapLocal, mapSeq (same type as map)
               reduceSeq (same type as reduce; sequential by definition)
               toGlobal F, toLocal F, toPrivate F (wrap a function)
+    Sec. 6.1 vector types:
+              asVector n e   m*n.num -> m.num<n> (a split whose rows are
+                             vectors: element i is elements i*n .. i*n+n-1)
+              asScalar n e   m.num<n> -> m*n.num (element i is component
+                             i mod n of vector i div n)
+              Arithmetic and abs on two vectors of one type act on each
+              component.  ``broadcast n a`` is the vector of n copies of the
+              number a: the vector zero that a vector accumulator starts
+              from, which the paper writes as 0 (OpenCL's (float4)(0)).
     Extensions that the paper's dot/asum/gemv benchmarks need but Fig. 5a
     does not define (each one is a plain total function):
               abs a          absolute value (asum, Sec. 7.1 benchmark list)
@@ -45,7 +54,11 @@ PRIMS = {
     "+": 2, "-": 2, "*": 2, "/": 2, "negate": 1, "abs": 1,
     "toGlobal": 1, "toLocal": 1, "toPrivate": 1,
     "f32": 1, "f64": 1, "bf16": 1, "fp8": 1,
+    "asVector": 2, "asScalar": 2, "broadcast": 2,
 }
+
+# primitives whose first argument is a literal size
+SIZED = ("split", "asVector", "asScalar", "broadcast")
 
 MAP_LIKE = ("map", "mapGlobal", "mapWorkgroup", "mapLocal", "mapSeq")
 REDUCE_LIKE = ("reduce", "reduceSeq")
@@ -161,8 +174,8 @@ def parse(text: str) -> Expr:
             pos += 1
             if len(args) != PRIMS[head]:
                 raise ParseError(f"{head} takes {PRIMS[head]} arguments, got {len(args)}")
-            if head == "split" and not isinstance(args[0], Lit):
-                raise ParseError("split needs a literal row length")
+            if head in SIZED and not isinstance(args[0], Lit):
+                raise ParseError(f"{head} needs a literal size")
             return Prim(head, tuple(args))
         fn = expr()
         args = []

@@ -65,6 +65,13 @@ class Num:
 
 
 @dataclass(frozen=True)
+class Vec:
+    """num<n>: n numbers of one format (Sec. 6.1 vector type)."""
+    n: int
+    dt: np.dtype
+
+
+@dataclass(frozen=True)
 class Arr:
     n: int
     elem: "Ty"
@@ -76,7 +83,7 @@ class Tup:
     b: "Ty"
 
 
-Ty = Union[Num, Arr, Tup]
+Ty = Union[Num, Vec, Arr, Tup]
 
 
 def type_of_array(a: np.ndarray) -> Ty:
@@ -94,8 +101,9 @@ class EvalError(ValueError):
 # A data value at batch rank ``nb`` holds, for every leaf number of its type,
 # an ndarray whose first ``nb`` axes are the batch axes (size 1 where the
 # value does not vary along that enclosing map) followed by one axis per
-# array level of the type, outermost first.  Pairs hold a tuple of the two
-# component representations; an array of pairs is therefore a pair of arrays.
+# array level of the type, outermost first, and, for a vector, one last axis
+# of its n components.  Pairs hold a tuple of the two component
+# representations; an array of pairs is therefore a pair of arrays.
 
 @dataclass
 class Data:
@@ -264,10 +272,38 @@ class _Evaluator:
             k = 0 if name == "fst" else 1
             return Data(p.ty.a if k == 0 else p.ty.b, p.rep[k])
 
+        if name == "asVector":
+            n = int(args[0].text)
+            v = self.data(args[1], env, nb)
+            if not (isinstance(v.ty, Arr) and isinstance(v.ty.elem, Num)) or n <= 0 \
+                    or v.ty.n % n:
+                raise EvalError(f"asVector {n} of {v.ty}")
+            m = v.ty.n // n
+            return Data(Arr(m, Vec(n, v.ty.elem.dt)),
+                        v.rep.reshape(v.rep.shape[:nb] + (m, n)))
+
+        if name == "asScalar":
+            n = int(args[0].text)
+            v = self.data(args[1], env, nb)
+            if not (isinstance(v.ty, Arr) and isinstance(v.ty.elem, Vec)) or v.ty.elem.n != n:
+                raise EvalError(f"asScalar {n} of {v.ty}")
+            m = v.ty.n
+            return Data(Arr(m * n, Num(v.ty.elem.dt)),
+                        v.rep.reshape(v.rep.shape[:nb] + (m * n,)))
+
+        if name == "broadcast":
+            n = int(args[0].text)
+            a = self.data(args[1], env, nb)
+            if not isinstance(a.ty, Num) or n <= 0:
+                raise EvalError(f"broadcast {n} of {a.ty}")
+            return Data(Vec(n, a.ty.dt),
+                        np.array(np.broadcast_to(a.rep[..., None], a.rep.shape + (n,))))
+
         if name in ("+", "-", "*", "/"):
             a = self.data(args[0], env, nb)
             b = self.data(args[1], env, nb)
-            if not (isinstance(a.ty, Num) and a.ty == b.ty):
+            # numbers of one format, or vectors of one type (per component)
+            if not (isinstance(a.ty, (Num, Vec)) and a.ty == b.ty):
                 raise EvalError(f"{name} on {a.ty} and {b.ty}")
             if a.ty.dt.kind not in "fu" or a.ty.dt.itemsize < 4:
                 raise EvalError(f"no arithmetic on storage codes ({a.ty.dt})")
@@ -280,6 +316,11 @@ class _Evaluator:
 
         if name in ("negate", "abs", "f32", "f64", "bf16", "fp8"):
             a = self.data(args[0], env, nb)
+            if isinstance(a.ty, Vec) and name in ("negate", "abs"):
+                if a.ty.dt.kind != "f":
+                    raise EvalError(f"{name} is defined on floating point only")
+                op = np.negative if name == "negate" else np.abs
+                return Data(a.ty, np.asarray(op(a.rep)))
             if not isinstance(a.ty, Num):
                 raise EvalError(f"{name} of a non-number")
             dt = a.ty.dt

@@ -106,6 +106,8 @@ def _to_value(a: np.ndarray):
 
 
 def _from_value(v):
+    if isinstance(v, Vc):
+        return np.array([_from_value(x) for x in v])
     if isinstance(v, tuple):
         return tuple(_from_value(x) for x in v)
     if isinstance(v, list):
@@ -113,6 +115,20 @@ def _from_value(v):
     dt = {"f32": np.float32, "f64": np.float64, "u32": np.uint32,
           "u16": np.uint16, "u8": np.uint8}[v.fmt]
     return np.array(v.v, dtype=dt)
+
+
+class Vc(tuple):
+    """A vector value num<n>: a tuple of n numbers of one format."""
+
+
+def _vec_arith(name, a, b):
+    if isinstance(a, Vc) and isinstance(b, Vc):
+        if len(a) != len(b):
+            raise ValueError("vectors of different lengths")
+        return Vc(_arith(name, a[i], b[i]) for i in range(len(a)))
+    if isinstance(a, Vc) or isinstance(b, Vc):
+        raise ValueError(f"{name} of a vector and a number")
+    return _arith(name, a, b)
 
 
 class _Fn:
@@ -180,9 +196,29 @@ def _eval(e, env, num: str):
         return _eval(args[0], env, num)[0]
     if name == "snd":
         return _eval(args[0], env, num)[1]
+    if name == "asVector":
+        n = int(args[0].text)
+        v = _eval(args[1], env, num)
+        if n <= 0 or len(v) % n:
+            raise ValueError("asVector does not divide")
+        return [Vc(v[r * n:(r + 1) * n]) for r in range(len(v) // n)]
+    if name == "asScalar":
+        n = int(args[0].text)
+        out = []
+        for vec in _eval(args[1], env, num):
+            if not isinstance(vec, Vc) or len(vec) != n:
+                raise ValueError("asScalar of a non-vector")
+            out.extend(vec)
+        return out
+    if name == "broadcast":
+        n = int(args[0].text)
+        a = _eval(args[1], env, num)
+        return Vc([a] * n)
     if name in ("+", "-", "*", "/"):
-        return _arith(name, _eval(args[0], env, num), _eval(args[1], env, num))
+        return _vec_arith(name, _eval(args[0], env, num), _eval(args[1], env, num))
     a = _eval(args[0], env, num)
+    if isinstance(a, Vc) and name in ("negate", "abs"):
+        return Vc(N(c.fmt, -c.v if name == "negate" else abs(c.v)) for c in a)
     if name == "negate":
         return N(a.fmt, -a.v)
     if name == "abs":

@@ -42,6 +42,19 @@ strategy as a dot product of that row with x.  With two row parts, each half
 row is reduced on its own and the two halves are folded by
 ``reduceSeq add 0``.
 
+Vector strategies (Sec. 6.1 vectorisation; the dot expression of Sec. 6.2 is
+one): with vector width V > 1 the inputs are read through ``asVector V``, so
+the strategy works on vectors of V consecutive elements.  Each work-item
+keeps a vector accumulator (from ``broadcast V 0``) and every operation acts
+on each component, so component j of a lane folds elements j, j+V, ... of
+the lane's vectors.  The combine acts per component too; ``asScalar V``
+turns the chunks' vector values back into V numbers each, in component
+order, before the outer fold.  The Sec. 6.2 expression has no work-group
+combine at all: every work-item's value is written out.  Combine "none" is
+that form: the chunk's value is its L lane values (join of the mapLocal), so
+the outer fold runs over G*L (times V) numbers in chunk, lane, component
+order.
+
 The compensated ("kahan") variant keeps a pair (s, c) per accumulator:
 Kahan's summation step (N. J. Higham, Accuracy and Stability of Numerical
 Algorithms, 2nd ed., Alg. 4.2) inside the lanes, Knuth's TwoSum to merge two
@@ -87,6 +100,9 @@ class Plan:
     final_f64      kahan only: fold the chunk results in binary64
     rows (R)       gemv: rows per work-group
     row_parts      gemv: 1, or 2 halves reduced separately
+    vec (V)        dot / asum: vector width of the asVector view (1: none)
+
+    With vec = V the chunk holds L*C vectors, i.e. V*L*C numbers.
     """
     seq: int
     lanes: int
@@ -96,17 +112,19 @@ class Plan:
     final_f64: bool = False
     rows: int = 1
     row_parts: int = 1
+    vec: int = 1
 
     @property
     def chunk(self) -> int:
-        return self.seq * self.lanes
+        """Numbers per chunk."""
+        return self.seq * self.lanes * self.vec
 
     def check(self):
         if self.seq < 1 or self.lanes < 1:
             raise ValueError("seq and lanes must be positive")
         if self.order not in ("contiguous", "strided"):
             raise ValueError(f"bad order {self.order!r}")
-        if self.combine not in ("tree", "seq"):
+        if self.combine not in ("tree", "seq", "none"):
             raise ValueError(f"bad combine {self.combine!r}")
         if self.combine == "tree" and self.lanes & (self.lanes - 1):
             raise ValueError("a tree combine needs a power-of-two lane count")
@@ -114,6 +132,10 @@ class Plan:
             raise ValueError(f"bad accum {self.accum!r}")
         if self.row_parts not in (1, 2):
             raise ValueError("row_parts must be 1 or 2")
+        if self.vec < 1:
+            raise ValueError("vec must be positive")
+        if (self.vec > 1 or self.combine == "none") and self.accum != "plain":
+            raise ValueError("vector and uncombined strategies are defined for plain accumulation")
 
 
 def _rows_of(view: str, plan: Plan) -> str:
@@ -142,6 +164,8 @@ def _combine(lanes: str, plan: Plan, merge: str, init: str) -> str:
 
 
 def _chunk_value(view: str, plan: Plan, step: str) -> str:
+    if plan.combine == "none":
+        raise ValueError("an uncombined chunk has L values, not one")
     if plan.accum == "kahan":
         return _combine(_lanes(view, plan, step, ZERO_PAIR), plan, KAHAN_MERGE, ZERO_PAIR)
     return _combine(_lanes(view, plan, step, "0"), plan, ADD, "0")
@@ -160,22 +184,38 @@ def _reduction(n: int, view: str, plan: Plan, step: str) -> str:
     plan.check()
     if n % plan.chunk:
         raise ValueError(f"n={n} is not a multiple of the chunk {plan.chunk}")
-    partials = (f"(mapWorkgroup (lam (ch) {_chunk_value('ch', plan, step)})"
-                f" (split {plan.chunk} {view}))")
+    V = plan.vec
+    w = plan.seq * plan.lanes                    # elements (vectors if V > 1) per chunk
+    zero = "0" if V == 1 else f"(broadcast {V} 0)"
+    if plan.combine == "none":
+        body = _lanes("ch", plan, step, zero)
+        partials = f"(join (mapWorkgroup (lam (ch) {body}) (split {w} {view})))"
+    elif V == 1:
+        body = _chunk_value("ch", plan, step)
+        partials = f"(mapWorkgroup (lam (ch) {body}) (split {w} {view}))"
+    else:
+        body = _combine(_lanes("ch", plan, step, zero), plan, ADD, zero)
+        partials = f"(mapWorkgroup (lam (ch) {body}) (split {w} {view}))"
+    if V > 1:
+        partials = f"(asScalar {V} {partials})"
     return _final(partials, plan)
+
+
+def _vectors(name: str, plan: Plan) -> str:
+    return name if plan.vec == 1 else f"(asVector {plan.vec} {name})"
 
 
 def dot_expr(n: int, plan: Plan) -> str:
     """dot xs ys under ``plan``; inputs ``xs``, ``ys`` of length n."""
     step = KAHAN_MUL_STEP if plan.accum == "kahan" else MUL_ADD
-    return _reduction(n, "(zip xs ys)", plan, step)
+    return _reduction(n, f"(zip {_vectors('xs', plan)} {_vectors('ys', plan)})", plan, step)
 
 
 def asum_expr(n: int, plan: Plan) -> str:
     """sum of |xs[i]| under ``plan``; input ``xs`` of length n."""
     if plan.accum != "plain":
         raise ValueError("asum is defined for plain accumulation only")
-    return _reduction(n, "xs", plan, ABS_ADD)
+    return _reduction(n, _vectors("xs", plan), plan, ABS_ADD)
 
 
 def scal_expr() -> str:
@@ -192,6 +232,8 @@ def gemv_expr(m: int, k: int, plan: Plan, a_format: str = "f32") -> str:
     plan.check()
     if plan.accum != "plain":
         raise ValueError("gemv is defined for plain accumulation only")
+    if plan.vec != 1 or plan.combine == "none":
+        raise ValueError("gemv rows use scalar, combined strategies")
     if m % plan.rows:
         raise ValueError(f"m={m} is not a multiple of rows={plan.rows}")
     part = k // plan.row_parts

@@ -731,3 +731,124 @@ def test_blas_gemv_reduces_to_gemv_and_to_exact_integers():
     e = S.gemv_blas_expr(m, k, p, "fp8")
     assert same_bits(eval_scalar.evaluate(e, {"A": codes8, "x": x, "scale": scale, "alpha": a,
                                               "beta": b, "yin": y0}), y8)
+
+
+# ----------------------------------------------------------- vector strategies
+
+@pytest.mark.parametrize("ev", EVALS)
+def test_as_vector_and_as_scalar_move_indices_only(ev):
+    # asVector n: vector i holds elements i*n .. i*n+n-1; asScalar n: element
+    # i is component i mod n of vector i div n; one undoes the other.
+    x = np.arange(24, dtype=np.float32) * np.float32(0.5)
+    v = ev("(map (lam (q) q) (asVector 4 xs))", {"xs": x})
+    assert np.array_equal(np.asarray(v), x.reshape(6, 4))
+    assert same_bits(ev("(asScalar 4 (asVector 4 xs))", {"xs": x}), x)
+    assert same_bits(ev("(asScalar 3 (map (lam (q) (+ q q)) (asVector 3 xs)))", {"xs": x}), x + x)
+    b = ev("(broadcast 5 (* a a))", {"a": np.float32(3)})
+    assert same_bits(b, np.full(5, 9, np.float32))
+    with pytest.raises(ValueError):
+        ev("(asVector 5 xs)", {"xs": x})
+    with pytest.raises(ValueError):       # a vector plus a number is not defined
+        ev("(map (lam (q) (+ q 1)) (asVector 4 xs))", {"xs": x})
+
+
+def _loops_vector_dot(xs, ys, V, L, C, order, combine):
+    """The vector strategy as plain loops over binary32 numpy scalars: lane l
+    of chunk g keeps V component sums; component j of step k reads vector
+    g*L*C + l*C + k (contiguous) or g*L*C + k*L + l (strided), element
+    V*vector + j.  combine "none" writes every lane's components out;
+    "seq" folds lanes 0..L-1 per component.  Then one fold over the list."""
+    G = len(xs) // (V * L * C)
+    out = []
+    for g in range(G):
+        lanes = []
+        for l in range(L):
+            acc = [np.float32(0)] * V
+            for k in range(C):
+                vi = g * L * C + (l * C + k if order == "contiguous" else k * L + l)
+                for j in range(V):
+                    e = V * vi + j
+                    acc[j] = xs[e] * ys[e] + acc[j]
+            lanes.append(acc)
+        if combine == "none":
+            for acc in lanes:
+                out.extend(acc)
+        else:
+            comp = [np.float32(0)] * V
+            for acc in lanes:
+                for j in range(V):
+                    comp[j] = acc[j] + comp[j]
+            out.extend(comp)
+    r = np.float32(0)
+    for t in out:
+        r = t + r
+    return r
+
+
+@pytest.mark.parametrize("order", ["contiguous", "strided"])
+@pytest.mark.parametrize("combine", ["none", "seq"])
+@pytest.mark.parametrize("V", [1, 2, 4])
+def test_vector_strategies_match_plain_loops(order, combine, V):
+    # Sec. 6.2's dot expression keeps a float4 accumulator per work-item over
+    # asVector 4 views and writes every work-item's value out; the oracle's
+    # vector strategies against the same computation written as loops.
+    xs, ys = discriminating_dot_inputs(50 + V, V * 8 * 6 * 5)
+    p = S.Plan(seq=6, lanes=8, order=order, combine=combine, vec=V)
+    want = _loops_vector_dot(xs, ys, V, 8, 6, order, combine)
+    assert same_bits(S.dot(xs, ys, p), want)
+    e = S.dot_expr(len(xs), p)
+    assert same_bits(eval_scalar.evaluate(e, {"xs": xs, "ys": ys}), want)
+
+
+def test_vector_tree_is_the_scalar_tree_per_component():
+    # Component j of a V-wide strategy is the scalar strategy on the
+    # elements j, j+V, ...: the chunk values of the vector strategy are, per
+    # chunk and component, the scalar chunk values of the de-interleaved
+    # inputs, folded in chunk-then-component order.
+    V, L, C, G = 4, 8, 5, 3
+    xs, ys = discriminating_dot_inputs(61, V * L * C * G)
+    for order in ("contiguous", "strided"):
+        pv = S.Plan(seq=C, lanes=L, order=order, combine="tree", vec=V)
+        p1 = S.Plan(seq=C, lanes=L, order=order, combine="tree")
+        chunk_expr = (f"(mapWorkgroup (lam (ch) {S._chunk_value('ch', p1, S.MUL_ADD)})"
+                      f" (split {L * C} (zip xs ys)))")
+        per_comp = [eval_numpy.evaluate(chunk_expr, {"xs": xs[j::V], "ys": ys[j::V]})
+                    for j in range(V)]
+        r = np.float32(0)
+        for g in range(G):
+            for j in range(V):
+                r = per_comp[j][g] + r
+        assert same_bits(S.dot(xs, ys, pv), r), order
+
+
+def test_vector_lanes_are_adjacent_scalar_lanes():
+    # Uncombined strategies: a strided V-wide strategy with L lanes reads and
+    # folds exactly like the scalar strided one with V*L lanes (vector lane
+    # l component j = scalar lane V*l + j), and a contiguous V-wide one like
+    # the scalar strided strategy with V lanes on chunks of one lane's row.
+    V, L, C = 4, 8, 6
+    xs, ys = discriminating_dot_inputs(62, V * L * C * 7)
+    strided_v = S.dot(xs, ys, S.Plan(seq=C, lanes=L, order="strided", combine="none", vec=V))
+    assert same_bits(strided_v, S.dot(xs, ys, S.Plan(seq=C, lanes=V * L, order="strided",
+                                                     combine="none")))
+    contig_v = S.dot(xs, ys, S.Plan(seq=C, lanes=L, order="contiguous", combine="none", vec=V))
+    assert same_bits(contig_v, S.dot(xs, ys, S.Plan(seq=C, lanes=V, order="strided",
+                                                    combine="none")))
+    assert not same_bits(strided_v, contig_v)
+
+
+def test_vector_strategies_integer_and_all_ones():
+    # Exact cases: 32-bit integers (every strategy equals the modular sum) and
+    # all ones with exactly representable partial sums (result = n).
+    g = np.random.default_rng(63)
+    n = 4 * 8 * 16 * 3
+    xi = g.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    yi = g.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    want = int(sum(int(a) * int(b) for a, b in zip(xi, yi)) % (1 << 32))
+    ones = np.ones(n, np.float32)
+    for order in ("contiguous", "strided"):
+        for combine in ("tree", "seq", "none"):
+            p = S.Plan(seq=16, lanes=8, order=order, combine=combine, vec=4)
+            assert int(S.dot(xi, yi, p, num="u32")) == want
+            assert float(S.dot(ones, ones, p)) == n
+            assert float(S.asum(-ones, p)) == n
