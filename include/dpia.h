@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DPIA_ABI_VERSION 1u
+#define DPIA_ABI_VERSION 2u
 
 /* Same type as hipStream_t. */
 typedef struct ihipStream_t* dpia_stream_t;
@@ -82,7 +82,11 @@ typedef enum {
 
 typedef enum {
   DPIA_COMBINE_TREE = 0,     /* pairwise tree over the L lanes, lane order     */
-  DPIA_COMBINE_SEQ = 1       /* reduceSeq (+) 0 over the L lanes              */
+  DPIA_COMBINE_SEQ = 1,      /* reduceSeq (+) 0 over the L lanes              */
+  DPIA_COMBINE_NONE = 2      /* no work-group combine: every lane's value is a
+                                chunk value (join of the mapLocal level, as in
+                                the dot expression of Sec. 6.2), so the outer
+                                fold runs over G * L values; dot / asum only */
 } dpia_combine;
 
 typedef enum {
@@ -115,6 +119,15 @@ typedef enum {
  *  max_grid     0 = automatic; else an upper bound on launched work-groups
  *               (work is distributed by a grid-stride loop; no effect on
  *               the result)
+ *  vec_width    dot / asum: 0 or 1 = scalar elements; V = 2 or 4: the inputs
+ *               are read as vectors of V consecutive elements (Sec. 6.1
+ *               asVector V), so lanes fold vectors: a chunk is L*C vectors
+ *               (V*L*C elements), every lane keeps V component accumulators
+ *               (component j folds elements j, j+V, ... of its vectors), the
+ *               combine acts per component, and each chunk contributes its
+ *               V components (asScalar V) -- or, with DPIA_COMBINE_NONE,
+ *               its L lanes' V components each, lane by lane -- to the
+ *               outer fold.  Plain accumulation only.
  */
 typedef struct {
   uint32_t abi_version;
@@ -128,6 +141,7 @@ typedef struct {
   uint32_t rows_per_wg;
   uint32_t row_parts;
   uint32_t max_grid;
+  uint32_t vec_width;
 } dpia_strategy;
 
 /*
@@ -214,13 +228,15 @@ dpia_status dpia_scal(const dpia_strategy* s, dpia_dtype dt, int64_t n, float al
  * the work-group combine of its L lane folds (the OpenCL dot kernel of
  * Sec. 6.2 likewise writes its per-work-group results and leaves the last
  * reduction to a later step).  dpia_fold then computes the outer
- * reduceSeq (+) 0 over those G = n / W values in chunk order.  Together they
+ * reduceSeq (+) 0 over those values in chunk order.  Together they
  * give the same bits as dpia_dot / dpia_asum with the same strategy, whatever
  * its `passes`; a caller that gathers chunk values from several devices in
  * device order can fold them the same way.
  *   op       DPIA_OP_DOT (x and y) or DPIA_OP_ASUM (x; y ignored)
  *   dt, n    as for dpia_dot / dpia_asum
- *   chunks   device buffer of chunks_bytes >= G * value size, where a chunk
+ *   chunks   device buffer of chunks_bytes >= G * values per chunk * value
+ *            size.  A chunk has one value, or V with vec_width V, times L
+ *            with DPIA_COMBINE_NONE (in lane, then component order); a
  *            value is the accumulator: 4 bytes (binary32 or I32), or a pair
  *            of binary32 (s, c), 8 bytes, for Kahan
  *   out, out_dt  as for dpia_dot / dpia_asum

@@ -180,7 +180,8 @@ def _final(partials: str, plan: Plan) -> str:
     return f"(reduceSeq {ADD} 0 {partials})"
 
 
-def _reduction(n: int, view: str, plan: Plan, step: str) -> str:
+def _partials(n: int, view: str, plan: Plan, step: str) -> str:
+    """The chunk values: what the mapWorkgroup level writes out."""
     plan.check()
     if n % plan.chunk:
         raise ValueError(f"n={n} is not a multiple of the chunk {plan.chunk}")
@@ -198,7 +199,11 @@ def _reduction(n: int, view: str, plan: Plan, step: str) -> str:
         partials = f"(mapWorkgroup (lam (ch) {body}) (split {w} {view}))"
     if V > 1:
         partials = f"(asScalar {V} {partials})"
-    return _final(partials, plan)
+    return partials
+
+
+def _reduction(n: int, view: str, plan: Plan, step: str) -> str:
+    return _final(_partials(n, view, plan, step), plan)
 
 
 def _vectors(name: str, plan: Plan) -> str:
@@ -209,6 +214,15 @@ def dot_expr(n: int, plan: Plan) -> str:
     """dot xs ys under ``plan``; inputs ``xs``, ``ys`` of length n."""
     step = KAHAN_MUL_STEP if plan.accum == "kahan" else MUL_ADD
     return _reduction(n, f"(zip {_vectors('xs', plan)} {_vectors('ys', plan)})", plan, step)
+
+
+def dot_chunks_expr(n: int, plan: Plan) -> str:
+    """The chunk values of dot xs ys under ``plan`` (the array the outer fold
+    reads: one value per chunk, V per chunk for vector strategies, L*V for
+    uncombined ones)."""
+    if plan.accum != "plain":
+        raise ValueError("chunk values are given for plain accumulation")
+    return _partials(n, f"(zip {_vectors('xs', plan)} {_vectors('ys', plan)})", plan, MUL_ADD)
 
 
 def asum_expr(n: int, plan: Plan) -> str:
@@ -312,6 +326,12 @@ def dot(xs: np.ndarray, ys: np.ndarray, plan: Plan, num: str = "f32"):
     if n != len(xs) and plan.accum != "plain":
         raise ValueError("compensated accumulation needs n to be a multiple of the chunk")
     return evaluate(dot_expr(n, plan), {"xs": _zero_extend(xs, n), "ys": _zero_extend(ys, n)}, num)
+
+
+def dot_chunks(xs: np.ndarray, ys: np.ndarray, plan: Plan, num: str = "f32"):
+    n = extended_length(len(xs), plan.chunk)
+    return evaluate(dot_chunks_expr(n, plan), {"xs": _zero_extend(xs, n),
+                                               "ys": _zero_extend(ys, n)}, num)
 
 
 def asum(xs: np.ndarray, plan: Plan, num: str = "f32"):

@@ -12,8 +12,9 @@ import ctypes
 from dataclasses import dataclass, replace
 
 from . import _lib
-from ._lib import (BF16, CONTIGUOUS, F32, F64, FP8_E4M3, I32, KAHAN, OP_ASUM, OP_DOT,  # noqa: F401
-                   OP_GEMV, OP_SCAL, PLAIN, SEQ, STRIDED, TREE, DpiaError, last_error_detail)
+from ._lib import (BF16, CONTIGUOUS, F32, F64, FP8_E4M3, I32, KAHAN, NONE, OP_ASUM,  # noqa: F401
+                   OP_DOT, OP_GEMV, OP_SCAL, PLAIN, SEQ, STRIDED, TREE, DpiaError,
+                   last_error_detail)
 
 
 @dataclass(frozen=True)
@@ -29,11 +30,12 @@ class Strategy:
     rows_per_wg: int = 1
     row_parts: int = 1
     max_grid: int = 0
+    vec_width: int = 1            # V: dot / asum over asVector V views (1: scalar)
 
     def c(self) -> _lib.CStrategy:
         return _lib.CStrategy(_lib.ABI_VERSION, self.seq_len, self.local_size, self.order,
                               self.wg_combine, self.passes, self.accum, self.final_f64,
-                              self.rows_per_wg, self.row_parts, self.max_grid)
+                              self.rows_per_wg, self.row_parts, self.max_grid, self.vec_width)
 
     def with_(self, **kw) -> "Strategy":
         return replace(self, **kw)
@@ -176,18 +178,27 @@ def scal(alpha: float, x, s: Strategy, y=None, stream=None):
 
 
 def num_chunks(s: Strategy, n: int) -> int:
-    return n // (s.seq_len * s.local_size)
+    """G: chunks of a length-n dot / asum (the last one may be partial)."""
+    w = s.seq_len * s.local_size * max(1, s.vec_width)
+    return -(-n // w)
+
+
+def values_per_chunk(s: Strategy) -> int:
+    """Chunk values per chunk: the vector width, times L when uncombined."""
+    return max(1, s.vec_width) * (s.local_size if s.wg_combine == NONE else 1)
 
 
 def chunks(op: int, s: Strategy, x, y=None, out=None, stream=None):
-    """The mapWorkgroup level of a dot (op=OP_DOT) or asum (OP_ASUM): one
-    accumulator value per chunk (4 bytes, or 8 for a Kahan pair)."""
+    """The mapWorkgroup level of a dot (op=OP_DOT) or asum (OP_ASUM): the
+    chunks' values (``values_per_chunk`` each; 4 bytes, or 8 for a Kahan
+    pair)."""
     torch = _torch()
     n = x.numel()
     dt = _dtype_code(x)
     vb = 8 if s.accum == KAHAN else 4
     if out is None:
-        out = torch.empty(max(1, num_chunks(s, n)) * vb, dtype=torch.uint8, device=x.device)
+        out = torch.empty(max(1, num_chunks(s, n) * values_per_chunk(s)) * vb, dtype=torch.uint8,
+                          device=x.device)
     cs = s.c()
     yp = _dev(y) if y is not None else ctypes.c_void_p(0)
     _lib.check(_lib.lib().dpia_chunks(ctypes.byref(cs), op, dt, n, _dev(x), yp, _dev(out),

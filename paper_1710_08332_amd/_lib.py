@@ -10,7 +10,7 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpia.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 # dpia_status
 OK, ERR_NULL, ERR_SHAPE, ERR_STRATEGY, ERR_DTYPE, ERR_WORKSPACE, ERR_HIP, ERR_ABI = range(8)
@@ -20,7 +20,7 @@ F32, F64, I32, BF16, FP8_E4M3 = range(5)
 OP_DOT, OP_ASUM, OP_GEMV, OP_SCAL = range(4)
 # dpia_order, dpia_combine, dpia_accum
 CONTIGUOUS, STRIDED = 0, 1
-TREE, SEQ = 0, 1
+TREE, SEQ, NONE = 0, 1, 2
 PLAIN, KAHAN = 0, 1
 
 EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
@@ -33,7 +33,7 @@ EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_ge
 class CStrategy(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "abi_version", "seq_len", "local_size", "order", "wg_combine", "passes", "accum",
-        "final_f64", "rows_per_wg", "row_parts", "max_grid")]
+        "final_f64", "rows_per_wg", "row_parts", "max_grid", "vec_width")]
 
 
 class CInstance(ctypes.Structure):

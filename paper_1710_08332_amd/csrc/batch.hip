@@ -169,6 +169,8 @@ extern "C" dpia_status dpia_batch_plan_create(const dpia_instance* inst, int32_t
     const dpia_strategy& s = strategies[d.strategy];
     if (s.accum != DPIA_ACCUM_PLAIN)
       return bad(DPIA_ERR_STRATEGY, where + "batched strategies use plain accumulation");
+    if (s.vec_width > 1 || s.wg_combine == DPIA_COMBINE_NONE)
+      return bad(DPIA_ERR_STRATEGY, where + "batched strategies are scalar and combined");
     Plan p;
     std::string detail;
     const dpia_op op = static_cast<dpia_op>(d.op);

@@ -24,7 +24,7 @@
 namespace dpia {
 
 enum : int { kContiguous = 0, kStrided = 1 };
-enum : int { kTree = 0, kSeq = 1 };
+enum : int { kTree = 0, kSeq = 1, kNone = 2 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -372,6 +372,76 @@ __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool act
   }
   lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
   return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
+}
+
+}  // namespace dpia
+
+namespace dpia {
+
+// A view whose element offsets start `base` elements into another view.
+template <class View>
+struct ShiftedView {
+  View v;
+  int base;
+  template <int NV, class Term>
+  __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
+    v.template load<NV>(base + off, z);
+  }
+};
+
+// Chunk values of vector strategies (VEC > 1: the view is read as vectors of
+// VEC consecutive elements, asVector VEC) and of uncombined ones (COMBINE ==
+// kNone: every lane's value is a chunk value).  Writes the chunk's values to
+// out[g * cv ...], cv = VEC, or L * VEC uncombined, in lane then component
+// order (asScalar VEC of the join).  All threads of the work-group call this
+// together (the combine has barriers).
+template <class Op, int ORDER, int NV, int COMBINE, int VEC, class View>
+__device__ __forceinline__ void chunk_values_wide(const View& view, bool active, int t, int team,
+                                                  int L, int C, int limit,
+                                                  typename Op::T* scratch, typename Op::T* out,
+                                                  int64_t g) {
+  using T = typename Op::T;
+  if constexpr (VEC == 1) {
+    static_assert(COMBINE == kNone, "scalar combined chunks use chunk_value");
+    constexpr int NL = (ORDER == kStrided) ? NV : 1;
+    T acc[NL];
+    lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
+    if (active) {
+      const int64_t lane0 = g * L + (ORDER == kStrided ? t * NV : t);
+#pragma unroll
+      for (int v = 0; v < NL; ++v) out[lane0 + v] = acc[v];
+    }
+  } else {
+    static_assert(NV == VEC, "a thread is one vector lane");
+    T acc[VEC];
+    if constexpr (ORDER == kStrided) {
+      // vector lane t takes vectors t, t + L, ...: element VEC*(k*L + t) + j
+      // is scalar lane VEC*t + j of the strided order over VEC*L lanes
+      lane_folds<Op, kStrided, VEC>(view, active, t, L * VEC, C, limit, acc);
+    } else {
+      // vector lane t takes vectors t*C .. t*C + C-1: within the lane's row of
+      // VEC*C elements, component j takes elements j, j + VEC, ..., the
+      // strided order over VEC lanes
+      const int base = t * VEC * C;
+      int have = limit - base;
+      have = have < 0 ? 0 : (have > VEC * C ? VEC * C : have);
+      lane_folds<Op, kStrided, VEC>(ShiftedView<View>{view, base}, active, 0, VEC, C, have, acc);
+    }
+    if constexpr (COMBINE == kNone) {
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) out[(g * L + t) * VEC + j] = acc[j];
+      }
+    } else {
+      // the combine acts on each component
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) {
+        T one[1] = {acc[j]};
+        const T c = combine_lanes<typename Op::Arith, 1, COMBINE>(one, t, team, L, scratch);
+        if (active && t == 0) out[g * VEC + j] = c;
+      }
+    }
+  }
 }
 
 }  // namespace dpia

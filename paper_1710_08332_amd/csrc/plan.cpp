@@ -61,8 +61,17 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   if (s->seq_len < 1 || s->local_size < 1)
     return fail(detail, DPIA_ERR_STRATEGY, "seq_len and local_size must be >= 1");
   if (s->order > DPIA_ORDER_STRIDED) return fail(detail, DPIA_ERR_STRATEGY, "unknown order");
-  if (s->wg_combine > DPIA_COMBINE_SEQ)
+  if (s->wg_combine > DPIA_COMBINE_NONE)
     return fail(detail, DPIA_ERR_STRATEGY, "unknown wg_combine");
+  const int V = s->vec_width == 0 ? 1 : static_cast<int>(s->vec_width);
+  if (V != 1 && V != 2 && V != 4)
+    return fail(detail, DPIA_ERR_STRATEGY, "vec_width must be 0, 1, 2 or 4");
+  if ((V > 1 || s->wg_combine == DPIA_COMBINE_NONE) && op != DPIA_OP_DOT && op != DPIA_OP_ASUM)
+    return fail(detail, DPIA_ERR_STRATEGY,
+                "vector and uncombined strategies apply to dot and asum only");
+  if ((V > 1 || s->wg_combine == DPIA_COMBINE_NONE) && s->accum != DPIA_ACCUM_PLAIN)
+    return fail(detail, DPIA_ERR_STRATEGY,
+                "vector and uncombined strategies use plain accumulation");
   if (s->passes != 1 && s->passes != 2)
     return fail(detail, DPIA_ERR_STRATEGY, "passes must be 1 or 2");
   if (s->accum > DPIA_ACCUM_KAHAN) return fail(detail, DPIA_ERR_STRATEGY, "unknown accum");
@@ -104,8 +113,11 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   q.order = s->order;
   q.L = s->local_size;
   q.C = s->seq_len;
-  q.W = q.L * q.C;
-  q.combine = (q.L == 1) ? static_cast<uint32_t>(DPIA_COMBINE_SEQ) : s->wg_combine;
+  q.V = V;
+  q.W = q.L * q.C * V;
+  q.combine = (q.L == 1 && s->wg_combine != DPIA_COMBINE_NONE)
+                  ? static_cast<uint32_t>(DPIA_COMBINE_SEQ)
+                  : s->wg_combine;
   q.accum = s->accum;
   q.final_f64 = s->final_f64 != 0;
   q.passes = s->passes;
@@ -150,7 +162,12 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
 
   // Vector width (semantics-free: it decides which lanes or elements one
   // thread loads at once, never the order of any operation).
-  if (q.order == DPIA_ORDER_STRIDED) {
+  if (V > 1) {
+    // a thread is one vector lane and loads its V components at once
+    if (V > cap) return fail(detail, DPIA_ERR_STRATEGY, "vec_width exceeds a 16-byte load");
+    q.nv = V;
+    q.team = static_cast<int>(q.L);
+  } else if (q.order == DPIA_ORDER_STRIDED) {
     q.nv = widest_vector(cap, {q.L});
     q.team = static_cast<int>(q.L / q.nv);
   } else {
@@ -177,15 +194,17 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   // LDS: lane values for a sequential combine, one value per wave for a
   // tree wider than a wavefront, and the staging block of the final fold.
   size_t lds = 0;
-  if (q.combine == DPIA_COMBINE_SEQ) {
+  if (q.combine == DPIA_COMBINE_NONE) {
+    lds = 0;
+  } else if (q.combine == DPIA_COMBINE_SEQ) {
     lds = static_cast<size_t>(q.teams_per_wg) * q.L * q.acc_bytes;
   } else if (q.team > 64) {
     lds = static_cast<size_t>(q.teams_per_wg) * (q.team / 64) * q.acc_bytes;
   }
   // The contiguous order with binary32 operands is staged through LDS when
   // every lane holds whole tiles and the work-group has at most 256 threads.
-  q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 &&
-            q.C % kStage == 0 && q.wg_threads <= 256;
+  q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 && V == 1 &&
+            q.combine != DPIA_COMBINE_NONE && q.C % kStage == 0 && q.wg_threads <= 256;
   q.stage_off = 0;
   if (q.stage) {
     q.stage_off = round_up(lds, 16);
@@ -214,7 +233,9 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     q.partial_bytes = 0;
     q.ws_bytes = 0;
   } else {
-    q.partial_bytes = round_up(static_cast<size_t>(q.items) * q.acc_bytes, kWsAlign);
+    q.cv = (q.combine == DPIA_COMBINE_NONE ? q.L : 1) * V;
+    q.values = q.items * q.cv;
+    q.partial_bytes = round_up(static_cast<size_t>(q.values) * q.acc_bytes, kWsAlign);
     q.ws_bytes = q.partial_bytes + kWsAlign;   // + the arrival counter
   }
   *p = q;

@@ -35,14 +35,18 @@ struct Plan {
   bool final_f64;
   uint32_t passes;
 
-  int64_t L, C, W;        // lanes, elements per lane, elements per chunk
+  int64_t L, C, W;        // lanes, elements (vectors) per lane, elements per chunk
+  int V;                  // vector width of the asVector view (1: scalar)
   int64_t items;          // dot/asum: chunks G = ceil(n / W); gemv: rows m
+  int64_t cv;             // dot/asum: values per chunk (V, times L uncombined)
+  int64_t values;         // dot/asum: values the outer fold reads, items * cv
   int64_t n;              // dot/asum: vector length
   int64_t k, lda;         // gemv only
   int row_parts, R;       // gemv only
 
   int nv;                 // strided: lanes per thread; contiguous: elements
-                          // per vector load of one lane
+                          // per vector load of one lane; V > 1: V (a thread
+                          // is one vector lane)
   int team;               // threads cooperating on one chunk (P)
   int teams_per_wg;       // chunks (rows) a hardware work-group holds at once
   int wg_threads;         // teams_per_wg * team

@@ -19,6 +19,7 @@ namespace dpia {
 
 struct ReduceArgs {
   int64_t items;          // G chunks
+  int64_t values;         // values the outer fold reads (G * values per chunk)
   int64_t n;              // elements; the last chunk may be partly beyond n
   int64_t W;
   int L, C, team, teams_per_wg;
@@ -31,7 +32,7 @@ struct ReduceArgs {
   void* out;
 };
 
-template <class Op, int ORDER, int NV, int COMBINE, int FINAL>
+template <class Op, int ORDER, int NV, int COMBINE, int FINAL, int VEC>
 __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
   using T = typename Op::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -54,9 +55,14 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
     const auto view = op.chunk(active ? g : 0, a.W);
     const int64_t rest = a.n - g * a.W;
     const int limit = static_cast<int>(rest < a.W ? rest : a.W);
-    const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, limit,
-                                                    scratch, stage);
-    if (active && t == 0) partials[g] = v;
+    if constexpr (VEC == 1 && COMBINE != kNone) {
+      const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, limit,
+                                                      scratch, stage);
+      if (active && t == 0) partials[g] = v;
+    } else {
+      chunk_values_wide<Op, ORDER, NV, COMBINE, VEC>(view, active, t, a.team, a.L, a.C, limit,
+                                                     scratch, partials, g);
+    }
   }
   if (a.one_pass) {
     // The barrier makes this work-group's partial stores happen before
@@ -73,7 +79,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
     }
     __syncthreads();
     if (is_last) {
-      final_fold<typename Op::Arith, FINAL>(partials, a.items, a.out, a.out_f64, lds);
+      final_fold<typename Op::Arith, FINAL>(partials, a.values, a.out, a.out_f64, lds);
       if (threadIdx.x == 0)   // leave the counter at zero for the next call
         __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -92,6 +98,7 @@ ReduceArgs reduce_args(const Plan& p, void* partials, void* counter, void* out, 
                        bool one_pass) {
   ReduceArgs a{};
   a.items = p.items;
+  a.values = p.values;
   a.n = p.n;
   a.W = p.W;
   a.L = static_cast<int>(p.L);
@@ -109,25 +116,51 @@ ReduceArgs reduce_args(const Plan& p, void* partials, void* counter, void* out, 
   return a;
 }
 
+// Calls f(order, combine, nv, vec constants) for a plan.  Vector and
+// uncombined shapes exist for the plain operations only (WIDE).
+template <bool WIDE, class F>
+hipError_t with_reduce_shape(const Plan& p, F&& f) {
+  constexpr int MAXNV = kVecBytes / static_cast<int>(sizeof(float));
+  if (p.V == 1 && p.combine != DPIA_COMBINE_NONE) {
+    return with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
+      return with_nv<MAXNV>(p.nv, [&](auto nvc) { return f(ord, comb, nvc, ic<1>{}); });
+    });
+  }
+  if constexpr (WIDE) {
+    auto by_order = [&](auto comb, auto nvc, auto vec) {
+      if (p.order == DPIA_ORDER_STRIDED) return f(ic<kStrided>{}, comb, nvc, vec);
+      return f(ic<kContiguous>{}, comb, nvc, vec);
+    };
+    if (p.V == 1)
+      return with_nv<MAXNV>(p.nv, [&](auto nvc) { return by_order(ic<kNone>{}, nvc, ic<1>{}); });
+    auto by_combine = [&](auto vec) {
+      if (p.combine == DPIA_COMBINE_TREE) return by_order(ic<kTree>{}, vec, vec);
+      if (p.combine == DPIA_COMBINE_SEQ) return by_order(ic<kSeq>{}, vec, vec);
+      return by_order(ic<kNone>{}, vec, vec);
+    };
+    if (p.V == 2) return by_combine(ic<2>{});
+    if (p.V == 4) return by_combine(ic<4>{});
+  }
+  return hipErrorInvalidValue;
+}
+
 // The mapWorkgroup level: chunk values into `partials`; with one_pass the
 // last work-group also folds them into `out`.
 template <class Op, int FINAL>
 hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
   if (p.items == 0) return hipSuccess;
   const int64_t grid = grid_size(p);
-  return with_order_combine(p.order, p.combine, [&](auto ord, auto comb) {
+  return with_reduce_shape<FINAL == kFinalPlain>(p, [&](auto ord, auto comb, auto nvc, auto vec) {
     constexpr int ORDER = decltype(ord)::value;
     constexpr int COMBINE = decltype(comb)::value;
-    constexpr int MAXNV = kVecBytes / static_cast<int>(sizeof(float));
-    return with_nv<MAXNV>(p.nv, [&](auto nvc) {
-      constexpr int NV = decltype(nvc)::value;
-      auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL>;
-      Op op_copy = op;
-      ReduceArgs a_copy = a;
-      void* args[] = {&op_copy, &a_copy};
-      return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
-                             dim3(p.wg_threads), args, p.lds_bytes, stream);
-    });
+    constexpr int NV = decltype(nvc)::value;
+    constexpr int VEC = decltype(vec)::value;
+    auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL, VEC>;
+    Op op_copy = op;
+    ReduceArgs a_copy = a;
+    void* args[] = {&op_copy, &a_copy};
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(p.wg_threads),
+                           args, p.lds_bytes, stream);
   });
 }
 
@@ -151,7 +184,7 @@ hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, vo
                                  !two_pass);
   hipError_t e = launch_chunks<Op, FINAL>(p, op, a, stream);
   if (e != hipSuccess || !two_pass) return e;
-  return launch_fold<Op, FINAL>(p.items, ws, out, out_f64, stream);
+  return launch_fold<Op, FINAL>(p.values, ws, out, out_f64, stream);
 }
 
 // Calls f(op, final-kind constant) for the operation and accumulation of a plan.
@@ -261,7 +294,7 @@ extern "C" dpia_status dpia_chunks(const dpia_strategy* s, dpia_op op, dpia_dtyp
   if (n > 0 && (!x || (dot && !y))) return bad(DPIA_ERR_NULL, "input vectors must be non-NULL");
   if (n > 0 && (!aligned16(x) || (dot && !aligned16(y))))
     return bad(DPIA_ERR_SHAPE, "input vectors must be 16-byte aligned");
-  const size_t need = static_cast<size_t>(p.items) * p.acc_bytes;
+  const size_t need = static_cast<size_t>(p.values) * p.acc_bytes;
   if (p.items > 0 && !chunks) return bad(DPIA_ERR_NULL, "chunks must be non-NULL");
   if (chunks_bytes < need)
     return bad(DPIA_ERR_WORKSPACE, "chunks holds " + std::to_string(chunks_bytes) +
@@ -295,7 +328,7 @@ extern "C" dpia_status dpia_fold(const dpia_strategy* s, dpia_op op, dpia_dtype 
   hipError_t e = with_reduction(p, nullptr, nullptr, [&](auto op_v, auto fin) {
     using Op = decltype(op_v);
     constexpr int FINAL = decltype(fin)::value;
-    return launch_fold<Op, FINAL>(p.items, chunks, out, out_dt == DPIA_F64, hs);
+    return launch_fold<Op, FINAL>(p.values, chunks, out, out_dt == DPIA_F64, hs);
   });
   if (e != hipSuccess) return hip_fail(e, "dpia_fold launch");
   clear_detail();

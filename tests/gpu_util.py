@@ -11,9 +11,10 @@ def to_plan(s: dp.Strategy) -> S.Plan:
     """The oracle's reading of a descriptor (field for field)."""
     return S.Plan(seq=s.seq_len, lanes=s.local_size,
                   order="strided" if s.order == dp.STRIDED else "contiguous",
-                  combine="seq" if s.wg_combine == dp.SEQ else "tree",
+                  combine={dp.SEQ: "seq", dp.TREE: "tree", dp.NONE: "none"}[s.wg_combine],
                   accum="kahan" if s.accum == dp.KAHAN else "plain",
-                  final_f64=bool(s.final_f64), rows=s.rows_per_wg, row_parts=s.row_parts)
+                  final_f64=bool(s.final_f64), rows=s.rows_per_wg, row_parts=s.row_parts,
+                  vec=max(1, s.vec_width))
 
 
 def bits(a):

@@ -61,6 +61,19 @@ def test_ragged_lengths_are_zero_extended():
     assert check(BASE.with_(row_parts=2), dp.OP_GEMV, dp.F32, 10, 4097)[0] == _lib.OK
 
 
+def test_vector_and_uncombined_workspace():
+    # a chunk of V*L*C elements gives V values, or L*V uncombined
+    s = dp.Strategy(seq_len=2048, local_size=64, vec_width=4, wg_combine=dp.NONE)
+    st, ws = check(s, dp.OP_DOT, dp.F32, 0, 1 << 26)
+    assert st == _lib.OK and ws == 128 * 64 * 4 * 4 + 256
+    assert dp.num_chunks(s, 1 << 26) == 128 and dp.values_per_chunk(s) == 256
+    st, ws = check(s.with_(wg_combine=dp.TREE), dp.OP_ASUM, dp.F32, 0, (1 << 26) + 1)
+    assert st == _lib.OK and ws == 256 + 4 * 129 * 4 + (256 - 4 * 129 * 4 % 256) % 256 * 1
+    st, ws = check(dp.Strategy(seq_len=64, local_size=1, wg_combine=dp.NONE), dp.OP_DOT, dp.I32,
+                   0, 640)
+    assert st == _lib.OK and ws == 256 + 256
+
+
 def test_valid_strategy_reports_workspace():
     st, ws = check(BASE, dp.OP_DOT, dp.F32, 0, 1 << 20)
     assert st == _lib.OK
@@ -92,6 +105,12 @@ def test_valid_strategy_reports_workspace():
     (BASE.with_(rows_per_wg=0), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
     (BASE.with_(row_parts=3), dp.OP_GEMV, dp.F32, 10, 4096, _lib.ERR_STRATEGY),
     (BASE, dp.OP_DOT, dp.F32, 0, -4096, _lib.ERR_SHAPE),
+    (BASE.with_(vec_width=3), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
+    (BASE.with_(vec_width=8), dp.OP_DOT, dp.F32, 0, 1 << 15, _lib.ERR_STRATEGY),
+    (BASE.with_(vec_width=4), dp.OP_GEMV, dp.F32, 16, 1024, _lib.ERR_STRATEGY),
+    (BASE.with_(wg_combine=dp.NONE), dp.OP_GEMV, dp.F32, 16, 1024, _lib.ERR_STRATEGY),
+    (BASE.with_(vec_width=4, accum=dp.KAHAN), dp.OP_DOT, dp.F32, 0, 1 << 14, _lib.ERR_STRATEGY),
+    (BASE.with_(wg_combine=3), dp.OP_DOT, dp.F32, 0, 4096, _lib.ERR_STRATEGY),
 ])
 def test_invalid_descriptors_are_rejected(s, op, dt, m, n, want):
     st, _ = check(s, op, dt, m, n)

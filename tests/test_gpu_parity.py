@@ -476,3 +476,58 @@ def test_gemv_blas_bit_exact(kw, fmt, alpha, beta):
     torch.cuda.synchronize()
     want = S.gemv_blas(alpha, src, x, beta, y0, plan, a_format=fmt, scale=scale)
     assert_same_bits(yt.cpu().numpy(), want, f"gemv_blas {fmt}")
+
+
+VEC_STRATS = [
+    dict(seq_len=16, local_size=64, order=C_, wg_combine=dp.NONE, vec_width=4),  # Sec. 6.2 form
+    dict(seq_len=8, local_size=256, order=T_, wg_combine=TREE, vec_width=4),
+    dict(seq_len=5, local_size=128, order=C_, wg_combine=TREE, vec_width=4),
+    dict(seq_len=7, local_size=12, order=T_, wg_combine=SEQ, vec_width=2),
+    dict(seq_len=9, local_size=1024, order=T_, wg_combine=TREE, vec_width=2),
+    dict(seq_len=6, local_size=32, order=C_, wg_combine=SEQ, vec_width=4),
+    dict(seq_len=4, local_size=64, order=T_, wg_combine=dp.NONE, vec_width=4),
+    dict(seq_len=3, local_size=16, order=C_, wg_combine=dp.NONE),
+    dict(seq_len=4, local_size=64, order=T_, wg_combine=dp.NONE),
+    dict(seq_len=33, local_size=1, order=C_, wg_combine=dp.NONE, vec_width=4),
+]
+
+
+@pytest.mark.parametrize("kw", VEC_STRATS, ids=lambda k: "-".join(f"{a[:3]}{b}" for a, b in k.items()))
+@pytest.mark.parametrize("passes", [1, 2])
+@pytest.mark.parametrize("ragged", [0, 1])
+def test_vector_and_uncombined_strategies_bit_exact(kw, passes, ragged):
+    import torch
+    s = dp.Strategy(passes=passes, **kw)
+    p = to_plan(s)
+    n = p.chunk * 17 - ragged * (p.chunk // 3 + 5)
+    x, y = discriminating(23 + ragged, n)
+    assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, p), "dot")
+    assert_same_bits(gpu_asum(x, s), S.asum(x, p), "asum")
+    g = np.random.default_rng(5)
+    xi, yi = synthetic.integers_u32(g, n), synthetic.integers_u32(g, n)
+    assert_same_bits(gpu_dot(xi, yi, s), S.dot(xi, yi, p, num="u32"), "i32 dot")
+    # the chunk values element by element, then the fold
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    c = dp.chunks(dp.OP_DOT, s, xt, yt)
+    torch.cuda.synchronize()
+    want = np.asarray(S.dot_chunks(x, y, p), np.float32)
+    assert_same_bits(c.cpu().numpy()[:4 * len(want)].view(np.float32), want, "chunk values")
+
+
+def test_paper_vector_dot_at_full_size():
+    # the dot expression of Sec. 6.2: float4 views, 64 work-items per work-group
+    # each folding 2048 vectors, every work-item's value written out; then the
+    # ordered fold.  N = 2^26.
+    import torch
+    s = dp.Strategy(seq_len=2048, local_size=64, order=C_, wg_combine=dp.NONE, vec_width=4)
+    p = to_plan(s)
+    n = 1 << 26
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["scale"])
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    c = dp.chunks(dp.OP_DOT, s, xt, yt)
+    r = dp.dot(xt, yt, s)
+    torch.cuda.synchronize()
+    want = np.asarray(S.dot_chunks(x, y, p), np.float32)
+    assert len(want) == 128 * 64 * 4
+    assert_same_bits(c.cpu().numpy().view(np.float32), want, "Sec. 6.2 chunk values")
+    assert_same_bits(r.cpu().numpy()[0], S.dot(x, y, p), "Sec. 6.2 dot")

@@ -852,3 +852,24 @@ def test_vector_strategies_integer_and_all_ones():
             assert int(S.dot(xi, yi, p, num="u32")) == want
             assert float(S.dot(ones, ones, p)) == n
             assert float(S.asum(-ones, p)) == n
+
+
+def test_chunk_values_fold_to_the_result():
+    # The outer fold of the chunk values is the strategy's value, and the
+    # uncombined chunk values are the lanes' own folds (plain loops).
+    xs, ys = discriminating_dot_inputs(64, 4 * 8 * 6 * 5)
+    for p in (S.Plan(seq=6, lanes=8, combine="none", vec=4), S.Plan(seq=6, lanes=32),
+              S.Plan(seq=24, lanes=8, order="strided", combine="seq", vec=2)):
+        c = S.dot_chunks(xs, ys, p)
+        r = np.float32(0)
+        for v in c:
+            r = v + r
+        assert same_bits(S.dot(xs, ys, p), r)
+    c = S.dot_chunks(xs, ys, S.Plan(seq=6, lanes=8, combine="none", vec=4))
+    for i in (0, 1, 37, len(c) - 1):       # lane (g, l), component j of vector lane
+        g, l, j = i // 32, (i // 4) % 8, i % 4
+        acc = np.float32(0)
+        for k in range(6):
+            e = 4 * (g * 48 + l * 6 + k) + j
+            acc = xs[e] * ys[e] + acc
+        assert same_bits(c[i], acc)
