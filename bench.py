@@ -30,6 +30,11 @@ Other workloads (one JSON line per measured item, not the headline):
                           (eager, graph)
     --workload scal       scal y = alpha x, N = 2^26, under strided and
                           contiguous strategies, out of place and in place
+    --workload vector     dot N = 2^26 under vector (asVector 4) strategies,
+                          among them the dot expression of Sec. 6.2 (float4
+                          views, 64 work-items folding 2048 vectors each, no
+                          work-group combine): chunk kernel and fold timed
+                          apart
 Oracle work (parity, exact references) runs only in the CPU-baseline leg,
 which --no-cpu-baseline skips.
 """
@@ -92,8 +97,9 @@ def measured_traffic():
 
 
 def strategy_text(s: dp.Strategy, gemv: bool = False) -> str:
+    comb = {dp.TREE: "tree", dp.SEQ: "seq", dp.NONE: "uncombined"}[s.wg_combine]
     return (f"C={s.seq_len} L={s.local_size} {'strided' if s.order == dp.STRIDED else 'contiguous'}"
-            f" {'tree' if s.wg_combine == dp.TREE else 'seq'}"
+            f" {comb}" + (f" V={s.vec_width}" if s.vec_width > 1 else "")
             + (f" R={s.rows_per_wg}" if gemv else f" passes={s.passes}"))
 
 
@@ -471,6 +477,58 @@ def workload_scal(args):
                                                               np.asarray(want, np.float32).view(np.uint32)))})
 
 
+VECTOR_STRATEGIES = [
+    ("sec6.2", dp.Strategy(seq_len=2048, local_size=64, order=dp.CONTIGUOUS, wg_combine=dp.NONE,
+                           vec_width=4)),
+    ("contig-v4-tree", dp.Strategy(seq_len=64, local_size=256, order=dp.CONTIGUOUS,
+                                   wg_combine=dp.TREE, vec_width=4)),
+    ("strided-v4-tree", dp.Strategy(seq_len=64, local_size=256, order=dp.STRIDED,
+                                    wg_combine=dp.TREE, vec_width=4)),
+    ("strided-v4-tree-c256", dp.Strategy(seq_len=256, local_size=256, order=dp.STRIDED,
+                                         wg_combine=dp.TREE, vec_width=4)),
+    ("scalar-headline", DOT_STRATEGY),
+]
+
+
+def workload_vector(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import time_us
+    n = N_DOT
+    x, y = synthetic.dot_inputs(n, SEED)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    res = {}
+    for name, s in VECTOR_STRATEGIES:
+        s = s.with_(passes=2)
+        cbuf = torch.empty(dp.num_chunks(s, n) * dp.values_per_chunk(s) * 4, dtype=torch.uint8,
+                           device="cuda")
+        out = torch.empty(1, device="cuda")
+        c_us = time_us(lambda: dp.chunks(dp.OP_DOT, s, xt, yt, out=cbuf), reps=40)[0]
+        f_us = time_us(lambda: dp.fold(dp.OP_DOT, s, cbuf, n, dp.F32, out=out), reps=40)[0]
+        ws = dp.workspace(s, dp.OP_DOT, dp.F32, 0, n)
+        t_us = time_us(lambda: dp.dot(xt, yt, s, out=out, ws=ws), reps=40)[0]
+        torch.cuda.synchronize()
+        res[name] = (s, out.cpu().numpy()[0])
+        nval = dp.num_chunks(s, n) * dp.values_per_chunk(s)
+        _line(workload="vector", name=name, n=n, strategy=strategy_text(s), chunk_values=nval,
+              chunks_us=round(c_us, 2), fold_us=round(f_us, 2), dot_us=round(t_us, 2),
+              chunks_gbs=_gbs(8 * n + 4 * nval, c_us),
+              chunks_pct_peak=round(100 * (8 * n + 4 * nval) / c_us / 1e3 / PEAK_GBPS, 1),
+              dot_gbs=_gbs(8 * n + 4, t_us))
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        parity = {}
+        t0 = time.perf_counter()
+        for name, (s, got) in res.items():
+            want = np.float32(S.dot(x, y, to_plan(s)))
+            parity[name] = bool(want.view(np.uint32) == np.float32(got).view(np.uint32))
+        el = time.perf_counter() - t0
+        _line(workload="vector", cpu_baseline={"kind": "oracle", "cores": 1,
+                                               "seconds_all_strategies": round(el, 2)},
+              parity_bit_exact=parity)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,7 +536,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "small", "sweep", "precision", "batch", "scal"])
+                    choices=["scale", "small", "sweep", "precision", "batch", "scal", "vector"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -496,7 +554,8 @@ def main():
         sys.exit(1)
     if args.workload != "scale":
         {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision,
-         "batch": workload_batch, "scal": workload_scal}[args.workload](args)
+         "batch": workload_batch, "scal": workload_scal,
+         "vector": workload_vector}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)
