@@ -249,6 +249,28 @@ dpia_status dpia_fold(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
                       const void* chunks, void* out, dpia_dtype out_dt, dpia_stream_t stream);
 
 /*
+ * Generated kernels.  The expression generator (Secs. 4 and 6: Stage I and
+ * II translation, hoisting, one kernel per top-level parallel loop) emits
+ * HIP source for a DPIA expression; hipcc turns it into a gfx950 code
+ * object, and these calls load it and launch its kernels.
+ *   dpia_module_load    loads the code object at `path` on the current
+ *                       device; *out receives an opaque handle the caller
+ *                       releases with dpia_module_unload.
+ *   dpia_module_launch  launches `kernel` (a name in the module) with a 1-D
+ *                       grid of `grid` work-groups of `block` work-items
+ *                       (1..1024) on `stream`.  Every generated kernel takes
+ *                       device pointers only: args[0 .. nargs) are those
+ *                       pointers in the kernel's parameter order (at most
+ *                       64, none NULL).  Asynchronous, like every call here.
+ */
+typedef struct dpia_module dpia_module;
+dpia_status dpia_module_load(const char* path, dpia_module** out);
+dpia_status dpia_module_launch(dpia_module* m, const char* kernel, uint32_t grid,
+                               uint32_t block, void* const* args, int32_t nargs,
+                               dpia_stream_t stream);
+dpia_status dpia_module_unload(dpia_module* m);
+
+/*
  * Batched execution: many independent dot / asum / gemv instances, each with
  * its own strategy, in two launches (a persistent kernel over a table of
  * tiles, then one work-group per reduction instance folding its chunk values

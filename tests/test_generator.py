@@ -1,0 +1,116 @@
+"""The expression generator on the CPU: nesting rules, and the translated
+imperative program (run by tests/gen_interp.py) against the oracle's
+evaluation of the same expression text, bit for bit."""
+
+import numpy as np
+import pytest
+
+from oracle import eval_numpy
+from oracle import strategies as S
+from paper_1710_08332_amd.generator import CheckError, check, parse
+from paper_1710_08332_amd.generator import translate as T
+from tests import gen_interp as GI
+
+
+def disc(seed, n):
+    g = np.random.default_rng(seed)
+    h = n // 2
+    v = (np.where(g.random(h) < 0.5, -1, 1) * 2.0 ** g.uniform(-20, 20, h)).astype(np.float32)
+    w = 2 * g.random(h, dtype=np.float32) - 1
+    pad = [np.zeros(n % 2, np.float32)]
+    p = g.permutation(n)
+    return np.concatenate([v, v] + pad)[p], np.concatenate([w, -w] + pad)[p]
+
+
+def same(a, b):
+    return np.asarray(a).tobytes() == np.asarray(b).tobytes()
+
+
+DOT_PLANS = [
+    S.Plan(seq=4, lanes=8, order="strided", combine="tree"),
+    S.Plan(seq=5, lanes=3, combine="seq"),
+    S.Plan(seq=3, lanes=16, order="contiguous", combine="tree"),
+    S.Plan(seq=3, lanes=4, combine="none", vec=4),
+    S.Plan(seq=3, lanes=8, order="strided", combine="tree", vec=2),
+    S.Plan(seq=2, lanes=4, order="strided", combine="seq", vec=4),
+    S.Plan(seq=6, lanes=1),
+    S.Plan(seq=2, lanes=2, accum="kahan", final_f64=True),
+    S.Plan(seq=3, lanes=4, order="strided", accum="kahan"),
+]
+
+
+@pytest.mark.parametrize("p", DOT_PLANS, ids=str)
+def test_generated_dot_and_asum_match_the_oracle(p):
+    n = p.chunk * 3
+    x, y = disc(7, n)
+    prog = T.translate(S.dot_expr(n, p), {"xs": ("f32", (n,)), "ys": ("f32", (n,))})
+    got = GI.run(prog, {"xs": x, "ys": y})
+    want = S.dot(x, y, p)
+    assert same(got["out"][0], want)
+    if p.accum == "plain":
+        prog = T.translate(S.asum_expr(n, p), {"xs": ("f32", (n,))})
+        assert same(GI.run(prog, {"xs": x})["out"][0], S.asum(x, p))
+        g = np.random.default_rng(3)
+        xi = g.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+        yi = g.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+        prog = T.translate(S.dot_expr(n, p), {"xs": ("u32", (n,)), "ys": ("u32", (n,))}, num="u32")
+        assert same(GI.run(prog, {"xs": xi, "ys": yi})["out"][0], S.dot(xi, yi, p, num="u32"))
+
+
+@pytest.mark.parametrize("p", [S.Plan(seq=4, lanes=8, order="strided", rows=2),
+                               S.Plan(seq=3, lanes=4, combine="seq", rows=1, row_parts=2),
+                               S.Plan(seq=2, lanes=16, order="contiguous", rows=4)], ids=str)
+def test_generated_gemv_matches_the_oracle(p):
+    m, k = 4 * p.rows, p.chunk * p.row_parts
+    g = np.random.default_rng(11)
+    A = g.standard_normal((m, k)).astype(np.float32)
+    x = g.standard_normal(k).astype(np.float32)
+    prog = T.translate(S.gemv_expr(m, k, p), {"A": ("f32", (m, k)), "x": ("f32", (k,))})
+    assert same(GI.run(prog, {"A": A, "x": x})["out"], S.gemv(A, x, p))
+    y0 = g.standard_normal(m).astype(np.float32)
+    e = S.gemv_blas_expr(m, k, p)
+    prog = T.translate(e, {"A": ("f32", (m, k)), "x": ("f32", (k,)), "alpha": ("f32", ()),
+                           "beta": ("f32", ()), "yin": ("f32", (m,))})
+    got = GI.run(prog, {"A": A, "x": x, "alpha": np.float32(0.5), "beta": np.float32(-2),
+                        "yin": y0})["out"]
+    assert same(got, S.gemv_blas(0.5, A, x, -2.0, y0, p))
+
+
+def test_generated_scal_and_paper_listing_forms():
+    x = disc(5, 64)[0]
+    prog = T.translate("(mapGlobal (lam (e) (* alpha e)) xs)",
+                       {"alpha": ("f32", ()), "xs": ("f32", (64,))})
+    assert [k.kind for k in prog.kernels] == ["global"]
+    assert same(GI.run(prog, {"alpha": np.float32(1.7), "xs": x})["out"], np.float32(1.7) * x)
+    # the dot expression of Sec. 6.2 (float4 views, work-items' values written
+    # out), smaller: 2 work-groups of 4 work-items folding 3 vectors each
+    e = ("(asScalar 4 (join (mapWorkgroup (lam (zs1) (mapLocal (lam (zs2) (reduceSeq"
+         " (lam (x a) (+ (* (fst x) (snd x)) a)) (broadcast 4 0) zs2)) (split 3 zs1)))"
+         " (split 12 (zip (asVector 4 xs) (asVector 4 ys))))))")
+    xs, ys = disc(6, 96)
+    prog = T.translate(e, {"xs": ("f32", (96,)), "ys": ("f32", (96,))})
+    want = eval_numpy.evaluate(e, {"xs": xs, "ys": ys})
+    assert same(GI.run(prog, {"xs": xs, "ys": ys})["out"], want)
+    assert same(want, S.dot_chunks(xs, ys, S.Plan(seq=3, lanes=4, combine="none", vec=4)))
+
+
+@pytest.mark.parametrize("text", [
+    "(mapLocal (lam (x) x) xs)",                                            # no work-group
+    "(mapWorkgroup (lam (r) (mapLocal (lam (q) (mapLocal (lam (z) z) q)) r)) xs)",
+    "(mapWorkgroup (lam (r) (mapWorkgroup (lam (q) q) r)) xs)",
+    "(mapGlobal (lam (r) (mapLocal (lam (q) q) r)) xs)",
+    "(mapSeq (lam (r) (mapGlobal (lam (q) q) r)) xs)",
+    "(reduceSeq (lam (r a) (mapWorkgroup (lam (q) q) r)) 0 xs)",
+])
+def test_illegal_nestings_are_rejected(text):
+    with pytest.raises(CheckError):
+        check(parse(text))
+
+
+def test_legal_nestings_are_accepted():
+    # a sequential loop around mapLocal inside a work-group (gemv rows), and
+    # sequential maps inside work-items
+    for text in ["(mapWorkgroup (lam (rows) (map (lam (r) (mapLocal (lam (q) q) r)) rows)) xs)",
+                 "(mapWorkgroup (lam (r) (mapLocal (lam (q) (mapSeq (lam (z) z) q)) r)) xs)",
+                 "(mapGlobal (lam (r) (reduceSeq (lam (e a) (+ e a)) 0 r)) xs)"]:
+        check(parse(text))
