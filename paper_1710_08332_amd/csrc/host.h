@@ -43,8 +43,8 @@ inline bool aligned16(const void* ptr) {
   return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0;
 }
 
-inline dpia_status hip_fail(hipError_t e, const char* what) {
-  set_detail(std::string(what) + ": " + hipGetErrorString(e));
+inline dpia_status hip_fail(hipError_t e, const std::string& what) {
+  set_detail(what + ": " + hipGetErrorString(e));
   return DPIA_ERR_HIP;
 }
 

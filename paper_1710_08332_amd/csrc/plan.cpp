@@ -78,7 +78,8 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   if (s->final_f64 > 1) return fail(detail, DPIA_ERR_STRATEGY, "final_f64 must be 0 or 1");
   if (s->final_f64 && s->accum != DPIA_ACCUM_KAHAN)
     return fail(detail, DPIA_ERR_STRATEGY, "final_f64 applies to the Kahan accumulation only");
-  if (s->wg_combine == DPIA_COMBINE_TREE && !is_pow2(s->local_size))
+  // (scal is a map: it has no combine, whatever the descriptor says)
+  if (s->wg_combine == DPIA_COMBINE_TREE && !is_pow2(s->local_size) && op != DPIA_OP_SCAL)
     return fail(detail, DPIA_ERR_STRATEGY, "a tree combine needs a power-of-two local_size");
   if (s->rows_per_wg < 1) return fail(detail, DPIA_ERR_STRATEGY, "rows_per_wg must be >= 1");
   if (s->row_parts != 1 && s->row_parts != 2)
