@@ -66,3 +66,6 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    from paper_1710_08332_amd.generator import catalog   # noqa: E402
+    for p in catalog.build_all():
+        print(p)

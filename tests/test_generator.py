@@ -114,3 +114,23 @@ def test_legal_nestings_are_accepted():
                  "(mapWorkgroup (lam (r) (mapLocal (lam (q) (mapSeq (lam (z) z) q)) r)) xs)",
                  "(mapGlobal (lam (r) (reduceSeq (lam (e a) (+ e a)) 0 r)) xs)"]:
         check(parse(text))
+
+
+def test_catalogued_programs_match_the_oracle_on_the_cpu():
+    # every program the build compiles, at its own sizes (the small ones; the
+    # full-size ones share their shapes), run through the imperative form
+    from paper_1710_08332_amd.generator import catalog
+    g = np.random.default_rng(21)
+    for name, text, inputs, num in catalog.programs():
+        if max(int(np.prod(s)) for _, s in inputs.values()) > 70000:
+            continue
+        feed = {}
+        for k, (et, shape) in inputs.items():
+            if et == "u32":
+                feed[k] = g.integers(0, 2 ** 32, shape, dtype=np.uint64).astype(np.uint32)
+            else:
+                feed[k] = (2 * g.random(shape) - 1).astype(np.float32)
+        prog = T.translate(text, inputs, num=num, name=name)
+        got = GI.run(prog, feed)["out"]
+        want = np.atleast_1d(eval_numpy.evaluate(text, feed, num=num))
+        assert same(got[:want.size], want), name

@@ -13,7 +13,7 @@ import paper_1710_08332_amd as dp
 import synthetic
 from oracle import exact, formats
 from oracle import strategies as S
-from tests.gpu_util import (assert_same_bits, discriminating, gpu_asum, gpu_dot, gpu_gemv,
+from tests.gpu_util import (assert_same_bits, cuda, discriminating, gpu_asum, gpu_dot, gpu_gemv,
                             to_plan)
 
 pytestmark = pytest.mark.gpu
@@ -531,3 +531,113 @@ def test_paper_vector_dot_at_full_size():
     assert len(want) == 128 * 64 * 4
     assert_same_bits(c.cpu().numpy().view(np.float32), want, "Sec. 6.2 chunk values")
     assert_same_bits(r.cpu().numpy()[0], S.dot(x, y, p), "Sec. 6.2 dot")
+
+
+# ------------------------------------------------------------ generated kernels
+
+def _generated(name):
+    from paper_1710_08332_amd.generator import catalog, runtime
+    return runtime.Generated(catalog.path(name))
+
+
+def _meta(name):
+    import json
+    from paper_1710_08332_amd.generator import catalog
+    with open(catalog.path(name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,strategy", [
+    ("dot_strided_tree", dict(seq_len=4, local_size=64, order=T_)),
+    ("dot_contiguous_seq", dict(seq_len=16, local_size=32, order=C_, wg_combine=SEQ)),
+    ("dot_kahan_f64", dict(seq_len=16, local_size=64, order=T_, accum=dp.KAHAN, final_f64=1)),
+    ("dot_u32", dict(seq_len=4, local_size=16, order=C_)),
+    ("dot_v4_strided_tree", dict(seq_len=8, local_size=64, order=T_, vec_width=4)),
+    ("asum_strided_tree", dict(seq_len=8, local_size=128, order=T_)),
+])
+def test_generated_reductions_equal_oracle_and_library(name, strategy):
+    # a descriptor printed as its expression, compiled by the generator: the
+    # same bits as the oracle's evaluation of that text and as the library's
+    # hand-written kernels for the descriptor
+    import torch
+    from oracle import eval_numpy
+    meta = _meta(name)
+    n = meta["inputs"]["xs"][1][0]
+    s = dp.Strategy(**strategy)
+    if meta["num"] == "u32":
+        g = np.random.default_rng(8)
+        x, y = synthetic.integers_u32(g, n), synthetic.integers_u32(g, n)
+        feed = {"xs": cuda(x.view(np.int32)), "ys": cuda(y.view(np.int32))}
+    else:
+        x, y = discriminating(29, n)
+        feed = {"xs": cuda(x), "ys": cuda(y)}
+    prog = _generated(name)
+    out = prog.run(feed)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    args = {"xs": x, "ys": y} if "ys" in meta["inputs"] else {"xs": x}
+    want = eval_numpy.evaluate(meta["expression"], args, num=meta["num"])
+    res = got["out"][0]
+    if meta["num"] == "u32":
+        res = res.view(np.uint32)
+    assert_same_bits(res, want, f"{name} vs oracle")
+    if name.startswith("asum"):
+        lib = gpu_asum(x, s)
+    else:
+        lib = gpu_dot(x, y, s, out_dtype=torch.float64 if s.final_f64 else None)
+    assert_same_bits(res, lib, f"{name} vs library kernel")
+    prog.close()
+
+
+def test_generated_sec62_dot_equals_library_chunks():
+    import torch
+    from oracle import eval_numpy
+    meta = _meta("dot_sec62_chunks")
+    n = meta["inputs"]["xs"][1][0]
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["scale"])
+    prog = _generated("dot_sec62_chunks")
+    out = prog.run({"xs": cuda(x), "ys": cuda(y)})
+    s = dp.Strategy(seq_len=2048, local_size=64, order=C_, wg_combine=dp.NONE, vec_width=4)
+    c = dp.chunks(dp.OP_DOT, s, cuda(x), cuda(y))
+    torch.cuda.synchronize()
+    got = out["out"].cpu().numpy()
+    assert_same_bits(got, c.cpu().numpy().view(np.float32), "Sec. 6.2 generated vs library")
+    assert_same_bits(got, eval_numpy.evaluate(meta["expression"], {"xs": x, "ys": y}),
+                     "Sec. 6.2 generated vs oracle")
+    prog.close()
+
+
+def test_generated_gemv_and_scal():
+    import torch
+    from oracle import eval_numpy
+    A, x = synthetic.gemv_inputs(96, 1024, synthetic.SEEDS["scale"])
+    prog = _generated("gemv_strided_tree")
+    y = prog.run({"A": cuda(A), "x": cuda(x)})["out"]
+    s = dp.Strategy(seq_len=16, local_size=64, order=T_, rows_per_wg=2)
+    torch.cuda.synchronize()
+    assert_same_bits(y.cpu().numpy(), gpu_gemv(A, x, s), "generated gemv vs library")
+    assert_same_bits(y.cpu().numpy(), S.gemv(A, x, to_plan(s)), "generated gemv vs oracle")
+    prog.close()
+    xs = discriminating(4, 1 << 20)[0]
+    prog = _generated("scal_global")
+    r = prog.run({"alpha": cuda(np.array([1.3], np.float32)), "xs": cuda(xs)})["out"]
+    torch.cuda.synchronize()
+    assert_same_bits(r.cpu().numpy(), S.scal(np.float32(1.3), xs), "generated scal")
+    prog.close()
+
+
+def test_generated_headline_dot_and_gemv_at_full_size():
+    import torch
+    from paper_1710_08332_amd.generator import catalog
+    x, y = synthetic.dot_inputs(1 << 26, synthetic.SEEDS["scale"])
+    prog = _generated("dot_headline_2p26")
+    r = prog.run({"xs": cuda(x), "ys": cuda(y)})["out"]
+    torch.cuda.synchronize()
+    assert_same_bits(r.cpu().numpy()[0], gpu_dot(x, y, catalog.HEADLINE_DOT), "generated dot")
+    prog.close()
+    A, xv = synthetic.gemv_inputs(8192, 8192, synthetic.SEEDS["scale"])
+    prog = _generated("gemv_headline_8192")
+    g = prog.run({"A": cuda(A), "x": cuda(xv)})["out"]
+    torch.cuda.synchronize()
+    assert_same_bits(g.cpu().numpy(), gpu_gemv(A, xv, catalog.HEADLINE_GEMV), "generated gemv")
+    prog.close()
