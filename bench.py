@@ -35,6 +35,9 @@ Other workloads (one JSON line per measured item, not the headline):
                           views, 64 work-items folding 2048 vectors each, no
                           work-group combine): chunk kernel and fold timed
                           apart
+    --workload generated  the headline dot and gemv strategies compiled from
+                          their DPIA expressions by the generator, timed
+                          beside the hand-written kernels (same bits)
 Oracle work (parity, exact references) runs only in the CPU-baseline leg,
 which --no-cpu-baseline skips.
 """
@@ -529,6 +532,43 @@ def workload_vector(args):
               parity_bit_exact=parity)
 
 
+def workload_generated(args):
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import time_us
+    from paper_1710_08332_amd.generator import catalog, runtime
+    x, y = synthetic.dot_inputs(N_DOT, SEED)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    A, xv = synthetic.gemv_inputs(M_GEMV, K_GEMV, SEED)
+    At, xvt = torch.from_numpy(A).cuda(), torch.from_numpy(xv).cuda()
+    gd = runtime.Generated(catalog.path("dot_headline_2p26"))
+    gg = runtime.Generated(catalog.path("gemv_headline_8192"))
+    dout, gout = gd.outputs(), gg.outputs()
+    ws = dp.workspace(DOT_STRATEGY, dp.OP_DOT, dp.F32, 0, N_DOT)
+    out = torch.empty(1, device="cuda")
+    yg = torch.empty(M_GEMV, device="cuda")
+    rows = [
+        ("dot", "generated", lambda: gd.run({"xs": xt, "ys": yt}, dout), DOT_BYTES),
+        ("dot", "library", lambda: dp.dot(xt, yt, DOT_STRATEGY, out=out, ws=ws), DOT_BYTES),
+        ("gemv", "generated", lambda: gg.run({"A": At, "x": xvt}, gout), GEMV_BYTES),
+        ("gemv", "library", lambda: dp.gemv(At, xvt, GEMV_STRATEGY, y=yg), GEMV_BYTES),
+    ]
+    for op, kind, fn, nbytes in rows:
+        med, p10, p90 = time_us(fn, reps=30)
+        _line(workload="generated", op=op, kind=kind, us=round(med, 2), p10=round(p10, 2),
+              p90=round(p90, 2), gbs=_gbs(nbytes, med),
+              pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1))
+    torch.cuda.synchronize()
+    same_dot = bool(dout["out"].cpu().numpy()[:1].view(np.uint32)[0]
+                    == out.cpu().numpy().view(np.uint32)[0])
+    same_gemv = bool(np.array_equal(gout["out"].cpu().numpy().view(np.uint32),
+                                    yg.cpu().numpy().view(np.uint32)))
+    _line(workload="generated", generated_equals_library_bitwise={"dot": same_dot,
+                                                                  "gemv": same_gemv})
+    gd.close()
+    gg.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,7 +576,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "small", "sweep", "precision", "batch", "scal", "vector"])
+                    choices=["scale", "small", "sweep", "precision", "batch", "scal", "vector",
+                             "generated"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -555,7 +596,7 @@ def main():
     if args.workload != "scale":
         {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision,
          "batch": workload_batch, "scal": workload_scal,
-         "vector": workload_vector}[args.workload](args)
+         "vector": workload_vector, "generated": workload_generated}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)
