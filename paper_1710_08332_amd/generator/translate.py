@@ -691,6 +691,7 @@ def _has_local_loop(body) -> bool:
 
 
 def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -> str:
+    inputs = {b.name for b in buffers if b.kind == "in"}
     lines = ["#include <hip/hip_runtime.h>",
              "// generated from a DPIA expression: one operation per node, no contraction",
              "#pragma clang fp contract(off)", ""]
@@ -699,7 +700,7 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -
     for k in kernels:
         body: List[str] = []
         shared: List[str] = []
-        _emit_block(k.body, body, shared, 1, types)
+        _emit_block(k.body, body, shared, 1, types, inputs)
         lines.append(f'extern "C" __global__ void __launch_bounds__({block_size(k)}) '
                      f"{k.name}({params}) {{")
         lines.extend("  " + s for s in shared)
@@ -709,7 +710,8 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -
     return "\n".join(lines)
 
 
-def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict[str, str]):
+def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict[str, str],
+                inputs=frozenset()):
     pad = "  " * depth
     for c in cmds:
         if isinstance(c, Decl):
@@ -728,9 +730,11 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
                 out.append(f"{pad}__syncthreads();")
             else:
                 out.append(f"{pad}{lv} = {rhs};")
+        elif isinstance(c, For) and _batchable(c, inputs):
+            _emit_batched(c, out, shared, depth, types, inputs)
         elif isinstance(c, For):
             out.append(f"{pad}for (int {c.var} = 0; {c.var} < {c.n}; ++{c.var}) {{")
-            _emit_block(c.body, out, shared, depth + 1, types)
+            _emit_block(c.body, out, shared, depth + 1, types, inputs)
             if _has_local_loop(c.body):
                 # a work-group-level loop around mapLocal: the next iteration
                 # may overwrite local memory this one still reads
@@ -740,18 +744,119 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
             v, n = c.var, c.n
             if c.level == "workgroup":
                 out.append(f"{pad}for (int {v} = blockIdx.x; {v} < {n}; {v} += gridDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types)
+                _emit_block(c.body, out, shared, depth + 1, types, inputs)
                 out.append(f"{pad}  __syncthreads();")
                 out.append(f"{pad}}}")
             elif c.level == "local":
                 out.append(f"{pad}for (int {v} = threadIdx.x; {v} < {n}; {v} += blockDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types)
+                _emit_block(c.body, out, shared, depth + 1, types, inputs)
                 out.append(f"{pad}}}")
                 out.append(f"{pad}__syncthreads();")
             else:
                 out.append(f"{pad}for (int {v} = blockIdx.x * blockDim.x + threadIdx.x; {v} < {n};"
                            f" {v} += gridDim.x * blockDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types)
+                _emit_block(c.body, out, shared, depth + 1, types, inputs)
                 out.append(f"{pad}}}")
         else:
             raise TranslateError(f"unknown command {c!r}")
+
+
+# ------------------------------------------------------------------ load batching
+# A sequential loop whose body is straight-line code (a fold step) reading the
+# read-only inputs at positions that depend on the loop index is emitted with
+# its input reads for B consecutive iterations issued first, then the B steps
+# in increasing order.  Only reads of inputs move (nothing writes them), so
+# every operation and its order are unchanged; the loads are in flight
+# together instead of one after another.
+
+BATCH_ELEMS = 16
+
+
+def _ix_uses(e, var: str) -> bool:
+    if isinstance(e, ir.IVar):
+        return e.name == var
+    if isinstance(e, ir.IBin):
+        return _ix_uses(e.a, var) or _ix_uses(e.b, var)
+    return False
+
+
+def _ix_sub(e, var: str, u: int):
+    if isinstance(e, ir.IVar) and e.name == var:
+        return iadd(e, u)
+    if isinstance(e, ir.IBin):
+        return ir.IBin(e.op, _ix_sub(e.a, var, u), _ix_sub(e.b, var, u))
+    return e
+
+
+def _ex_map(e, f):
+    """Rebuilds expression e with f applied to every Ref."""
+    if isinstance(e, ir.Ref):
+        return f(e)
+    if isinstance(e, ir.Bin):
+        return ir.Bin(e.op, _ex_map(e.a, f), _ex_map(e.b, f))
+    if isinstance(e, ir.Un):
+        return ir.Un(e.op, _ex_map(e.a, f))
+    if isinstance(e, ir.Cast):
+        return ir.Cast(e.ctype, _ex_map(e.a, f))
+    if isinstance(e, ir.Select):
+        return ir.Select(e.sel, tuple(_ex_map(o, f) for o in e.options))
+    return e
+
+
+def _loads(body, var: str, inputs) -> List[ir.Ref]:
+    found: List[ir.Ref] = []
+
+    def visit(r):
+        if r.name in inputs and r.idx is not None and _ix_uses(r.idx, var) and r not in found:
+            found.append(r)
+        return r
+    for c in body:
+        if isinstance(c, Assign):
+            _ex_map(c.rhs, visit)
+    return found
+
+
+def _batchable(c: For, inputs) -> bool:
+    if not all(isinstance(b, (Decl, Assign)) for b in c.body):
+        return False
+    if any(isinstance(b, Decl) and b.space != "private" for b in c.body):
+        return False
+    loads = _loads(c.body, c.var, inputs)
+    return bool(loads) and c.n >= 2 * max(1, BATCH_ELEMS // len(loads))
+
+
+def _emit_batched(c: For, out, shared, depth, types, inputs):
+    pad = "  " * depth
+    loads = _loads(c.body, c.var, inputs)
+    B = max(1, BATCH_ELEMS // len(loads))
+    k = c.var
+    out.append(f"{pad}int {k} = 0;")
+    out.append(f"{pad}for (; {k} + {B} <= {c.n}; {k} += {B}) {{")
+    regs = {}
+    for u in range(B):
+        for j, r in enumerate(loads):
+            name = f"{k}_r{u}_{j}"
+            idx = _ix_sub(r.idx, k, u)
+            regs[(u, ir.Ref(r.name, idx))] = name
+            out.append(f"{pad}  const {types[r.name]} {name} = {r.name}[{ir.ix_c(idx)}];")
+    out.append(f"{pad}  __builtin_amdgcn_sched_barrier(0);")
+    for u in range(B):
+        def sub(ref, u=u):
+            if ref.idx is None:
+                return ref
+            moved = ir.Ref(ref.name, _ix_sub(ref.idx, k, u))
+            return ir.Ref(regs[(u, moved)], None) if (u, moved) in regs else moved
+        step = []
+        for b in c.body:
+            if isinstance(b, Assign):
+                idx = _ix_sub(b.idx, k, u) if b.idx is not None else None
+                step.append(Assign(b.name, idx, _ex_map(b.rhs, sub), b.space, b.ctx))
+            else:
+                step.append(b)
+        out.append(f"{pad}  {{")
+        _emit_block(step, out, shared, depth + 2, types, inputs)
+        out.append(f"{pad}  }}")
+    out.append(f"{pad}}}")
+    out.append(f"{pad}for (; {k} < {c.n}; ++{k}) {{")
+    _emit_block(c.body, out, shared, depth + 1, types, inputs)
+    out.append(f"{pad}}}")
