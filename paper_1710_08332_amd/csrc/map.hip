@@ -35,9 +35,34 @@ __device__ __forceinline__ void scal_vec(float alpha, const float* x, float* y,
   }
 }
 
+// U vectors of one thread at offsets off0 + u * stride: all loads first,
+// then the products and stores (whole chunks only: every offset exists).
+template <int NV, int U>
+__device__ __forceinline__ void scal_batch(float alpha, const float* x, float* y, int64_t off0,
+                                           int64_t stride) {
+  float v[U][NV];
+#pragma unroll
+  for (int u = 0; u < U; ++u) vload<float, NV>(x + off0 + u * stride, v[u]);
+  __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t off = off0 + u * stride;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[u][i] = alpha * v[u][i];
+    if constexpr (NV == 4) {
+      f32x4 w = {v[u][0], v[u][1], v[u][2], v[u][3]};
+      __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(y + off));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) y[off + i] = v[u][i];
+    }
+  }
+}
+
 template <int ORDER, int NV>
 __global__ void __launch_bounds__(1024) scal_kernel(float alpha, const float* x, float* y,
                                                     MapArgs a) {
+  constexpr int U = (32 / NV) < 1 ? 1 : (32 / NV);   // 32 elements per batch
   const int team_id = threadIdx.x / a.team;
   const int t = threadIdx.x - team_id * a.team;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
@@ -47,22 +72,23 @@ __global__ void __launch_bounds__(1024) scal_kernel(float alpha, const float* x,
     if (g >= a.items) continue;       // no barriers in this kernel
     const int64_t c0 = g * a.W;
     const int64_t rest = a.n - c0;
-    const int64_t limit = c0 + (rest < a.W ? rest : a.W);
-    constexpr int U = 4;              // vectors in flight per thread
+    const bool whole = rest >= a.W;
+    const int64_t limit = c0 + (whole ? a.W : rest);
     if constexpr (ORDER == kStrided) {
       // lane l = t*NV + v maps elements l, l + L, ...
       int k = 0;
-      for (; k + U <= a.C; k += U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          scal_vec<NV>(alpha, x, y, c0 + static_cast<int64_t>(k + u) * a.L + t * NV, limit);
-      }
+      if (whole)
+        for (; k + U <= a.C; k += U)
+          scal_batch<NV, U>(alpha, x, y, c0 + static_cast<int64_t>(k) * a.L + t * NV, a.L);
       for (; k < a.C; ++k)
         scal_vec<NV>(alpha, x, y, c0 + static_cast<int64_t>(k) * a.L + t * NV, limit);
     } else {
       // lane l = t maps elements l*C .. l*C + C-1
       const int64_t s = c0 + static_cast<int64_t>(t) * a.C;
-      for (int k = 0; k < a.C; k += NV) scal_vec<NV>(alpha, x, y, s + k, limit);
+      int k = 0;
+      if (whole)
+        for (; k + U * NV <= a.C; k += U * NV) scal_batch<NV, U>(alpha, x, y, s + k, NV);
+      for (; k < a.C; k += NV) scal_vec<NV>(alpha, x, y, s + k, limit);
     }
   }
 }
