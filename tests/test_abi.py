@@ -259,3 +259,13 @@ def test_gemv_blas_validates_before_launching():
     assert L.dpia_gemv_blas(ctypes.byref(cs), dp.F32, 4, 256, 255, 1.0, P, None, P2, 0.5, P2,
                             None) == _lib.ERR_SHAPE
     assert L.dpia_gemv_blas(ctypes.byref(cs), dp.F32, 0, *args) == _lib.OK
+
+
+def test_module_entry_points_validate_before_any_hip_call():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.dpia_module_load(None, ctypes.byref(h)) == _lib.ERR_NULL
+    assert L.dpia_module_load(b"/nonexistent.hsaco", None) == _lib.ERR_NULL
+    args = (ctypes.c_void_p * 1)(0x7000_0000)
+    assert L.dpia_module_launch(None, b"k", 1, 64, args, 1, None) == _lib.ERR_NULL
+    assert L.dpia_module_unload(None) == _lib.OK
