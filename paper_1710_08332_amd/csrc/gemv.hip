@@ -39,7 +39,7 @@ __device__ __forceinline__ void row_block_folds(const Op& op, const int64_t (&ro
 #pragma unroll
   for (int b = 0; b < RB; ++b) any = any || act[b];
   if (!any) return;
-  constexpr int U = Batch<NV>::U;
+  constexpr int U = Batch<NV, OpBatch<Op>::E>::U;
   const int rows = limit / L;
   const int nfull = rows < C ? rows : C;
   const int start = t * NV;
@@ -281,10 +281,18 @@ dpia_status gemv_impl(const char* name, const dpia_strategy* s, dpia_dtype a_dt,
           m, lda, hs, kRowBlock);
       break;
     case DPIA_FP8_E4M3:
-      e = launch_gemv<GemvFP8, 16>(
-          p, with_epilogue(GemvFP8{static_cast<const uint8_t*>(A), static_cast<const float*>(x),
-                                   row_scale, static_cast<float*>(y)}),
-          m, lda, hs, kRowBlock);
+      if (p.C >= 64)
+        e = launch_gemv<GemvFP8Long, 16>(
+            p, with_epilogue(GemvFP8Long{static_cast<const uint8_t*>(A),
+                                         static_cast<const float*>(x), row_scale,
+                                         static_cast<float*>(y)}),
+            m, lda, hs, kRowBlock);
+      else
+        e = launch_gemv<GemvFP8, 16>(
+            p, with_epilogue(GemvFP8{static_cast<const uint8_t*>(A),
+                                     static_cast<const float*>(x), row_scale,
+                                     static_cast<float*>(y)}),
+            m, lda, hs, kRowBlock);
       break;
     case DPIA_I32:
       e = launch_gemv<GemvU32, 4>(

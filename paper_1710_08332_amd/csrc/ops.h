@@ -140,7 +140,15 @@ __device__ __forceinline__ void fp8_to_f32(const uint8_t (&c)[NV], float (&f)[NV
   }
 }
 
-template <typename E, class Decode>
+#ifndef DPIA_BF16_BATCH_ELEMS
+#define DPIA_BF16_BATCH_ELEMS 16
+#endif
+#ifndef DPIA_FP8_BATCH_ELEMS
+#define DPIA_FP8_BATCH_ELEMS 16
+#endif
+
+// BATCH: elements per load batch (0: the format's default).
+template <typename E, class Decode, int BATCH = 0>
 struct GemvF32Acc {
   using Arith = PlainF32;
   using T = float;
@@ -149,7 +157,9 @@ struct GemvF32Acc {
   // loads of A stream faster than the dot's settings (16 elements,
   // non-temporal); the narrow formats keep those (row-blocked kernel).
   static constexpr bool kF32 = std::is_same<E, float>::value;
-  static constexpr int kBatchElems = kF32 ? 32 : 16;
+  static constexpr int kBatchElems =
+      BATCH ? BATCH
+            : (kF32 ? 32 : (sizeof(E) == 2 ? DPIA_BF16_BATCH_ELEMS : DPIA_FP8_BATCH_ELEMS));
   static constexpr bool kStreamA = !kF32;
   struct View {
     static constexpr bool kStageable = std::is_same<E, float>::value;
@@ -235,6 +245,9 @@ struct DecodeFP8 {
 using GemvF32 = GemvF32Acc<float, DecodeF32>;
 using GemvBF16 = GemvF32Acc<uint16_t, DecodeBF16>;
 using GemvFP8 = GemvF32Acc<uint8_t, DecodeFP8>;
+// fp8 rows with long lanes: four 16-byte loads per row in flight (measured
+// faster from C = 64 up, slower for short lanes)
+using GemvFP8Long = GemvF32Acc<uint8_t, DecodeFP8, 64>;
 
 struct GemvU32 {
   static constexpr bool kRowBlockable = false;
