@@ -553,6 +553,29 @@ def workload_generated(args):
         ("gemv", "generated", lambda: gg.run({"A": At, "x": xvt}, gout), GEMV_BYTES),
         ("gemv", "library", lambda: dp.gemv(At, xvt, GEMV_STRATEGY, y=yg), GEMV_BYTES),
     ]
+    # low-precision gemv 16384 x 16384, C=128 L=128 strided tree
+    big = dp.Strategy(seq_len=128, local_size=128, order=dp.STRIDED, wg_combine=dp.TREE)
+    A16, xv16 = synthetic.gemv_inputs(16384, 16384, synthetic.SEEDS["precision"])
+    xv16t = torch.from_numpy(xv16).cuda()
+    c16 = torch.from_numpy(synthetic.quantise_bf16(A16).view(np.int16)).cuda()
+    c8n, sc8n = synthetic.quantise_fp8_rows(A16)
+    c8, sc8 = torch.from_numpy(c8n).cuda(), torch.from_numpy(sc8n).cuda()
+    del A16
+    gb, gf = (runtime.Generated(catalog.path("gemv_bf16_16384")),
+              runtime.Generated(catalog.path("gemv_fp8_16384")))
+    bout, fout = gb.outputs(), gf.outputs()
+    yb, yf = torch.empty(16384, device="cuda"), torch.empty(16384, device="cuda")
+    nb16 = 2 * 16384 * 16384 + 8 * 16384
+    nb8 = 16384 * 16384 + 12 * 16384
+    rows += [
+        ("gemv_bf16_16384", "generated", lambda: gb.run({"A": c16, "x": xv16t}, bout), nb16),
+        ("gemv_bf16_16384", "library",
+         lambda: dp.gemv(c16, xv16t, big, y=yb, a_dtype=dp.BF16), nb16),
+        ("gemv_fp8_16384", "generated",
+         lambda: gf.run({"A": c8, "x": xv16t, "scale": sc8}, fout), nb8),
+        ("gemv_fp8_16384", "library",
+         lambda: dp.gemv(c8, xv16t, big, y=yf, row_scale=sc8, a_dtype=dp.FP8_E4M3), nb8),
+    ]
     for op, kind, fn, nbytes in rows:
         med, p10, p90 = time_us(fn, reps=30)
         _line(workload="generated", op=op, kind=kind, us=round(med, 2), p10=round(p10, 2),
@@ -563,10 +586,13 @@ def workload_generated(args):
                     == out.cpu().numpy().view(np.uint32)[0])
     same_gemv = bool(np.array_equal(gout["out"].cpu().numpy().view(np.uint32),
                                     yg.cpu().numpy().view(np.uint32)))
-    _line(workload="generated", generated_equals_library_bitwise={"dot": same_dot,
-                                                                  "gemv": same_gemv})
-    gd.close()
-    gg.close()
+    same_lp = {name: bool(np.array_equal(a["out"].cpu().numpy().view(np.uint32),
+                                         b.cpu().numpy().view(np.uint32)))
+               for name, a, b in (("gemv_bf16", bout, yb), ("gemv_fp8", fout, yf))}
+    _line(workload="generated", generated_equals_library_bitwise=dict(
+        dot=same_dot, gemv=same_gemv, **same_lp))
+    for g in (gd, gg, gb, gf):
+        g.close()
 
 
 def main():

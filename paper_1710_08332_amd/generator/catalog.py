@@ -60,6 +60,21 @@ def programs() -> List[Tuple[str, str, Dict, str]]:
                 {"A": ("f32", (8192, 8192)), "x": ("f32", (8192,))}, "f32"))
     out.append(("scal_global", "(mapGlobal (lam (e) (* alpha e)) xs)",
                 {"alpha": ("f32", ()), "xs": ("f32", (1 << 20,))}, "f32"))
+    # low-precision gemv: small (parity) and 16384 x 16384 (speed), and every
+    # storage code through the generated decoders
+    lp = Strategy(seq_len=4, local_size=64, order=STRIDED, rows_per_wg=2)
+    big = Strategy(seq_len=128, local_size=128, order=STRIDED)
+    for fmt, et in (("bf16", "u16"), ("fp8", "u8")):
+        ins = {"A": (et, (64, 256)), "x": ("f32", (256,))}
+        bins = {"A": (et, (16384, 16384)), "x": ("f32", (16384,))}
+        if fmt == "fp8":
+            ins["scale"] = ("f32", (64,))
+            bins["scale"] = ("f32", (16384,))
+        out.append((f"gemv_{fmt}_strided_tree", P.gemv_text(lp, 64, 256, fmt), ins, "f32"))
+        out.append((f"gemv_{fmt}_16384", P.gemv_text(big, 16384, 16384, fmt), bins, "f32"))
+        ncodes = 1 << (16 if fmt == "bf16" else 8)
+        out.append((f"decode_{fmt}_all", f"(mapGlobal (lam (c) ({fmt} c)) codes)",
+                    {"codes": (et, (ncodes,))}, "f32"))
     return out
 
 

@@ -133,7 +133,32 @@ class Select:
     options: Tuple["Ex", ...]
 
 
-Ex = Union[Lit, Ref, Bin, Un, Cast, Select]
+@dataclass(frozen=True)
+class Decode:
+    """The binary32 value of a storage code: "bf16" or "fp8" (OCP E4M3)."""
+    fmt: str
+    a: "Ex"
+
+
+Ex = Union[Lit, Ref, Bin, Un, Cast, Select, Decode]
+
+# Device functions the emitted code may call, written from the formats'
+# definitions: bfloat16 is the upper half of a binary32; OCP fp8 E4M3 has a
+# sign bit, 4 exponent bits with bias 7 and 3 mantissa bits, exponent 0
+# holds the subnormals m * 2^-9, S.1111.111 is NaN and there are no
+# infinities.
+DECODERS = """__device__ __forceinline__ float dpia_bf16(unsigned short c) {
+  return __uint_as_float(static_cast<unsigned>(c) << 16);
+}
+__device__ __forceinline__ float dpia_fp8(unsigned char c) {
+  const unsigned e = (c >> 3) & 15u, m = c & 7u;
+  float v;
+  if (e == 15u && m == 7u) v = __uint_as_float(0x7fc00000u);
+  else if (e == 0u) v = static_cast<float>(m) * 0x1p-9f;
+  else v = __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return (c & 0x80u) ? -v : v;
+}
+"""
 
 
 def ex_c(e: Ex, types: dict) -> str:
@@ -157,6 +182,8 @@ def ex_c(e: Ex, types: dict) -> str:
         return f"{fn}({ex_c(e.a, types)})"
     if isinstance(e, Cast):
         return f"(({e.ctype}){ex_c(e.a, types)})"
+    if isinstance(e, Decode):
+        return f"dpia_{e.fmt}({ex_c(e.a, types)})"
     code = ex_c(e.options[-1], types)
     for k in range(len(e.options) - 2, -1, -1):
         code = f"({ix_c(e.sel)} == {k} ? {ex_c(e.options[k], types)} : {code})"
@@ -174,6 +201,8 @@ def ex_type(e: Ex, types: dict) -> str:
         return ex_type(e.a, types)
     if isinstance(e, Cast):
         return e.ctype
+    if isinstance(e, Decode):
+        return "float"
     return ex_type(e.options[0], types)
 
 

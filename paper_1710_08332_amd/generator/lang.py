@@ -5,7 +5,9 @@ use): a number literal, a name, ``(lam (x ...) body)``, ``(prim arg ...)``
 or ``(f arg ...)``.  Size arguments are literals: ``(split n e)``,
 ``(asVector n e)``, ``(asScalar n e)``, ``(broadcast n e)``.
 
-Types: ``Num(c)`` a scalar of C type c ("float", "double" or "unsigned"),
+Types: ``Num(c)`` a scalar of C type c ("float", "double", "unsigned", or the
+storage codes "unsigned short" of bf16 and "unsigned char" of OCP fp8-e4m3,
+which ``bf16`` / ``fp8`` decode exactly to float and nothing else accepts),
 ``Vec(n, c)`` an OpenCL-style vector (Sec. 6.1), ``Arr(n, t)`` and
 ``Pair(a, b)`` (Sec. 5.1).  Functions are not first-class data: every lambda
 is applied where it appears (as the argument of map / reduce / toX, or in a
@@ -93,6 +95,7 @@ ARITY = {
     "zip": 2, "split": 2, "join": 1, "transpose": 1, "pair": 2, "fst": 1, "snd": 1,
     "asVector": 2, "asScalar": 2, "broadcast": 2,
     "+": 2, "-": 2, "*": 2, "/": 2, "negate": 1, "abs": 1, "f32": 1, "f64": 1,
+    "bf16": 1, "fp8": 1,
     "toGlobal": 1, "toLocal": 1, "toPrivate": 1,
 }
 MAPS = ("map", "mapSeq", "mapGlobal", "mapWorkgroup", "mapLocal")

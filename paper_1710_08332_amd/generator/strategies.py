@@ -109,20 +109,36 @@ def dot_chunks_text(s, n: int) -> str:
     return full[len(prefix):-1]
 
 
-def gemv_text(s, m: int, k: int) -> str:
-    """y = A x, A m x k row-major (binary32)."""
+def gemv_text(s, m: int, k: int, a_format: str = "f32") -> str:
+    """y = A x, A m x k row-major: binary32, or bf16 / fp8-e4m3 codes
+    decoded exactly in the lane step (the decode fused into the fold, which
+    gives the values of decoding first: the map fusion law, Sec. 5.3).  For
+    fp8 every row value is multiplied by its ``scale`` afterwards."""
     C, L, V = _parts(s)
     R, parts = int(s.rows_per_wg), int(s.row_parts)
     if V != 1 or s.wg_combine == 2 or s.accum != 0:
         raise ValueError("gemv rows use scalar, combined, plain strategies")
     if m % R or k != C * L * parts:
         raise ValueError("m must be a multiple of R and k = C * L * row_parts")
+    if a_format == "f32":
+        step = DOT_STEP
+    elif a_format in ("bf16", "fp8"):
+        step = f"(lam (z acc) (+ (* ({a_format} (fst z)) (snd z)) acc))"
+    else:
+        raise ValueError(f"unknown matrix format {a_format!r}")
 
     def chunk(view: str) -> str:
-        return _combine(_lanes(view, s, DOT_STEP, "0"), s, PLUS, "0")
-    if parts == 1:
-        row = chunk("(zip row x)")
+        return _combine(_lanes(view, s, step, "0"), s, PLUS, "0")
+
+    def rowred(row: str) -> str:
+        if parts == 1:
+            return chunk(f"(zip {row} x)")
+        return (f"(reduceSeq {PLUS} 0 (map (lam (h) {chunk('h')})"
+                f" (split {C * L} (zip {row} x))))")
+    if a_format == "fp8":
+        body = f"(map (lam (rw) (* (snd rw) {rowred('(fst rw)')})) rows)"
+        src = "(zip A scale)"
     else:
-        row = (f"(reduceSeq {PLUS} 0 (map (lam (h) {chunk('h')})"
-               f" (split {C * L} (zip row x))))")
-    return f"(join (mapWorkgroup (lam (rows) (map (lam (row) {row}) rows)) (split {R} A)))"
+        body = f"(map (lam (row) {rowred('row')}) rows)"
+        src = "A"
+    return f"(join (mapWorkgroup (lam (rows) {body}) (split {R} {src})))"

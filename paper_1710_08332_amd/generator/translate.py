@@ -54,7 +54,9 @@ from .ir import Assign, Decl, For, IX, ParFor, iadd, idiv, imod, imul
 from .lang import (MAPS, REDUCES, SPACES, Arr, Call, Lam, Lit, Name, Node, Num, Pair, Type,
                    Vec, check, parse)
 
-CTYPES = {"f32": "float", "f64": "double", "u32": "unsigned"}
+CTYPES = {"f32": "float", "f64": "double", "u32": "unsigned", "u16": "unsigned short",
+          "u8": "unsigned char"}
+CODES = {"bf16": "unsigned short", "fp8": "unsigned char"}
 
 
 class TranslateError(ValueError):
@@ -290,9 +292,14 @@ class Translator:
             return x.a if h == "fst" else x.b
         if h in ("+", "-", "*", "/"):
             x, y = self.tyof(a[0], tenv), self.tyof(a[1], tenv)
-            if x != y or not isinstance(x, (Num, Vec)):
+            if x != y or not isinstance(x, (Num, Vec)) or x.c in CODES.values():
                 raise TranslateError(f"{h} on {x} and {y}")
             return x
+        if h in CODES:
+            x = self.tyof(a[0], tenv)
+            if x != Num(CODES[h]):
+                raise TranslateError(f"{h} decodes {CODES[h]} codes, not {x}")
+            return Num("float")
         if h in ("negate", "abs"):
             x = self.tyof(a[0], tenv)
             if not isinstance(x, (Num, Vec)):
@@ -549,7 +556,7 @@ class Translator:
             return p.a if h == "fst" else p.b
         if h in ("+", "-", "*", "/"):
             x, y = self.val(args[0], env, out, ctx), self.val(args[1], env, out, ctx)
-            if x.ty != y.ty:
+            if x.ty != y.ty or x.ty.c in CODES.values():
                 raise TranslateError(f"{h} on {x.ty} and {y.ty}")
             if x.ty.c == "unsigned" and h == "/":
                 raise TranslateError("integer division is not defined")
@@ -567,6 +574,11 @@ class Translator:
         if h in ("f32", "f64"):
             x = self.val(args[0], env, out, ctx)
             return SV(Num(CTYPES[h]), ir.Cast(CTYPES[h], x.e))
+        if h in CODES:
+            x = self.val(args[0], env, out, ctx)
+            if x.ty != Num(CODES[h]):
+                raise TranslateError(f"{h} decodes {CODES[h]} codes, not {x.ty}")
+            return SV(Num("float"), ir.Decode(h, x.e))
         raise TranslateError(f"{h} cannot be used as data here")
 
 
@@ -617,11 +629,25 @@ def translate(text: str, inputs: Dict[str, Tuple[str, Tuple[int, ...]]], num: st
     out_acc = _acceptor(out_ty, "out", [], t.dims, t.scalars, "global")
     top: list = []
     t.acc(node, t.env, out_acc, top, "host")
+    big = [b.name for b in t.buffers if b.elems >= (1 << 31)]
+    if big or _max_extent(top) >= (1 << 31):
+        # every index is computed in 32-bit int arithmetic
+        raise TranslateError(f"arrays or loops of 2^31 elements or more ({big or 'a loop'})")
     kernels = _split(top, name)
     types = {b.name: b.ctype for b in t.buffers}
     _collect_types(top, types)
     src = _emit(kernels, t.buffers, types)
     return Program(src, kernels, t.buffers, out_ty, types, dict(t.dims))
+
+
+def _max_extent(cmds) -> int:
+    m = 0
+    for c in cmds:
+        if isinstance(c, Decl):
+            m = max(m, c.size)
+        elif isinstance(c, (For, ParFor)):
+            m = max(m, c.n, _max_extent(c.body))
+    return m
 
 
 def _collect_types(cmds, types):
@@ -694,7 +720,7 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -
     inputs = {b.name for b in buffers if b.kind == "in"}
     lines = ["#include <hip/hip_runtime.h>",
              "// generated from a DPIA expression: one operation per node, no contraction",
-             "#pragma clang fp contract(off)", ""]
+             "#pragma clang fp contract(off)", "", ir.DECODERS]
     params = ", ".join((f"const {b.ctype}* __restrict__ {b.name}" if b.kind == "in"
                         else f"{b.ctype}* {b.name}") for b in buffers)
     for k in kernels:
@@ -800,6 +826,8 @@ def _ex_map(e, f):
         return ir.Cast(e.ctype, _ex_map(e.a, f))
     if isinstance(e, ir.Select):
         return ir.Select(e.sel, tuple(_ex_map(o, f) for o in e.options))
+    if isinstance(e, ir.Decode):
+        return ir.Decode(e.fmt, _ex_map(e.a, f))
     return e
 
 

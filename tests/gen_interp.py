@@ -14,9 +14,11 @@ from __future__ import annotations
 
 import numpy as np
 
+from oracle import formats
 from paper_1710_08332_amd.generator import ir
 
-NP = {"float": np.float32, "double": np.float64, "unsigned": np.uint32}
+NP = {"float": np.float32, "double": np.float64, "unsigned": np.uint32,
+      "unsigned short": np.uint16, "unsigned char": np.uint8}
 
 
 def _ix(e, env):
@@ -55,6 +57,10 @@ def _ex(e, env, mem, types):
         return type(a)(-a if e.op == "neg" else abs(a))
     if isinstance(e, ir.Cast):
         return NP[e.ctype](_ex(e.a, env, mem, types))
+    if isinstance(e, ir.Decode):
+        c = _ex(e.a, env, mem, types)
+        dec = formats.bf16_decode if e.fmt == "bf16" else formats.fp8_decode
+        return np.float32(dec(np.asarray([c]))[0])
     return _ex(e.options[_ix(e.sel, env)], env, mem, types)
 
 

@@ -128,9 +128,55 @@ def test_catalogued_programs_match_the_oracle_on_the_cpu():
         for k, (et, shape) in inputs.items():
             if et == "u32":
                 feed[k] = g.integers(0, 2 ** 32, shape, dtype=np.uint64).astype(np.uint32)
+            elif et == "u16":                        # bf16 codes, no inf / NaN
+                c = g.integers(0, 2 ** 16, shape).astype(np.uint16)
+                c[(c & 0x7F80) == 0x7F80] = 0x3F80
+                feed[k] = c
+            elif et == "u8":                         # fp8 codes, no NaN
+                c = g.integers(0, 256, shape).astype(np.uint8)
+                c[(c & 0x7F) == 0x7F] = 0x38
+                feed[k] = c
             else:
                 feed[k] = (2 * g.random(shape) - 1).astype(np.float32)
         prog = T.translate(text, inputs, num=num, name=name)
         got = GI.run(prog, feed)["out"]
         want = np.atleast_1d(eval_numpy.evaluate(text, feed, num=num))
         assert same(got[:want.size], want), name
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_generated_low_precision_gemv_matches_the_oracle(fmt):
+    from paper_1710_08332_amd import Strategy, STRIDED
+    from paper_1710_08332_amd.generator import strategies as P
+    s = Strategy(seq_len=4, local_size=16, order=STRIDED, rows_per_wg=2)
+    m, k = 6, 64
+    g = np.random.default_rng(17)
+    x = g.standard_normal(k).astype(np.float32)
+    if fmt == "bf16":
+        codes = g.integers(0, 2 ** 16, (m, k)).astype(np.uint16)
+        inputs = {"A": ("u16", (m, k)), "x": ("f32", (k,))}
+        feed, scale = {"A": codes, "x": x}, None
+    else:
+        codes = g.integers(0, 256, (m, k)).astype(np.uint8)
+        scale = g.random(m, dtype=np.float32) + np.float32(0.5)
+        inputs = {"A": ("u8", (m, k)), "x": ("f32", (k,)), "scale": ("f32", (m,))}
+        feed = {"A": codes, "x": x, "scale": scale}
+    text = P.gemv_text(s, m, k, fmt)
+    prog = T.translate(text, inputs)
+    got = GI.run(prog, feed)["out"]
+    want = S.gemv(codes, x, S.Plan(seq=4, lanes=16, order="strided", rows=2), a_format=fmt,
+                  scale=scale)
+    assert same(got, want) or (np.isnan(got) == np.isnan(want)).all() and \
+        same(got[~np.isnan(got)], np.asarray(want)[~np.isnan(want)])
+
+
+def test_translation_errors():
+    from paper_1710_08332_amd.generator.translate import TranslateError
+    with pytest.raises(TranslateError):      # arithmetic on storage codes
+        T.translate("(map (lam (c) (+ c c)) xs)", {"xs": ("u16", (8,))})
+    with pytest.raises(TranslateError):      # zip of different lengths
+        T.translate("(zip xs ys)", {"xs": ("f32", (8,)), "ys": ("f32", (4,))})
+    with pytest.raises(TranslateError):      # split that does not divide
+        T.translate("(split 3 xs)", {"xs": ("f32", (8,))})
+    with pytest.raises(TranslateError):      # 32-bit indices only
+        T.translate("(mapGlobal (lam (e) (* e e)) xs)", {"xs": ("f32", (1 << 31,))})

@@ -47,3 +47,25 @@ def test_printed_gemv_equals_the_oracle_expression(s):
     A = g.standard_normal((m, k)).astype(np.float32)
     x = g.standard_normal(k).astype(np.float32)
     assert same(eval_numpy.evaluate(P.gemv_text(s, m, k), {"A": A, "x": x}), S.gemv(A, x, p))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_printed_low_precision_gemv_equals_the_oracle_expression(fmt):
+    # the printer fuses the decode into the lane step; the oracle decodes
+    # with a map first: the same values
+    s = dp.Strategy(seq_len=4, local_size=8, order=T_, rows_per_wg=2)
+    p = to_plan(s)
+    m, k = 4, p.chunk
+    g = np.random.default_rng(3)
+    x = g.standard_normal(k).astype(np.float32)
+    if fmt == "bf16":
+        codes = g.integers(0, 2 ** 16, (m, k)).astype(np.uint16)
+        codes[(codes & 0x7F80) == 0x7F80] = 0x3F80
+        inp, scale = {"A": codes, "x": x}, None
+    else:
+        codes = g.integers(0, 256, (m, k)).astype(np.uint8)
+        codes[(codes & 0x7F) == 0x7F] = 0x38
+        scale = g.random(m, dtype=np.float32) + np.float32(0.5)
+        inp = {"A": codes, "x": x, "scale": scale}
+    got = eval_numpy.evaluate(P.gemv_text(s, m, k, fmt), inp)
+    assert same(got, S.gemv(codes, x, p, a_format=fmt, scale=scale))

@@ -641,3 +641,44 @@ def test_generated_headline_dot_and_gemv_at_full_size():
     torch.cuda.synchronize()
     assert_same_bits(g.cpu().numpy(), gpu_gemv(A, xv, catalog.HEADLINE_GEMV), "generated gemv")
     prog.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_generated_decoders_cover_every_code(fmt):
+    # the generator's decoders, written from the format definitions, against
+    # the oracle's decode of every storage code (NaN codes: NaN on both sides)
+    import torch
+    n = 1 << (16 if fmt == "bf16" else 8)
+    codes = np.arange(n, dtype=np.uint16 if fmt == "bf16" else np.uint8)
+    prog = _generated(f"decode_{fmt}_all")
+    dev = cuda(codes.view(np.int16) if fmt == "bf16" else codes)
+    got = prog.run({"codes": dev})["out"]
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = (formats.bf16_decode if fmt == "bf16" else formats.fp8_decode)(codes)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    assert_same_bits(got[~nan], want[~nan], f"{fmt} decode")
+    prog.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_generated_low_precision_gemv_equals_oracle_and_library(fmt):
+    import torch
+    s = dp.Strategy(seq_len=4, local_size=64, order=T_, rows_per_wg=2)
+    A, x = synthetic.gemv_inputs(64, 256, synthetic.SEEDS["scale"])
+    if fmt == "bf16":
+        codes, scale, adt = synthetic.quantise_bf16(A), None, dp.BF16
+        feed = {"A": cuda(codes.view(np.int16)), "x": cuda(x)}
+    else:
+        (codes, scale), adt = synthetic.quantise_fp8_rows(A), dp.FP8_E4M3
+        feed = {"A": cuda(codes), "x": cuda(x), "scale": cuda(scale)}
+    prog = _generated(f"gemv_{fmt}_strided_tree")
+    y = prog.run(feed)["out"]
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    assert_same_bits(got, S.gemv(codes, x, to_plan(s), a_format=fmt, scale=scale),
+                     f"generated {fmt} gemv vs oracle")
+    assert_same_bits(got, gpu_gemv(codes, x, s, a_dtype=adt, scale=scale),
+                     f"generated {fmt} gemv vs library")
+    prog.close()
