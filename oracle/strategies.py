@@ -55,6 +55,10 @@ that form: the chunk's value is its L lane values (join of the mapLocal), so
 the outer fold runs over G*L (times V) numbers in chunk, lane, component
 order.
 
+A second compensated variant ("sum2") follows Ogita, Rump and Oishi's Sum2:
+TwoSum at every step, the exact errors summed into c, value s + c; unlike
+Kahan's step it keeps the error when a term outweighs the running sum.
+
 The compensated ("kahan") variant keeps a pair (s, c) per accumulator:
 Kahan's summation step (N. J. Higham, Accuracy and Stability of Numerical
 Algorithms, 2nd ed., Alg. 4.2) inside the lanes, Knuth's TwoSum to merge two
@@ -87,6 +91,22 @@ KAHAN_MERGE = ("(lam (r l) ((lam (s) ((lam (bp) (pair s (- (+ (snd l) (snd r))"
 
 ZERO_PAIR = "(pair 0 0)"
 
+# Sum2 (T. Ogita, S. M. Rump, S. Oishi, "Accurate sum and dot product", SIAM
+# J. Sci. Comput. 26(6), 2005, Alg. 4.4) over the rounded products: the pair
+# (s, c) has value s + c; each step adds the product p to s with TwoSum and
+# adds the exact error to c:
+#   p = x*y ; t = s + p ; bp = t - s ; new pair (t, c + ((s - (t - bp)) + (p - bp)))
+SUM2_MUL_STEP = ("(lam (z acc) ((lam (p) ((lam (t) ((lam (bp) (pair t (+ (snd acc)"
+                 " (+ (- (fst acc) (- t bp)) (- p bp))))) (- t (fst acc)))) (+ (fst acc) p)))"
+                 " (* (fst z) (snd z))))")
+
+# Merge of a later pair r into the earlier l: TwoSum of the s parts, the
+# error joining the c parts: s = s_l + s_r ; bp = s - s_l ;
+# new pair (s, (c_l + c_r) + ((s_l - (s - bp)) + (s_r - bp))).
+SUM2_MERGE = ("(lam (r l) ((lam (s) ((lam (bp) (pair s (+ (+ (snd l) (snd r))"
+              " (+ (- (fst l) (- s bp)) (- (fst r) bp))))) (- s (fst l))))"
+              " (+ (fst l) (fst r))))")
+
 
 @dataclass(frozen=True)
 class Plan:
@@ -96,8 +116,8 @@ class Plan:
     lanes (L)      work-items per chunk (mapLocal width)
     order          "contiguous" (rows of C) or "strided" (stride-L rows)
     combine        "tree" (pairwise in local memory) or "seq" (reduceSeq)
-    accum          "plain" or "kahan"
-    final_f64      kahan only: fold the chunk results in binary64
+    accum          "plain", "kahan" or "sum2"
+    final_f64      kahan / sum2 only: fold the chunk values in binary64
     rows (R)       gemv: rows per work-group
     row_parts      gemv: 1, or 2 halves reduced separately
     vec (V)        dot / asum: vector width of the asVector view (1: none)
@@ -128,7 +148,7 @@ class Plan:
             raise ValueError(f"bad combine {self.combine!r}")
         if self.combine == "tree" and self.lanes & (self.lanes - 1):
             raise ValueError("a tree combine needs a power-of-two lane count")
-        if self.accum not in ("plain", "kahan"):
+        if self.accum not in ("plain", "kahan", "sum2"):
             raise ValueError(f"bad accum {self.accum!r}")
         if self.row_parts not in (1, 2):
             raise ValueError("row_parts must be 1 or 2")
@@ -166,12 +186,18 @@ def _combine(lanes: str, plan: Plan, merge: str, init: str) -> str:
 def _chunk_value(view: str, plan: Plan, step: str) -> str:
     if plan.combine == "none":
         raise ValueError("an uncombined chunk has L values, not one")
-    if plan.accum == "kahan":
-        return _combine(_lanes(view, plan, step, ZERO_PAIR), plan, KAHAN_MERGE, ZERO_PAIR)
+    if plan.accum in ("kahan", "sum2"):
+        merge = KAHAN_MERGE if plan.accum == "kahan" else SUM2_MERGE
+        return _combine(_lanes(view, plan, step, ZERO_PAIR), plan, merge, ZERO_PAIR)
     return _combine(_lanes(view, plan, step, "0"), plan, ADD, "0")
 
 
 def _final(partials: str, plan: Plan) -> str:
+    if plan.accum == "sum2":
+        if plan.final_f64:
+            return (f"(reduceSeq (lam (p a) (+ (+ (f64 (fst p)) (f64 (snd p))) a))"
+                    f" (f64 0) {partials})")
+        return f"((lam (r) (+ (fst r) (snd r))) (reduceSeq {SUM2_MERGE} {ZERO_PAIR} {partials}))"
     if plan.accum == "kahan":
         if plan.final_f64:
             return (f"(reduceSeq (lam (p a) (+ (- (f64 (fst p)) (f64 (snd p))) a))"
@@ -212,7 +238,7 @@ def _vectors(name: str, plan: Plan) -> str:
 
 def dot_expr(n: int, plan: Plan) -> str:
     """dot xs ys under ``plan``; inputs ``xs``, ``ys`` of length n."""
-    step = KAHAN_MUL_STEP if plan.accum == "kahan" else MUL_ADD
+    step = {"kahan": KAHAN_MUL_STEP, "sum2": SUM2_MUL_STEP}.get(plan.accum, MUL_ADD)
     return _reduction(n, f"(zip {_vectors('xs', plan)} {_vectors('ys', plan)})", plan, step)
 
 

@@ -873,3 +873,57 @@ def test_chunk_values_fold_to_the_result():
             e = 4 * (g * 48 + l * 6 + k) + j
             acc = xs[e] * ys[e] + acc
         assert same_bits(c[i], acc)
+
+
+# ----------------------------------------------------------- Sum2
+
+def test_sum2_keeps_the_error_of_a_dominant_term():
+    # products 2^30, 1, -2^30 folded in order: the exact sum is 1.  The plain
+    # fold loses the 1 (2^30 + 1 rounds to 2^30); Kahan's step also loses it
+    # (its correction -1 is absorbed when -2^30 + 1 rounds); Sum2's TwoSum
+    # keeps it in c, so s + c = 0 + 1.
+    xs = np.array([2.0 ** 30, 1.0, -2.0 ** 30], np.float32)
+    ys = np.ones(3, np.float32)
+    for ev in EVALS:
+        for acc, want in (("sum2", 1.0), ("kahan", 0.0), ("plain", 0.0)):
+            p = S.Plan(seq=3, lanes=1, accum=acc)
+            assert float(ev(S.dot_expr(3, p), {"xs": xs, "ys": ys})) == want, (acc, ev)
+        p = S.Plan(seq=3, lanes=1, accum="sum2", final_f64=True)
+        assert float(ev(S.dot_expr(3, p), {"xs": xs, "ys": ys})) == 1.0
+
+
+def test_sum2_meets_its_error_bound_where_plain_and_kahan_do_not():
+    # Cancelling products (every rounded product has its exact negation in
+    # the input, so their exact sum S is 0): Sum2's result is within
+    # u|S| + gamma_h^2 * sum|p| (Ogita, Rump, Oishi 2005, Prop. 4.5, with h the
+    # strategy's depth in place of n - 1), i.e. essentially 0.  The plain and
+    # Kahan folds of the same strategies leave that bound (on some of them:
+    # a plain fold can cancel exactly by chance).
+    outside = 0
+    for p in (S.Plan(seq=64, lanes=16, order="strided", accum="sum2"),
+              S.Plan(seq=32, lanes=8, combine="seq", accum="sum2"),
+              S.Plan(seq=16, lanes=64, accum="sum2", final_f64=True),
+              S.Plan(seq=512, lanes=2, combine="seq", accum="sum2")):
+        n = p.chunk * 6
+        xs, ys = discriminating_dot_inputs(70, n)
+        prods = (xs * ys).astype(np.float64)     # rounded products, exact in binary64
+        assert math.fsum(prods.tolist()) == 0.0
+        h = exact.strategy_depth(n, p.seq, p.lanes, p.combine) + 2
+        bound = 2 * exact.gamma(h) ** 2 * math.fsum(np.abs(prods).tolist())
+        assert abs(float(S.dot(xs, ys, p))) <= bound, p
+        for acc in ("plain", "kahan"):
+            q = S.Plan(seq=p.seq, lanes=p.lanes, order=p.order, combine=p.combine, accum=acc)
+            outside += abs(float(S.dot(xs, ys, q))) > 10 * bound
+    assert outside >= 5
+
+
+def test_sum2_evaluators_agree_and_exact_cases():
+    g = np.random.default_rng(71)
+    x = (g.standard_normal(96) * 2.0 ** g.uniform(-20, 20, 96)).astype(np.float32)
+    y = g.standard_normal(96).astype(np.float32)
+    p = S.Plan(seq=6, lanes=4, order="strided", accum="sum2")
+    e = S.dot_expr(96, p)
+    assert same_bits(eval_scalar.evaluate(e, {"xs": x, "ys": y}),
+                     eval_numpy.evaluate(e, {"xs": x, "ys": y}))
+    ones = np.ones(p.chunk * 4, np.float32)
+    assert float(S.dot(ones, ones, p)) == p.chunk * 4
