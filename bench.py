@@ -20,7 +20,7 @@ Other workloads (one JSON line per measured item, not the headline):
     --workload sweep      dot N = 2^26 and gemv 16384^2 over the 24-strategy
                           sweep each, with the autotuner's pick
     --workload precision  gemv 16384^2 with bf16 and fp8-e4m3 (row-scaled) A,
-                          and the compensated dot at N = 2^28, with their
+                          and the compensated dots (Kahan, Sum2) at N = 2^28, with their
                           error against the exact (binary64-correctly-rounded)
                           value
     --workload batch      4096 dot / asum instances (n log-uniform in
@@ -266,13 +266,16 @@ def workload_precision(args):
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     ws = dp.workspace(KAHAN_DOT, dp.OP_DOT, dp.F32, 0, n)
     plain = KAHAN_DOT.with_(accum=dp.PLAIN, final_f64=0)
+    sum2 = KAHAN_DOT.with_(accum=dp.SUM2)
     out32 = torch.empty(1, device="cuda")
-    for name, fn in (("dot_kahan", lambda: dp.dot(xt, yt, KAHAN_DOT, out=out, ws=ws)),
-                     ("dot_plain", lambda: dp.dot(xt, yt, plain, out=out32, ws=ws))):
+    out2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    for name, fn, o in (("dot_kahan", lambda: dp.dot(xt, yt, KAHAN_DOT, out=out, ws=ws), out),
+                        ("dot_sum2", lambda: dp.dot(xt, yt, sum2, out=out2, ws=ws), out2),
+                        ("dot_plain", lambda: dp.dot(xt, yt, plain, out=out32, ws=ws), out32)):
         med, p10, p90 = time_us(fn, reps=args.steps)
         fn()
         torch.cuda.synchronize()
-        results[name] = (out if name == "dot_kahan" else out32).cpu().numpy()[0]
+        results[name] = o.cpu().numpy()[0]
         _line(workload="precision", op=name, n=n, strategy=strategy_text(KAHAN_DOT), us=round(med, 2),
               p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(8 * n + 8, med),
               pct_peak=round(100 * (8 * n + 8) / med / 1e3 / PEAK_GBPS, 1))
@@ -301,6 +304,7 @@ def workload_precision(args):
         # accumulator of the kernel's products would return
         s32 = math.fsum((x * y).astype(np.float64))
         kref = S.dot(x, y, to_plan(KAHAN_DOT))
+        sref = S.dot(x, y, to_plan(sum2))
         pref = S.dot(x, y, to_plan(plain))
         _line(workload="precision", op="dot_kahan",
               bit_exact_vs_oracle=bool(np.float64(kref).view(np.uint64) == np.float64(results["dot_kahan"]).view(np.uint64)),
@@ -309,6 +313,9 @@ def workload_precision(args):
               accumulation_err=abs(float(results["dot_kahan"]) - s32) / sabs,
               plain_accumulation_err=abs(float(results["dot_plain"]) - s32) / sabs,
               plain_bit_exact_vs_oracle=bool(np.float32(pref).view(np.uint32) == np.float32(results["dot_plain"]).view(np.uint32)),
+              sum2_bit_exact_vs_oracle=bool(np.float64(sref).view(np.uint64) == np.float64(results["dot_sum2"]).view(np.uint64)),
+              sum2_rel_err_vs_exact=abs(float(results["dot_sum2"]) - sx) / sabs,
+              sum2_accumulation_err=abs(float(results["dot_sum2"]) - s32) / sabs,
               cpu_seconds=round(time.perf_counter() - t0, 1),
               note="normwise: |computed - exact| / sum |x_i y_i|; exact = math.fsum of binary64 "
                    "products; accumulation_err uses the exact sum of the binary32-rounded "

@@ -91,11 +91,16 @@ typedef enum {
 
 typedef enum {
   DPIA_ACCUM_PLAIN = 0,      /* binary32 (or integer) accumulators            */
-  DPIA_ACCUM_KAHAN = 1       /* compensated (s, c) accumulators, dot only:
+  DPIA_ACCUM_KAHAN = 1,      /* compensated (s, c) accumulators, dot only:
                                 Kahan's step in the lanes (Higham, Accuracy
                                 and Stability of Numerical Algorithms,
                                 Alg. 4.2), Knuth's TwoSum merge in the
                                 combines, value s - c                       */
+  DPIA_ACCUM_SUM2 = 2        /* compensated (s, c), dot only: Sum2 of Ogita,
+                                Rump and Oishi (SIAM J. Sci. Comput. 26(6),
+                                2005, Alg. 4.4) over the rounded products:
+                                TwoSum at every step and merge, the exact
+                                errors summed in c, value s + c             */
 } dpia_accum;
 
 /*
@@ -112,7 +117,8 @@ typedef enum {
  *               2: a second kernel does.  Same expression, same bits.
  *               gemv needs no cross-work-group step and takes 1 or 2.
  *  accum        dpia_accum
- *  final_f64    Kahan only: fold the chunk values s - c in binary64
+ *  final_f64    compensated only: fold the chunk values (s - c for Kahan,
+ *               s + c for Sum2) in binary64
  *  rows_per_wg  gemv: R rows per work-group (M must be a multiple)
  *  row_parts    gemv: 1, or 2 halves per row, each reduced with (C, L)
  *               and folded as (0 + h0) + h1

@@ -13,7 +13,7 @@ from dataclasses import dataclass, replace
 
 from . import _lib
 from ._lib import (BF16, CONTIGUOUS, F32, F64, FP8_E4M3, I32, KAHAN, NONE, OP_ASUM,  # noqa: F401
-                   OP_DOT, OP_GEMV, OP_SCAL, PLAIN, SEQ, STRIDED, TREE, DpiaError,
+                   OP_DOT, OP_GEMV, OP_SCAL, PLAIN, SEQ, STRIDED, SUM2, TREE, DpiaError,
                    last_error_detail)
 
 
@@ -25,7 +25,7 @@ class Strategy:
     order: int = CONTIGUOUS       # CONTIGUOUS | STRIDED
     wg_combine: int = TREE        # TREE | SEQ
     passes: int = 2               # 1 | 2
-    accum: int = PLAIN            # PLAIN | KAHAN
+    accum: int = PLAIN            # PLAIN | KAHAN | SUM2
     final_f64: int = 0
     rows_per_wg: int = 1
     row_parts: int = 1
@@ -106,7 +106,7 @@ def dot(x, y, s: Strategy, out=None, ws=None, out_dtype=None, stream=None):
         raise TypeError("x and y must have the same dtype")
     n = x.numel()
     if out is None:
-        od = out_dtype or (torch.float64 if (s.accum == KAHAN and s.final_f64) else x.dtype)
+        od = out_dtype or (torch.float64 if (s.accum != PLAIN and s.final_f64) else x.dtype)
         out = torch.empty(1, dtype=od, device=x.device)
     if ws is None:
         ws = workspace(s, OP_DOT, dt, 0, n, x.device)
@@ -195,7 +195,7 @@ def chunks(op: int, s: Strategy, x, y=None, out=None, stream=None):
     torch = _torch()
     n = x.numel()
     dt = _dtype_code(x)
-    vb = 8 if s.accum == KAHAN else 4
+    vb = 8 if s.accum != PLAIN else 4
     if out is None:
         out = torch.empty(max(1, num_chunks(s, n) * values_per_chunk(s)) * vb, dtype=torch.uint8,
                           device=x.device)
@@ -212,7 +212,7 @@ def fold(op: int, s: Strategy, chunk_values, n: int, dtype: int, out=None, out_d
     """The outer reduceSeq of the strategy over chunk values from ``chunks``."""
     torch = _torch()
     if out is None:
-        od = out_dtype or (torch.float64 if (s.accum == KAHAN and s.final_f64) else
+        od = out_dtype or (torch.float64 if (s.accum != PLAIN and s.final_f64) else
                            (torch.int32 if dtype == I32 else torch.float32))
         out = torch.empty(1, dtype=od, device=chunk_values.device)
     cs = s.c()

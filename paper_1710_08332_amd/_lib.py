@@ -21,7 +21,7 @@ OP_DOT, OP_ASUM, OP_GEMV, OP_SCAL = range(4)
 # dpia_order, dpia_combine, dpia_accum
 CONTIGUOUS, STRIDED = 0, 1
 TREE, SEQ, NONE = 0, 1, 2
-PLAIN, KAHAN = 0, 1
+PLAIN, KAHAN, SUM2 = 0, 1, 2
 
 EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
            "dpia_scal", "dpia_chunks", "dpia_module_load", "dpia_module_launch",

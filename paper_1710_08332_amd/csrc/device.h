@@ -118,6 +118,25 @@ struct KahanF32 {
   }
 };
 
+// Sum2 pair (s, c), value s + c (Ogita, Rump, Oishi 2005).  add(r, l)
+// merges a later pair r into an earlier accumulator l: TwoSum of the s
+// parts, whose exact error joins the c parts:
+//   s = l.s + r.s ; bp = s - l.s ; e = (l.s - (s - bp)) + (r.s - bp) ;
+//   result (s, (l.c + r.c) + e).
+struct Sum2F32 {
+  using T = KPair;
+  __device__ static T zero() { return KPair{0.0f, 0.0f}; }
+  __device__ static T add(T r, T l) {
+    const float s = l.s + r.s;
+    const float bp = s - l.s;
+    const float e = (l.s - (s - bp)) + (r.s - bp);
+    return KPair{s, (l.c + r.c) + e};
+  }
+  __device__ static T shfl_xor(T v, int d) {
+    return KPair{__shfl_xor(v.s, d, 64), __shfl_xor(v.c, d, 64)};
+  }
+};
+
 // One node of the pairwise tree: reduceSeq (+) 0 over [left, right].
 template <class A>
 __device__ __forceinline__ typename A::T tree_node(typename A::T left, typename A::T right) {

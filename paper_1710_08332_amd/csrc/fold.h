@@ -7,7 +7,15 @@
 
 namespace dpia {
 
-enum : int { kFinalPlain = 0, kFinalKahan32 = 1, kFinalKahan64 = 2 };
+// Kahan pairs have value s - c, Sum2 pairs s + c; "64": the chunk values are
+// folded in binary64.
+enum : int {
+  kFinalPlain = 0,
+  kFinalKahan32 = 1,
+  kFinalKahan64 = 2,
+  kFinalSum2_32 = 3,
+  kFinalSum2_64 = 4
+};
 
 // The outer reduceSeq over the G chunk values, from the literal 0, in chunk
 // order, by one thread.  The work-group stages blocks of chunk values in LDS
@@ -23,6 +31,8 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
   auto fold1 = [&](const T& e) {
     if constexpr (FINAL == kFinalKahan64)
       acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
+    else if constexpr (FINAL == kFinalSum2_64)
+      acc64 = (static_cast<double>(e.s) + static_cast<double>(e.c)) + acc64;
     else
       acc = A::add(e, acc);
   };
@@ -44,13 +54,15 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if constexpr (FINAL == kFinalKahan64) {
+    if constexpr (FINAL == kFinalKahan64 || FINAL == kFinalSum2_64) {
       if (out_f64)
         *static_cast<double*>(out) = acc64;
       else
         *static_cast<float*>(out) = static_cast<float>(acc64);
     } else if constexpr (FINAL == kFinalKahan32) {
       *static_cast<float*>(out) = acc.s - acc.c;
+    } else if constexpr (FINAL == kFinalSum2_32) {
+      *static_cast<float*>(out) = acc.s + acc.c;
     } else {
       *static_cast<T*>(out) = acc;
     }

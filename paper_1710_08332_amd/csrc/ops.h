@@ -108,6 +108,25 @@ struct KahanDotF32 {
 };
 
 
+// zip xs ys with Sum2's step on acc = (s, c), value s + c:
+//   p = x*y ; t = s + p ; bp = t - s ; new acc = (t, c + ((s - (t - bp)) + (p - bp)))
+struct Sum2DotF32 {
+  using Arith = Sum2F32;
+  using T = KPair;
+  using Term = TermF;
+  using View = DotF32::View;
+  const float* x;
+  const float* y;
+  __device__ View chunk(int64_t g, int64_t W) const { return View{x + g * W, y + g * W}; }
+  __device__ static T step(const Term& z, T acc) {
+    const float p = z.a * z.b;
+    const float t = acc.s + p;
+    const float bp = t - acc.s;
+    return KPair{t, acc.c + ((acc.s - (t - bp)) + (p - bp))};
+  }
+};
+
+
 // ---------------------------------------------------------------- gemv rows
 
 struct GTerm { float a, b; };

@@ -74,10 +74,12 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
                 "vector and uncombined strategies use plain accumulation");
   if (s->passes != 1 && s->passes != 2)
     return fail(detail, DPIA_ERR_STRATEGY, "passes must be 1 or 2");
-  if (s->accum > DPIA_ACCUM_KAHAN) return fail(detail, DPIA_ERR_STRATEGY, "unknown accum");
+  if (s->accum > DPIA_ACCUM_SUM2) return fail(detail, DPIA_ERR_STRATEGY, "unknown accum");
   if (s->final_f64 > 1) return fail(detail, DPIA_ERR_STRATEGY, "final_f64 must be 0 or 1");
-  if (s->final_f64 && s->accum != DPIA_ACCUM_KAHAN)
-    return fail(detail, DPIA_ERR_STRATEGY, "final_f64 applies to the Kahan accumulation only");
+  const bool compensated = s->accum == DPIA_ACCUM_KAHAN || s->accum == DPIA_ACCUM_SUM2;
+  if (s->final_f64 && !compensated)
+    return fail(detail, DPIA_ERR_STRATEGY,
+                "final_f64 applies to the compensated accumulations only");
   // (scal is a map: it has no combine, whatever the descriptor says)
   if (s->wg_combine == DPIA_COMBINE_TREE && !is_pow2(s->local_size) && op != DPIA_OP_SCAL)
     return fail(detail, DPIA_ERR_STRATEGY, "a tree combine needs a power-of-two local_size");
@@ -89,8 +91,8 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   if (op == DPIA_OP_DOT) {
     if (dt != DPIA_F32 && dt != DPIA_I32)
       return fail(detail, DPIA_ERR_DTYPE, "dot takes F32 or I32 vectors");
-    if (s->accum == DPIA_ACCUM_KAHAN && dt != DPIA_F32)
-      return fail(detail, DPIA_ERR_DTYPE, "Kahan accumulation is defined for F32 only");
+    if (compensated && dt != DPIA_F32)
+      return fail(detail, DPIA_ERR_DTYPE, "compensated accumulation is defined for F32 only");
   } else if (op == DPIA_OP_SCAL) {
     if (dt != DPIA_F32) return fail(detail, DPIA_ERR_DTYPE, "scal takes F32 vectors");
     if (s->accum != DPIA_ACCUM_PLAIN)
@@ -125,7 +127,7 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   q.max_grid = s->max_grid;
   q.row_parts = static_cast<int>(s->row_parts);
   q.R = static_cast<int>(s->rows_per_wg);
-  q.acc_bytes = (q.accum == DPIA_ACCUM_KAHAN) ? 8 : 4;
+  q.acc_bytes = compensated ? 8 : 4;
 
   const int cap = kVecBytes / static_cast<int>(elem_bytes(dt));
   if (op == DPIA_OP_GEMV) {
@@ -148,9 +150,9 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     if (n < 0) return fail(detail, DPIA_ERR_SHAPE, "negative length");
     // A length that is not a multiple of W is zero-extended to the next
     // multiple; that leaves plain folds unchanged but not compensated ones.
-    if (n % q.W && q.accum == DPIA_ACCUM_KAHAN) {
+    if (n % q.W && compensated) {
       os << "n = " << n << " is not a multiple of the chunk W = seq_len * local_size = " << q.W
-         << " (required for Kahan accumulation, which zero-extension would change)";
+         << " (required for compensated accumulation)";
       return fail(detail, DPIA_ERR_SHAPE, os.str());
     }
     q.n = n;

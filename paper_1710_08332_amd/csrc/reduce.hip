@@ -200,6 +200,11 @@ hipError_t with_reduction(const Plan& p, const void* x, const void* y, F&& f) {
     if (p.final_f64) return f(op, ic<kFinalKahan64>{});
     return f(op, ic<kFinalKahan32>{});
   }
+  if (p.accum == DPIA_ACCUM_SUM2) {
+    Sum2DotF32 op{static_cast<const float*>(x), static_cast<const float*>(y)};
+    if (p.final_f64) return f(op, ic<kFinalSum2_64>{});
+    return f(op, ic<kFinalSum2_32>{});
+  }
   return f(DotF32{static_cast<const float*>(x), static_cast<const float*>(y)},
            ic<kFinalPlain>{});
 }
@@ -242,14 +247,21 @@ extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n
     e = launch_reduce<DotU32, kFinalPlain>(
         p, DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)}, out, 0, ws,
         hs);
-  } else if (p.accum == DPIA_ACCUM_KAHAN) {
+  } else if (p.accum == DPIA_ACCUM_KAHAN || p.accum == DPIA_ACCUM_SUM2) {
     if (out_dt != DPIA_F32 && !(out_dt == DPIA_F64 && p.final_f64))
-      return bad(DPIA_ERR_DTYPE, "a Kahan dot writes F32, or F64 with final_f64");
-    KahanDotF32 op{static_cast<const float*>(x), static_cast<const float*>(y)};
-    if (p.final_f64)
-      e = launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, out_dt == DPIA_F64, ws, hs);
-    else
-      e = launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, ws, hs);
+      return bad(DPIA_ERR_DTYPE, "a compensated dot writes F32, or F64 with final_f64");
+    const float* xf = static_cast<const float*>(x);
+    const float* yf = static_cast<const float*>(y);
+    const int f64 = out_dt == DPIA_F64;
+    if (p.accum == DPIA_ACCUM_KAHAN) {
+      KahanDotF32 op{xf, yf};
+      e = p.final_f64 ? launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, f64, ws, hs)
+                      : launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, ws, hs);
+    } else {
+      Sum2DotF32 op{xf, yf};
+      e = p.final_f64 ? launch_reduce<Sum2DotF32, kFinalSum2_64>(p, op, out, f64, ws, hs)
+                      : launch_reduce<Sum2DotF32, kFinalSum2_32>(p, op, out, 0, ws, hs);
+    }
   } else {
     if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
     e = launch_reduce<DotF32, kFinalPlain>(

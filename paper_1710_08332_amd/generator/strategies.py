@@ -18,6 +18,17 @@ ASUM_STEP = "(lam (e acc) (+ (abs e) acc))"
 # yk = x*y - c ; t = s + yk ; new accumulator (t, (t - s) - yk)
 KAHAN_STEP = ("(lam (z acc) ((lam (yk) ((lam (t) (pair t (- (- t (fst acc)) yk)))"
               " (+ (fst acc) yk))) (- (* (fst z) (snd z)) (snd acc))))")
+# Sum2 (Ogita, Rump, Oishi 2005) with element z = (x, y) and accumulator
+# (s, c), value s + c: p = x*y ; t = s + p ; bp = t - s ;
+# new accumulator (t, c + ((s - (t - bp)) + (p - bp)))
+SUM2_STEP = ("(lam (z acc) ((lam (p) ((lam (t) ((lam (bp) (pair t (+ (snd acc)"
+             " (+ (- (fst acc) (- t bp)) (- p bp))))) (- t (fst acc)))) (+ (fst acc) p)))"
+             " (* (fst z) (snd z))))")
+# Sum2 merge of a later pair r into l: TwoSum of the s parts, error into c:
+# s = s_l + s_r ; bp = s - s_l ; new (s, (c_l + c_r) + ((s_l - (s - bp)) + (s_r - bp)))
+SUM2_MERGE = ("(lam (r l) ((lam (s) ((lam (bp) (pair s (+ (+ (snd l) (snd r))"
+              " (+ (- (fst l) (- s bp)) (- (fst r) bp))))) (- s (fst l))))"
+              " (+ (fst l) (fst r))))")
 # TwoSum merge of a later pair r into the earlier accumulator l:
 # s = s_l + s_r ; bp = s - s_l ; e = (s_l - (s - bp)) + (s_r - bp) ;
 # new accumulator (s, (c_l + c_r) - e)
@@ -63,11 +74,12 @@ def _combine(lanes: str, s, merge: str, zero: str) -> str:
 
 def _reduction(s, view: str, n: int, step: str) -> str:
     C, L, V = _parts(s)
-    kahan = s.accum == 1
+    kahan = s.accum != 0                              # a compensated pair
     if n % (C * L * V):
         raise ValueError(f"n = {n} is not a multiple of the chunk {C * L * V}")
     zero = _zero(V, kahan)
-    merge = KAHAN_MERGE if kahan else PLUS
+    pair_merge = KAHAN_MERGE if s.accum == 1 else SUM2_MERGE
+    merge = pair_merge if kahan else PLUS
     if s.wg_combine == 2:                             # uncombined: every lane's value
         chunks = f"(join (mapWorkgroup (lam (ch) {_lanes('ch', s, step, zero)}) (split {C * L} {view})))"
     else:
@@ -77,10 +89,11 @@ def _reduction(s, view: str, n: int, step: str) -> str:
         chunks = f"(asScalar {V} {chunks})"
     if not kahan:
         return f"(reduceSeq {PLUS} 0 {chunks})"
+    sign = "-" if s.accum == 1 else "+"               # Kahan s - c, Sum2 s + c
     if s.final_f64:
-        return (f"(reduceSeq (lam (p acc) (+ (- (f64 (fst p)) (f64 (snd p))) acc)) (f64 0)"
+        return (f"(reduceSeq (lam (p acc) (+ ({sign} (f64 (fst p)) (f64 (snd p))) acc)) (f64 0)"
                 f" {chunks})")
-    return f"((lam (r) (- (fst r) (snd r))) (reduceSeq {KAHAN_MERGE} (pair 0 0) {chunks}))"
+    return f"((lam (r) ({sign} (fst r) (snd r))) (reduceSeq {pair_merge} (pair 0 0) {chunks}))"
 
 
 def _vec(name: str, V: int) -> str:
@@ -89,7 +102,7 @@ def _vec(name: str, V: int) -> str:
 
 def dot_text(s, n: int) -> str:
     _, _, V = _parts(s)
-    step = KAHAN_STEP if s.accum == 1 else DOT_STEP
+    step = {1: KAHAN_STEP, 2: SUM2_STEP}.get(int(s.accum), DOT_STEP)
     return _reduction(s, f"(zip {_vec('xs', V)} {_vec('ys', V)})", n, step)
 
 

@@ -12,7 +12,7 @@ def to_plan(s: dp.Strategy) -> S.Plan:
     return S.Plan(seq=s.seq_len, lanes=s.local_size,
                   order="strided" if s.order == dp.STRIDED else "contiguous",
                   combine={dp.SEQ: "seq", dp.TREE: "tree", dp.NONE: "none"}[s.wg_combine],
-                  accum="kahan" if s.accum == dp.KAHAN else "plain",
+                  accum={dp.PLAIN: "plain", dp.KAHAN: "kahan", dp.SUM2: "sum2"}[s.accum],
                   final_f64=bool(s.final_f64), rows=s.rows_per_wg, row_parts=s.row_parts,
                   vec=max(1, s.vec_width))
 

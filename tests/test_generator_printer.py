@@ -21,6 +21,8 @@ DESCS = [
     dp.Strategy(seq_len=5, local_size=1),
     dp.Strategy(seq_len=2, local_size=4, order=T_, accum=dp.KAHAN, final_f64=1),
     dp.Strategy(seq_len=4, local_size=2, accum=dp.KAHAN),
+    dp.Strategy(seq_len=4, local_size=4, order=T_, accum=dp.SUM2),
+    dp.Strategy(seq_len=2, local_size=8, wg_combine=dp.SEQ, accum=dp.SUM2, final_f64=1),
 ]
 
 

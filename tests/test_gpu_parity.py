@@ -127,9 +127,10 @@ def test_integer_dot_is_exact(strat):
 @pytest.mark.parametrize("strat", [(256, 16, C_, TREE), (64, 256, T_, TREE), (16, 64, C_, SEQ),
                                    (5, 4, T_, SEQ), (32, 128, T_, TREE)], ids=_ids)
 @pytest.mark.parametrize("final_f64", [0, 1])
-def test_kahan_dot_bit_exact(strat, final_f64):
+@pytest.mark.parametrize("accum", [dp.KAHAN, dp.SUM2], ids=["kahan", "sum2"])
+def test_kahan_dot_bit_exact(strat, final_f64, accum):
     C, L, order, comb = strat
-    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, accum=dp.KAHAN,
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, accum=accum,
                     final_f64=final_f64)
     n = C * L * 19
     x, y = synthetic.kahan_dot_inputs(n, synthetic.SEEDS["precision"])
@@ -240,6 +241,7 @@ def test_config2_dot_and_gemv_at_full_size():
 @pytest.mark.parametrize("kw", [dict(seq_len=256, local_size=1024, order=T_),
                                 dict(seq_len=64, local_size=16, order=C_, wg_combine=SEQ),
                                 dict(seq_len=32, local_size=128, order=T_, accum=dp.KAHAN),
+                                dict(seq_len=32, local_size=128, order=T_, accum=dp.SUM2),
                                 dict(seq_len=32, local_size=128, order=C_, accum=dp.KAHAN,
                                      final_f64=1)], ids=str)
 def test_chunks_then_fold_equals_one_call(kw):
