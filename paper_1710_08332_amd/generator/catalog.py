@@ -8,7 +8,7 @@ import os
 from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Tuple
 
-from .. import CONTIGUOUS, KAHAN, NONE, SEQ, STRIDED, TREE, Strategy
+from .. import CONTIGUOUS, KAHAN, SEQ, STRIDED, SUM2, TREE, Strategy
 from . import strategies as P
 from .runtime import compile_program
 
@@ -42,6 +42,8 @@ def programs() -> List[Tuple[str, str, Dict, str]]:
                                        wg_combine=SEQ), 16 * 32 * 23)
     dot("dot_kahan_f64", Strategy(seq_len=16, local_size=64, order=STRIDED, accum=KAHAN,
                                   final_f64=1), 16 * 64 * 13)
+    dot("dot_sum2", Strategy(seq_len=16, local_size=64, order=STRIDED, accum=SUM2),
+        16 * 64 * 13)
     dot("dot_u32", Strategy(seq_len=4, local_size=16, order=CONTIGUOUS), 4 * 16 * 29, "u32")
     dot("dot_v4_strided_tree", Strategy(seq_len=8, local_size=64, order=STRIDED, vec_width=4),
         4 * 8 * 64 * 11)

@@ -36,6 +36,8 @@ DOT_PLANS = [
     S.Plan(seq=6, lanes=1),
     S.Plan(seq=2, lanes=2, accum="kahan", final_f64=True),
     S.Plan(seq=3, lanes=4, order="strided", accum="kahan"),
+    S.Plan(seq=4, lanes=8, order="strided", accum="sum2"),
+    S.Plan(seq=5, lanes=2, combine="seq", accum="sum2", final_f64=True),
 ]
 
 

@@ -553,6 +553,7 @@ def _meta(name):
     ("dot_strided_tree", dict(seq_len=4, local_size=64, order=T_)),
     ("dot_contiguous_seq", dict(seq_len=16, local_size=32, order=C_, wg_combine=SEQ)),
     ("dot_kahan_f64", dict(seq_len=16, local_size=64, order=T_, accum=dp.KAHAN, final_f64=1)),
+    ("dot_sum2", dict(seq_len=16, local_size=64, order=T_, accum=dp.SUM2)),
     ("dot_u32", dict(seq_len=4, local_size=16, order=C_)),
     ("dot_v4_strided_tree", dict(seq_len=8, local_size=64, order=T_, vec_width=4)),
     ("asum_strided_tree", dict(seq_len=8, local_size=128, order=T_)),
