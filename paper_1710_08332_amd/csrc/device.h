@@ -304,17 +304,23 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
 }
 
 // ------------------------------------------------------------ LDS staging
-// Contiguous order through LDS.  In the contiguous order lane l folds the
-// elements l*C .. l*C + C-1 of the chunk, so the lanes of a wavefront read
-// 64 different rows at once.  Here the team instead loads a tile of kStage
-// elements of every lane's row with coalesced 16-byte loads (4 threads read
-// one row's 64 contiguous bytes), writes it to LDS, and every lane then
-// reads its own kStage elements back and folds them in increasing index:
-// the same operands in the same order as the direct path.  Elements at or
-// past `limit` are read as zeros, which fold as the identity (see
-// lane_folds), so partial chunks take the same path and every team of the
-// work-group runs the same barriers.
-constexpr int kStageVec = kStage / 4;      // 16-byte vectors per lane row
+// Contiguous order through LDS, one wavefront at a time.  In the contiguous
+// order lane l folds the elements l*C .. l*C + C-1 of its chunk, so the 64
+// lanes of a wavefront read 64 different rows at once.  Here each wavefront
+// instead loads a tile of kStage elements of each of its own 64 lanes' rows
+// with 16-byte loads, kStage / 4 work-items covering one row's contiguous
+// bytes, writes the tile to the wavefront's own LDS region, and every lane
+// reads its kStage elements back and folds them in increasing index: the
+// same operands in the same order as the direct path.  A wavefront's LDS
+// accesses complete in program order, so the region needs no barrier
+// between the writes and the reads, or before the next tile overwrites it:
+// only a compiler fence keeps the accesses in that order.  Elements at or
+// past a row's end are read as zeros, which fold as the identity (see
+// lane_folds).
+constexpr int kStageVec = kStage / 4;            // 16-byte parts per row tile
+constexpr int kWave = 64;
+static_assert(kWave % kStageVec == 0, "a load instruction covers whole row tiles");
+constexpr int kStageRowsPerLoad = kWave / kStageVec;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -325,39 +331,58 @@ __device__ __forceinline__ f32x4 load4_masked(const float* p, int rem) {
   return r;
 }
 
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// `stage`: this wavefront's region of 2 * 64 rows of kStageRow floats.  Every
+// work-item of the wavefront calls this (inactive lanes fold nothing but
+// still load their share of the other rows).
 template <class Op, class View>
-__device__ __forceinline__ void contiguous_staged(const View& view, bool active, int t, int L,
-                                                  int C, int limit, typename Op::T& acc,
+__device__ __forceinline__ void contiguous_staged(const View& view, bool active, int t, int C,
+                                                  int limit, typename Op::T& acc,
                                                   float* stage) {
   constexpr int NOPS = View::kOps;
   acc = Op::Arith::zero();
+  const int lane = threadIdx.x & (kWave - 1);
+  int have = limit - t * C;                     // elements of this lane's row that exist
+  have = active ? (have < 0 ? 0 : (have > C ? C : have)) : 0;
+  // this work-item loads part `part` of rows i * kStageRowsPerLoad + lane / kStageVec
+  const int part = lane % kStageVec;
+  const float* rowp[NOPS][kStageVec];
+  int rowhave[kStageVec];
+#pragma unroll
+  for (int i = 0; i < kStageVec; ++i) {
+    const int r = i * kStageRowsPerLoad + lane / kStageVec;
+    rowhave[i] = __shfl(have, r, kWave);
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) {
+      const unsigned long long mine =
+          reinterpret_cast<unsigned long long>(view.operand(o) + static_cast<int64_t>(t) * C);
+      rowp[o][i] = reinterpret_cast<const float*>(__shfl(mine, r, kWave));
+    }
+  }
   const int ntiles = C / kStage;
   f32x4 regs[NOPS][kStageVec];
   auto gload = [&](int tile) {
 #pragma unroll
     for (int i = 0; i < kStageVec; ++i) {
-      const int q = i * L + t;
-      const int lane = q / kStageVec;
-      const int part = q - lane * kStageVec;
-      const int e = lane * C + tile * kStage + part * 4;
+      const int e = tile * kStage + part * 4;
 #pragma unroll
-      for (int o = 0; o < NOPS; ++o)
-        regs[o][i] = active ? load4_masked(view.operand(o) + e, limit - e)
-                            : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int o = 0; o < NOPS; ++o) regs[o][i] = load4_masked(rowp[o][i] + e, rowhave[i] - e);
     }
   };
   gload(0);
   for (int tile = 0; tile < ntiles; ++tile) {
 #pragma unroll
     for (int i = 0; i < kStageVec; ++i) {
-      const int q = i * L + t;
-      const int lane = q / kStageVec;
-      const int part = q - lane * kStageVec;
+      const int r = i * kStageRowsPerLoad + lane / kStageVec;
 #pragma unroll
       for (int o = 0; o < NOPS; ++o)
-        *reinterpret_cast<f32x4*>(stage + (o * L + lane) * kStageRow + part * 4) = regs[o][i];
+        *reinterpret_cast<f32x4*>(stage + (o * kWave + r) * kStageRow + part * 4) = regs[o][i];
     }
-    __syncthreads();
+    wave_lds_order();
     if (tile + 1 < ntiles) gload(tile + 1);   // in flight while this tile is folded
     if (active) {
 #pragma unroll
@@ -365,16 +390,16 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
         f32x4 v[NOPS];
 #pragma unroll
         for (int o = 0; o < NOPS; ++o)
-          v[o] = *reinterpret_cast<const f32x4*>(stage + (o * L + t) * kStageRow + j * 4);
+          v[o] = *reinterpret_cast<const f32x4*>(stage + (o * kWave + lane) * kStageRow + j * 4);
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc = Op::step(View::term(v, i), acc);
       }
     }
-    __syncthreads();
+    wave_lds_order();
   }
 }
 
-// `stage`: this team's LDS staging region (contiguous order, stageable
+// `stage`: this wavefront's LDS staging region (contiguous order, stageable
 // views) or nullptr for direct loads.  The choice is uniform per launch.
 template <class Op, int ORDER, int NV, int COMBINE, class View>
 __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool active, int t,
@@ -385,7 +410,7 @@ __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool act
   typename Op::T acc[NL];
   if constexpr (ORDER == kContiguous && View::kStageable) {
     if (stage != nullptr) {
-      contiguous_staged<Op>(view, active, t, L, C, limit, acc[0], stage);
+      contiguous_staged<Op>(view, active, t, C, limit, acc[0], stage);
       return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
     }
   }

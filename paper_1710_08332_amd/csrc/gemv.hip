@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
   T* scratch = lds + team_id * a.team_lds_elems;
   float* stage = a.stage_off < 0 ? nullptr
                                  : reinterpret_cast<float*>(lds_raw + a.stage_off) +
-                                       team_id * stage_floats(a.L);
+                                       (threadIdx.x / kWave) * stage_floats(kWave);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.m;
        base += stride) {

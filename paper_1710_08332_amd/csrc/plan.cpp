@@ -204,15 +204,16 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   } else if (q.team > 64) {
     lds = static_cast<size_t>(q.teams_per_wg) * (q.team / 64) * q.acc_bytes;
   }
-  // The contiguous order with binary32 operands is staged through LDS when
-  // every lane holds whole tiles and the work-group has at most 256 threads.
+  // The contiguous order with binary32 operands is staged through LDS, one
+  // wavefront at a time, when every lane holds whole tiles and the
+  // work-group is whole wavefronts, at most 256 threads.
   q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 && V == 1 &&
-            q.combine != DPIA_COMBINE_NONE && q.C % kStage == 0 && q.wg_threads <= 256;
+            q.combine != DPIA_COMBINE_NONE && q.C % kStage == 0 && q.wg_threads <= 256 &&
+            q.wg_threads % 64 == 0;
   q.stage_off = 0;
   if (q.stage) {
     q.stage_off = round_up(lds, 16);
-    lds = q.stage_off + static_cast<size_t>(q.teams_per_wg) * stage_floats(static_cast<int>(q.L)) *
-                            sizeof(float);
+    lds = q.stage_off + static_cast<size_t>(q.wg_threads / 64) * stage_floats(64) * sizeof(float);
   }
   if (op == DPIA_OP_SCAL) {
     lds = 0;                 // a map: no combine, no fold, no staging

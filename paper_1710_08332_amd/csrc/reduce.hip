@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
   T* scratch = lds + team_id * a.team_lds_elems;
   float* stage = a.stage_off < 0 ? nullptr
                                  : reinterpret_cast<float*>(lds_raw + a.stage_off) +
-                                       team_id * stage_floats(a.L);
+                                       (threadIdx.x / kWave) * stage_floats(kWave);
   T* partials = static_cast<T*>(a.partials);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
   // parforWorkgroup as a grid-stride loop: every thread of a work-group
