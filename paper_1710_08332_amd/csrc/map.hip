@@ -93,6 +93,89 @@ __global__ void __launch_bounds__(1024) scal_kernel(float alpha, const float* x,
   }
 }
 
+__device__ __forceinline__ void store4_masked(float* p, f32x4 v, int rem) {
+  if (rem >= 4) {
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+    return;
+  }
+  for (int i = 0; i < rem; ++i) p[i] = v[i];
+}
+
+// The contiguous order through LDS, one wavefront at a time (as for the
+// contiguous reductions): the wavefront loads a tile of S elements of each
+// of its 64 lanes' rows with 16-byte loads, every lane multiplies its own S
+// elements in the wavefront's LDS region, and the wavefront stores the tile
+// with 16-byte stores.  Each product is still made by the lane that owns the
+// element.  Elements past a row's end are neither loaded nor stored.  A
+// wavefront's LDS accesses complete in program order, so compiler fences
+// suffice between the phases.  With S = C a wavefront's tile is its 64
+// rows, one contiguous block.
+template <int S>
+__global__ void __launch_bounds__(256) scal_staged_kernel(float alpha, const float* x, float* y,
+                                                          MapArgs a) {
+  constexpr int P = S / 4;                 // 16-byte parts per row tile
+  constexpr int RPL = kWave / P;           // rows one load instruction covers
+  constexpr int ROW = S + 4;               // LDS row stride in floats
+  static_assert(kWave % P == 0, "a load instruction covers whole row tiles");
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* stage = reinterpret_cast<float*>(lds_raw) + (threadIdx.x / kWave) * kWave * ROW;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int team_id = threadIdx.x / a.team;
+  const int t = threadIdx.x - team_id * a.team;
+  const int part = lane % P;
+  const int ntiles = a.C / S;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
+  // the loop bounds depend on the work-group only: every wavefront runs them
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.items;
+       base += stride) {
+    const int64_t g = base + team_id;
+    const bool active = g < a.items;
+    const int64_t row0 = (active ? g : 0) * a.W + static_cast<int64_t>(t) * a.C;
+    const int64_t left = a.n - row0;
+    const int have = active ? static_cast<int>(left < 0 ? 0 : (left > a.C ? a.C : left)) : 0;
+    int64_t rowoff[P];
+    int rowhave[P], rowslot[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int r = i * RPL + lane / P;
+      rowoff[i] = __shfl(row0, r, kWave);
+      rowhave[i] = __shfl(have, r, kWave);
+      rowslot[i] = r * ROW + part * 4;
+    }
+    f32x4 regs[P];
+    auto gload = [&](int tile) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int e = tile * S + part * 4;
+        regs[i] = load4_masked(x + rowoff[i] + e, rowhave[i] - e);
+      }
+    };
+    gload(0);
+    for (int tile = 0; tile < ntiles; ++tile) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) *reinterpret_cast<f32x4*>(stage + rowslot[i]) = regs[i];
+      wave_lds_order();
+      if (tile + 1 < ntiles) gload(tile + 1);   // in flight during this tile
+#pragma unroll
+      for (int j = 0; j < P; ++j) {             // this lane's own elements
+        f32x4* q = reinterpret_cast<f32x4*>(stage + lane * ROW + j * 4);
+        f32x4 v = *q;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = alpha * v[i];
+        *q = v;
+      }
+      wave_lds_order();
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int e = tile * S + part * 4;
+        store4_masked(y + rowoff[i] + e, *reinterpret_cast<const f32x4*>(stage + rowslot[i]),
+                      rowhave[i] - e);
+      }
+      wave_lds_order();
+    }
+  }
+}
+
 }  // namespace dpia
 
 using namespace dpia;
@@ -115,6 +198,17 @@ extern "C" dpia_status dpia_scal(const dpia_strategy* s, dpia_dtype dt, int64_t 
   const int64_t grid = grid_size(p);
   const float* xp = static_cast<const float*>(x);
   float* yp = static_cast<float*>(y);
+  if (p.stage) {
+    void* args[] = {&alpha, &xp, &yp, &a};
+    const void* kern = p.scal_tile == 64   ? reinterpret_cast<const void*>(scal_staged_kernel<64>)
+                       : p.scal_tile == 32 ? reinterpret_cast<const void*>(scal_staged_kernel<32>)
+                                           : reinterpret_cast<const void*>(scal_staged_kernel<16>);
+    hipError_t e = hipLaunchKernel(kern, dim3(grid), dim3(p.wg_threads), args, p.lds_bytes,
+                                   reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "dpia_scal launch");
+    clear_detail();
+    return DPIA_OK;
+  }
   hipError_t e = with_order_combine(p.order, DPIA_COMBINE_TREE, [&](auto ord, auto) {
     constexpr int ORDER = decltype(ord)::value;
     return with_nv<4>(p.nv, [&](auto nvc) {

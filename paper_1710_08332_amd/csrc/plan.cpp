@@ -216,8 +216,15 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     lds = q.stage_off + static_cast<size_t>(q.wg_threads / 64) * stage_floats(64) * sizeof(float);
   }
   if (op == DPIA_OP_SCAL) {
-    lds = 0;                 // a map: no combine, no fold, no staging
-    q.stage = false;
+    // a map: no combine and no fold; the contiguous order is staged through
+    // LDS per wavefront (one operand) under the same conditions as above
+    // in tiles of up to 64 elements of a row (whole rows when C allows)
+    q.stage = q.order == DPIA_ORDER_CONTIGUOUS && q.nv == 4 && q.C % 16 == 0 &&
+              q.wg_threads <= 256 && q.wg_threads % 64 == 0;
+    q.scal_tile = q.C % 64 == 0 ? 64 : (q.C % 32 == 0 ? 32 : 16);
+    q.stage_off = 0;
+    lds = q.stage ? static_cast<size_t>(q.wg_threads / 64) * 64 * (q.scal_tile + 4) * sizeof(float)
+                  : 0;
   }
   if (op == DPIA_OP_DOT || op == DPIA_OP_ASUM) {
     size_t fold = static_cast<size_t>(kFoldBlock) * q.acc_bytes;
@@ -225,7 +232,7 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   }
   lds = round_up(lds + 16, 16);
 #ifndef DPIA_LDS_CAP
-#define DPIA_LDS_CAP (64 * 1024)
+#define DPIA_LDS_CAP (160 * 1024)   // gfx950: 160 KB of LDS per compute unit
 #endif
   if (lds > DPIA_LDS_CAP) {
     os << "strategy needs " << lds << " bytes of LDS per work-group (> " << DPIA_LDS_CAP << ")";

@@ -57,6 +57,7 @@ struct Plan {
   size_t ws_bytes;        // total workspace: partials + arrival counter
   size_t lds_bytes;       // dynamic LDS per work-group
   bool stage;             // contiguous order staged through LDS
+  int scal_tile;          // scal staged: elements of a row per tile (16, 32, 64)
   size_t stage_off;       // byte offset of the staging region in the LDS
 };
 

@@ -428,7 +428,10 @@ def test_batched_run_in_a_graph_replays_exactly():
 
 
 @pytest.mark.parametrize("kw", [dict(seq_len=16, local_size=256, order=T_),
-                                dict(seq_len=64, local_size=64, order=C_),
+                                dict(seq_len=64, local_size=64, order=C_),     # staged, tile 64
+                                dict(seq_len=96, local_size=128, order=C_),    # staged, tile 32
+                                dict(seq_len=16, local_size=64, order=C_),     # staged, tile 16
+                                dict(seq_len=48, local_size=48, order=C_),     # 240 threads: direct
                                 dict(seq_len=3, local_size=5, order=T_),
                                 dict(seq_len=1, local_size=1, order=C_)], ids=str)
 @pytest.mark.parametrize("n", [1, 1000, 4097, (1 << 20) + 3])
