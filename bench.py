@@ -119,7 +119,7 @@ def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
         g = S.gemv(A, xv, gplan)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 100:
+        if el >= budget_s or reps >= 1000:
             break
     parity = {
         "dot_bit_exact": bool(np.asarray(d).view(np.uint32) == np.float32(gpu_dot_val).view(np.uint32)),

@@ -269,3 +269,13 @@ def test_module_entry_points_validate_before_any_hip_call():
     args = (ctypes.c_void_p * 1)(0x7000_0000)
     assert L.dpia_module_launch(None, b"k", 1, 64, args, 1, None) == _lib.ERR_NULL
     assert L.dpia_module_unload(None) == _lib.OK
+
+
+def test_a_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback path: without libdpia.so every entry point raises
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()
+    with pytest.raises(ImportError):
+        dp.strategy_check(dp.Strategy(seq_len=4, local_size=4), dp.OP_DOT, dp.F32, 0, 16)
