@@ -238,6 +238,7 @@ def workload_precision(args):
     codes16 = synthetic.quantise_bf16(A)
     codes8, scale = synthetic.quantise_fp8_rows(A)
     results, chosen = {}, {}
+    evict = T.cache_evictor()
     cands = [dp.Strategy(seq_len=C, local_size=L, order=dp.STRIDED, wg_combine=dp.TREE)
              for C, L in PRECISION_CANDIDATES]
     for name, codes, dt, sc, nbytes in (
@@ -251,8 +252,10 @@ def workload_precision(args):
         s, table = T.tune(cands, lambda st: (lambda: dp.gemv(At, xvt, st, y=y, row_scale=sct,
                                                              a_dtype=dt)), reps=10)
         chosen[name] = s
+        # timed with the last-level cache evicted before every call (the fp8
+        # matrix alone is about the size of the 256 MB cache)
         med, p10, p90 = time_us(lambda: dp.gemv(At, xvt, s, y=y, row_scale=sct, a_dtype=dt),
-                                reps=args.steps)
+                                reps=args.steps, between=evict)
         results[name] = y.cpu().numpy()
         _line(workload="precision", op=name, m=m, k=k, strategy=strategy_text(s, gemv=True),
               us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
@@ -460,6 +463,9 @@ def workload_scal(args):
     alpha = np.float32(-1.3)
     xt = torch.from_numpy(x).cuda()
     yt = torch.empty_like(xt)
+    # in place, x is 256 MiB: evict the last-level cache before every timed call
+    from paper_1710_08332_amd.autotune import cache_evictor
+    evict = cache_evictor()
     strategies = [dp.Strategy(seq_len=C, local_size=L, order=o)
                   for C, L, o in ((16, 1024, dp.STRIDED), (64, 1024, dp.STRIDED),
                                   (256, 1024, dp.STRIDED), (16, 256, dp.CONTIGUOUS),
@@ -467,7 +473,8 @@ def workload_scal(args):
     for s in strategies:
         for place in ("out", "in"):
             dst = yt if place == "out" else xt
-            med, p10, p90 = time_us(lambda: dp.scal(float(alpha), xt, s, y=dst), reps=40)
+            med, p10, p90 = time_us(lambda: dp.scal(float(alpha), xt, s, y=dst), reps=40,
+                                    between=evict)
             _line(workload="scal", n=n, strategy=strategy_text(s), place=place,
                   us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2),
                   gbs=_gbs(8 * n, med), pct_peak=round(100 * 8 * n / med / 1e3 / PEAK_GBPS, 1))

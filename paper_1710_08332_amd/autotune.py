@@ -68,6 +68,15 @@ def sweep_gemv(m: int, k: int, max_lanes: int = 256) -> List[Strategy]:
     return out
 
 
+def cache_evictor(device=None, mib: int = 512):
+    """A callable that writes ``mib`` MiB of scratch memory: larger than the
+    MI355X's 256 MB last-level (Infinity) cache, so inputs timed after it
+    come from HBM."""
+    import torch
+    buf = torch.empty(mib << 18, dtype=torch.float32, device=device or "cuda")
+    return lambda: buf.fill_(0.0)
+
+
 def valid(s: Strategy, op: int, dtype: int, m: int, n: int) -> bool:
     try:
         strategy_check(s, op, dtype, m, n)
@@ -76,9 +85,11 @@ def valid(s: Strategy, op: int, dtype: int, m: int, n: int) -> bool:
         return False
 
 
-def time_us(fn: Callable[[], object], reps: int = 20, warmup: int = 3) -> Tuple[float, float, float]:
+def time_us(fn: Callable[[], object], reps: int = 20, warmup: int = 3,
+            between: Callable[[], object] = None) -> Tuple[float, float, float]:
     """(median, p10, p90) in microseconds of ``fn`` on torch's current stream,
-    with HIP events around each call."""
+    with HIP events around each call.  ``between`` (untimed) runs before every
+    timed call, e.g. to evict the last-level cache."""
     import torch
     for _ in range(warmup):
         fn()
@@ -86,6 +97,8 @@ def time_us(fn: Callable[[], object], reps: int = 20, warmup: int = 3) -> Tuple[
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(reps)]
     for a, b in ev:
+        if between is not None:
+            between()
         a.record()
         fn()
         b.record()

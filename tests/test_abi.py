@@ -279,3 +279,13 @@ def test_a_missing_library_fails_loudly(monkeypatch, tmp_path):
         _lib.lib()
     with pytest.raises(ImportError):
         dp.strategy_check(dp.Strategy(seq_len=4, local_size=4), dp.OP_DOT, dp.F32, 0, 16)
+
+
+@pytest.mark.parametrize("s,dt,n,want", [
+    (dp.Strategy(seq_len=16, local_size=16, accum=dp.SUM2), dp.F32, 256 * 3 + 1, _lib.ERR_SHAPE),
+    (dp.Strategy(seq_len=16, local_size=16, accum=dp.SUM2), dp.I32, 256 * 3, _lib.ERR_DTYPE),
+    (dp.Strategy(seq_len=16, local_size=16, accum=3), dp.F32, 256 * 3, _lib.ERR_STRATEGY),
+    (dp.Strategy(seq_len=16, local_size=16, accum=dp.SUM2, final_f64=1), dp.F32, 256 * 3, _lib.OK),
+])
+def test_sum2_descriptor_rules(s, dt, n, want):
+    assert check(s, dp.OP_DOT, dt, 0, n)[0] == want
