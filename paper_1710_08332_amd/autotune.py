@@ -69,12 +69,13 @@ def sweep_gemv(m: int, k: int, max_lanes: int = 256) -> List[Strategy]:
 
 
 def cache_evictor(device=None, mib: int = 512):
-    """A callable that writes ``mib`` MiB of scratch memory: larger than the
+    """A callable that reads ``mib`` MiB of scratch memory: more than the
     MI355X's 256 MB last-level (Infinity) cache, so inputs timed after it
-    come from HBM."""
+    come from HBM.  It reads rather than writes, so no dirty lines are left
+    to be written back while the timed kernel runs."""
     import torch
-    buf = torch.empty(mib << 18, dtype=torch.float32, device=device or "cuda")
-    return lambda: buf.fill_(0.0)
+    buf = torch.zeros(mib << 18, dtype=torch.float32, device=device or "cuda")
+    return lambda: buf.sum()
 
 
 def valid(s: Strategy, op: int, dtype: int, m: int, n: int) -> bool:
