@@ -182,3 +182,24 @@ def test_translation_errors():
         T.translate("(split 3 xs)", {"xs": ("f32", (8,))})
     with pytest.raises(TranslateError):      # 32-bit indices only
         T.translate("(mapGlobal (lam (e) (* e e)) xs)", {"xs": ("f32", (1 << 31,))})
+
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=40, deadline=None)
+@given(seq=st.integers(1, 6), lanes_log=st.integers(0, 4), order=st.sampled_from(["contiguous", "strided"]),
+       combine=st.sampled_from(["tree", "seq", "none"]), vec=st.sampled_from([1, 2, 4]),
+       accum=st.sampled_from(["plain", "kahan", "sum2"]), chunks=st.integers(1, 4),
+       seed=st.integers(0, 2 ** 16))
+def test_random_strategies_translate_to_the_oracle_value(seq, lanes_log, order, combine, vec,
+                                                         accum, chunks, seed):
+    # any strategy the oracle accepts: the generator's imperative program gives
+    # the oracle's bits
+    if accum != "plain" and (vec > 1 or combine == "none"):
+        vec, combine = 1, "tree"
+    p = S.Plan(seq=seq, lanes=1 << lanes_log, order=order, combine=combine, vec=vec, accum=accum)
+    n = p.chunk * chunks
+    x, y = disc(seed, n)
+    prog = T.translate(S.dot_expr(n, p), {"xs": ("f32", (n,)), "ys": ("f32", (n,))})
+    assert same(GI.run(prog, {"xs": x, "ys": y})["out"][0], S.dot(x, y, p))
