@@ -147,7 +147,9 @@ Ex = Union[Lit, Ref, Bin, Un, Cast, Select, Decode]
 # sign bit, 4 exponent bits with bias 7 and 3 mantissa bits, exponent 0
 # holds the subnormals m * 2^-9, S.1111.111 is NaN and there are no
 # infinities.
-DECODERS = """__device__ __forceinline__ float dpia_bf16(unsigned short c) {
+DECODERS = """typedef float dpia_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned dpia_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float dpia_bf16(unsigned short c) {
   return __uint_as_float(static_cast<unsigned>(c) << 16);
 }
 __device__ __forceinline__ float dpia_fp8(unsigned char c) {

@@ -118,6 +118,10 @@ class Generated:
                 if not t.is_contiguous() or t.numel() < b["elems"] or t.device.type != "cuda":
                     raise ValueError(f"input {b['name']} must be a contiguous device tensor of "
                                      f"{b['elems']} elements")
+                if t.data_ptr() % 16:
+                    # the generated kernels read adjacent lanes' elements with
+                    # 16-byte loads
+                    raise ValueError(f"input {b['name']} must be 16-byte aligned")
             elif b["kind"] == "out":
                 t = outs[b["name"]]
                 if t.numel() < b["elems"]:

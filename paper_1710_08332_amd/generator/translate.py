@@ -633,10 +633,10 @@ def translate(text: str, inputs: Dict[str, Tuple[str, Tuple[int, ...]]], num: st
     if big or _max_extent(top) >= (1 << 31):
         # every index is computed in 32-bit int arithmetic
         raise TranslateError(f"arrays or loops of 2^31 elements or more ({big or 'a loop'})")
-    kernels = _split(top, name)
+    kernels = _split(top, name, frozenset(b.name for b in t.buffers if b.kind == "in"))
     types = {b.name: b.ctype for b in t.buffers}
     _collect_types(top, types)
-    src = _emit(kernels, t.buffers, types)
+    src = _emit(kernels, t.buffers, types, t.dims)
     return Program(src, kernels, t.buffers, out_ty, types, dict(t.dims))
 
 
@@ -658,7 +658,7 @@ def _collect_types(cmds, types):
             _collect_types(c.body, types)
 
 
-def _split(top: list, name: str) -> List[Kernel]:
+def _split(top: list, name: str, inputs=frozenset()) -> List[Kernel]:
     kernels: List[Kernel] = []
     seq: list = []
 
@@ -670,7 +670,7 @@ def _split(top: list, name: str) -> List[Kernel]:
         if isinstance(c, ParFor) and c.level in ("workgroup", "global"):
             flush()
             kernels.append(Kernel(f"{name}_k{len(kernels)}", c.level, [c], c.n,
-                                  _local_width(c.body)))
+                                  _local_width(c.body, inputs)))
         elif isinstance(c, Decl) and c.space == "global":
             continue
         else:
@@ -679,14 +679,23 @@ def _split(top: list, name: str) -> List[Kernel]:
     return kernels
 
 
-def _local_width(body) -> int:
-    w = 1
-    for c in body:
-        if isinstance(c, ParFor) and c.level == "local":
-            w = max(w, c.n)
-        if isinstance(c, (For, ParFor)):
-            w = max(w, _local_width(c.body))
-    return w
+def _local_width(body, inputs=frozenset()) -> int:
+    """Work-items per work-group: enough for the widest coarsened mapLocal
+    (LANES lanes per work-item), else for the widest mapLocal.  Other
+    mapLocal loops are block-stride loops and run with any width."""
+    plain, coarse = [1], [0]
+
+    def walk(cmds):
+        for c in cmds:
+            if isinstance(c, ParFor) and c.level == "local":
+                if _coarsenable(c, inputs):
+                    coarse[0] = max(coarse[0], c.n // LANES)
+                else:
+                    plain[0] = max(plain[0], c.n)
+            if isinstance(c, (For, ParFor)):
+                walk(c.body)
+    walk(body)
+    return coarse[0] if coarse[0] else plain[0]
 
 
 def block_size(k: Kernel) -> int:
@@ -716,8 +725,22 @@ def _has_local_loop(body) -> bool:
     return False
 
 
-def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -> str:
+# Large one-dimensional inputs (vectors of at least STREAM_BYTES) are read
+# with non-temporal loads; matrices and small vectors with cached loads.  This
+# is the policy measured best for the hand-written kernels (streamed dot
+# operands non-temporal, the rows of a binary32 gemv cached).
+STREAM_BYTES = 64 << 20
+
+
+def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str],
+          dims: Dict[str, tuple] = None) -> str:
+    dims = dims or {}
     inputs = {b.name for b in buffers if b.kind == "in"}
+    size = {"float": 4, "unsigned": 4, "double": 8, "unsigned short": 2, "unsigned char": 1}
+    _STREAMED.clear()
+    _STREAMED.update(b.name for b in buffers
+                     if b.kind == "in" and len(dims.get(b.name, ())) == 1
+                     and b.elems * size.get(b.ctype, 4) >= STREAM_BYTES)
     lines = ["#include <hip/hip_runtime.h>",
              "// generated from a DPIA expression: one operation per node, no contraction",
              "#pragma clang fp contract(off)", "", ir.DECODERS]
@@ -773,6 +796,9 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
                 _emit_block(c.body, out, shared, depth + 1, types, inputs)
                 out.append(f"{pad}  __syncthreads();")
                 out.append(f"{pad}}}")
+            elif c.level == "local" and _coarsenable(c, inputs):
+                _emit_coarsened(c, out, shared, depth, types, inputs)
+                out.append(f"{pad}__syncthreads();")
             elif c.level == "local":
                 out.append(f"{pad}for (int {v} = threadIdx.x; {v} < {n}; {v} += blockDim.x) {{")
                 _emit_block(c.body, out, shared, depth + 1, types, inputs)
@@ -795,7 +821,8 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
 # every operation and its order are unchanged; the loads are in flight
 # together instead of one after another.
 
-BATCH_ELEMS = 16
+BATCH_ELEMS = 32
+_STREAMED: set = set()      # names of the inputs read with non-temporal loads
 
 
 def _ix_uses(e, var: str) -> bool:
@@ -853,7 +880,10 @@ def _batchable(c: For, inputs) -> bool:
     return bool(loads) and c.n >= 2 * max(1, BATCH_ELEMS // len(loads))
 
 
-def _emit_batched(c: For, out, shared, depth, types, inputs):
+def _emit_batched(c: For, out, shared, depth, types, inputs, quads=()):
+    """``quads``: groups of 4 loads (as they appear in the body) known to read
+    4 consecutive elements from a 16-byte aligned position; each is read with
+    one 16-byte load."""
     pad = "  " * depth
     loads = _loads(c.body, c.var, inputs)
     B = max(1, BATCH_ELEMS // len(loads))
@@ -861,12 +891,27 @@ def _emit_batched(c: For, out, shared, depth, types, inputs):
     out.append(f"{pad}int {k} = 0;")
     out.append(f"{pad}for (; {k} + {B} <= {c.n}; {k} += {B}) {{")
     regs = {}
+    in_quad = {r for q in quads for r in q}
     for u in range(B):
+        for qi, q in enumerate(quads):
+            name = f"{k}_q{u}_{qi}"
+            idx0 = _ix_sub(q[0].idx, k, u)
+            vt = "dpia_f4" if types[q[0].name] == "float" else "dpia_u4"
+            ptr = f"reinterpret_cast<const {vt}*>({q[0].name} + {ir.ix_c(idx0)})"
+            load = f"__builtin_nontemporal_load({ptr})" if q[0].name in _STREAMED else f"*{ptr}"
+            out.append(f"{pad}  const {vt} {name} = {load};")
+            for j, r in enumerate(q):
+                regs[(u, ir.Ref(r.name, _ix_sub(r.idx, k, u)))] = f"{name}.{'xyzw'[j]}"
         for j, r in enumerate(loads):
+            if r in in_quad:
+                continue
             name = f"{k}_r{u}_{j}"
             idx = _ix_sub(r.idx, k, u)
             regs[(u, ir.Ref(r.name, idx))] = name
-            out.append(f"{pad}  const {types[r.name]} {name} = {r.name}[{ir.ix_c(idx)}];")
+            elem = f"{r.name}[{ir.ix_c(idx)}]"
+            if r.name in _STREAMED:
+                elem = f"__builtin_nontemporal_load(&{elem})"
+            out.append(f"{pad}  const {types[r.name]} {name} = {elem};")
     out.append(f"{pad}  __builtin_amdgcn_sched_barrier(0);")
     for u in range(B):
         def sub(ref, u=u):
@@ -887,4 +932,124 @@ def _emit_batched(c: For, out, shared, depth, types, inputs):
     out.append(f"{pad}}}")
     out.append(f"{pad}for (; {k} < {c.n}; ++{k}) {{")
     _emit_block(c.body, out, shared, depth + 1, types, inputs)
+    out.append(f"{pad}}}")
+
+
+# ------------------------------------------------------------------ lane coarsening
+# A mapLocal loop whose lanes each fold read-only inputs (straight-line code
+# around sequential loops of straight-line code) runs LANES adjacent lanes per
+# work-item: the lanes' commands are copied with their private variables
+# renamed, and their fold loops are fused, each lane's steps still in its own
+# increasing order (the lanes are independent iterations, Stage II).  Where
+# the 4 lanes read 4 consecutive, 16-byte aligned input elements, one 16-byte
+# load serves them.  Nothing else changes: the same operations in the same
+# order per lane.
+
+LANES = 4
+
+
+def _straight(body) -> bool:
+    return all(isinstance(b, Assign) or (isinstance(b, Decl) and b.space == "private")
+               for b in body)
+
+
+def _coarsenable(c: ParFor, inputs) -> bool:
+    if c.level != "local" or c.n % LANES or c.n < 64 * LANES:
+        return False
+    folds = 0
+    for b in c.body:
+        if isinstance(b, For):
+            if not _straight(b.body):
+                return False
+            folds += _batchable(b, inputs)
+        elif not (isinstance(b, Assign) or (isinstance(b, Decl) and b.space == "private")):
+            return False
+    return folds > 0
+
+
+def _ix_replace(e, var: str, by):
+    if isinstance(e, ir.IVar) and e.name == var:
+        return by
+    if isinstance(e, ir.IBin):
+        return ir.IBin(e.op, _ix_replace(e.a, var, by), _ix_replace(e.b, var, by))
+    return e
+
+
+def _declared(body, acc: set):
+    for b in body:
+        if isinstance(b, Decl):
+            acc.add(b.name)
+        elif isinstance(b, For):
+            _declared(b.body, acc)
+    return acc
+
+
+def _lane_copy(body, var: str, by, ren: Dict[str, str]):
+    def rref(r):
+        return ir.Ref(ren.get(r.name, r.name),
+                      None if r.idx is None else _ix_replace(r.idx, var, by))
+    out = []
+    for b in body:
+        if isinstance(b, Decl):
+            out.append(Decl(ren.get(b.name, b.name), b.ctype, b.size, b.space))
+        elif isinstance(b, Assign):
+            out.append(Assign(ren.get(b.name, b.name),
+                              None if b.idx is None else _ix_replace(b.idx, var, by),
+                              _ex_map(b.rhs, rref), b.space, b.ctx))
+        else:
+            out.append(For(b.var, b.n, _lane_copy(b.body, var, by, ren)))
+    return out
+
+
+def _additive_once(e, var: str) -> int:
+    """Occurrences of var if it appears only as a summand (else -1)."""
+    if isinstance(e, ir.IVar):
+        return 1 if e.name == var else 0
+    if isinstance(e, ir.IConst):
+        return 0
+    if e.op == "+":
+        a, b = _additive_once(e.a, var), _additive_once(e.b, var)
+        return -1 if a < 0 or b < 0 else a + b
+    return -1 if _ix_uses(e, var) else 0
+
+
+def _aligned4(e, base: str) -> bool:
+    """e is a multiple of 4 for every value of the loop variables (base is a
+    multiple of 4 by construction)."""
+    if isinstance(e, ir.IConst):
+        return e.v % 4 == 0
+    if isinstance(e, ir.IVar):
+        return e.name == base
+    if e.op == "+":
+        return _aligned4(e.a, base) and _aligned4(e.b, base)
+    if e.op == "*":
+        return _aligned4(e.a, base) or _aligned4(e.b, base)
+    return False
+
+
+def _emit_coarsened(c: ParFor, out, shared, depth, types, inputs):
+    pad = "  " * depth
+    base = c.var + "_q"
+    names = _declared(c.body, set())
+    copies = []
+    for j in range(LANES):
+        ren = {nm: f"{nm}_{j}" for nm in names}
+        copies.append(_lane_copy(c.body, c.var, iadd(ir.IVar(base), j), ren))
+    out.append(f"{pad}for (int {base} = threadIdx.x * {LANES}; {base} < {c.n};"
+               f" {base} += blockDim.x * {LANES}) {{")
+    for pos, b in enumerate(c.body):
+        if not isinstance(b, For):
+            _emit_block([cp[pos] for cp in copies], out, shared, depth + 1, types, inputs)
+            continue
+        fused = For(b.var, b.n, [x for cp in copies for x in cp[pos].body])
+        quads = []
+        for r in _loads(b.body, b.var, inputs):
+            if types[r.name] in ("float", "unsigned") and _additive_once(r.idx, c.var) == 1 \
+                    and _aligned4(_ix_replace(r.idx, c.var, ir.IVar(base)), base):
+                quads.append(tuple(ir.Ref(r.name, _ix_replace(r.idx, c.var, iadd(ir.IVar(base), j)))
+                                   for j in range(LANES)))
+        if _batchable(fused, inputs):
+            _emit_batched(fused, out, shared, depth + 1, types, inputs, tuple(quads))
+        else:
+            _emit_block([fused], out, shared, depth + 1, types, inputs)
     out.append(f"{pad}}}")
