@@ -841,6 +841,24 @@ def _ix_sub(e, var: str, u: int):
     return e
 
 
+def _ex_ix(e, g):
+    """Rebuilds expression e with g applied to every index expression (array
+    positions and Select selectors)."""
+    if isinstance(e, ir.Ref):
+        return e if e.idx is None else ir.Ref(e.name, g(e.idx))
+    if isinstance(e, ir.Bin):
+        return ir.Bin(e.op, _ex_ix(e.a, g), _ex_ix(e.b, g))
+    if isinstance(e, ir.Un):
+        return ir.Un(e.op, _ex_ix(e.a, g))
+    if isinstance(e, ir.Cast):
+        return ir.Cast(e.ctype, _ex_ix(e.a, g))
+    if isinstance(e, ir.Select):
+        return ir.Select(g(e.sel), tuple(_ex_ix(o, g) for o in e.options))
+    if isinstance(e, ir.Decode):
+        return ir.Decode(e.fmt, _ex_ix(e.a, g))
+    return e
+
+
 def _ex_map(e, f):
     """Rebuilds expression e with f applied to every Ref."""
     if isinstance(e, ir.Ref):
@@ -859,10 +877,14 @@ def _ex_map(e, f):
 
 
 def _loads(body, var: str, inputs) -> List[ir.Ref]:
+    """Array reads at loop-dependent positions that can be issued early: of
+    the read-only inputs, or of any array the loop body does not write."""
+    written = {c.name for c in body if isinstance(c, Assign)}
     found: List[ir.Ref] = []
 
     def visit(r):
-        if r.name in inputs and r.idx is not None and _ix_uses(r.idx, var) and r not in found:
+        if r.idx is not None and _ix_uses(r.idx, var) and r not in found and \
+                (r.name in inputs or r.name not in written):
             found.append(r)
         return r
     for c in body:
@@ -914,16 +936,16 @@ def _emit_batched(c: For, out, shared, depth, types, inputs, quads=()):
             out.append(f"{pad}  const {types[r.name]} {name} = {elem};")
     out.append(f"{pad}  __builtin_amdgcn_sched_barrier(0);")
     for u in range(B):
-        def sub(ref, u=u):
-            if ref.idx is None:
-                return ref
-            moved = ir.Ref(ref.name, _ix_sub(ref.idx, k, u))
-            return ir.Ref(regs[(u, moved)], None) if (u, moved) in regs else moved
+        def reg(ref, u=u):
+            return ir.Ref(regs[(u, ref)], None) if (u, ref) in regs else ref
         step = []
         for b in c.body:
             if isinstance(b, Assign):
+                # iteration k + u: every index moves (selectors included), then
+                # the reads issued above take the place of their loads
                 idx = _ix_sub(b.idx, k, u) if b.idx is not None else None
-                step.append(Assign(b.name, idx, _ex_map(b.rhs, sub), b.space, b.ctx))
+                rhs = _ex_map(_ex_ix(b.rhs, lambda e, u=u: _ix_sub(e, k, u)), reg)
+                step.append(Assign(b.name, idx, rhs, b.space, b.ctx))
             else:
                 step.append(b)
         out.append(f"{pad}  {{")
@@ -985,17 +1007,17 @@ def _declared(body, acc: set):
 
 
 def _lane_copy(body, var: str, by, ren: Dict[str, str]):
-    def rref(r):
-        return ir.Ref(ren.get(r.name, r.name),
-                      None if r.idx is None else _ix_replace(r.idx, var, by))
+    def rename(r):
+        return ir.Ref(ren.get(r.name, r.name), r.idx)
     out = []
     for b in body:
         if isinstance(b, Decl):
             out.append(Decl(ren.get(b.name, b.name), b.ctype, b.size, b.space))
         elif isinstance(b, Assign):
+            rhs = _ex_map(_ex_ix(b.rhs, lambda e: _ix_replace(e, var, by)), rename)
             out.append(Assign(ren.get(b.name, b.name),
                               None if b.idx is None else _ix_replace(b.idx, var, by),
-                              _ex_map(b.rhs, rref), b.space, b.ctx))
+                              rhs, b.space, b.ctx))
         else:
             out.append(For(b.var, b.n, _lane_copy(b.body, var, by, ren)))
     return out
