@@ -242,4 +242,53 @@ class ParFor:
     body: List[object]
 
 
-Cmd = Union[Decl, Assign, For, ParFor]
+@dataclass
+class Load:
+    """A private constant ``name`` = buf[idx] (non-temporal if ``nt``)."""
+    name: str
+    ctype: str
+    buf: str
+    idx: IX
+    nt: bool = False
+
+
+@dataclass
+class VLoad:
+    """A private 4-vector ``name`` = buf[idx .. idx+3], read at once; idx is a
+    multiple of 4.  Its components are Ref(name, IConst(j))."""
+    name: str
+    ctype: str
+    buf: str
+    idx: IX
+    nt: bool = False
+
+
+@dataclass
+class SchedBarrier:
+    """Keeps the loads before it ahead of the code after it (scheduling only)."""
+
+
+@dataclass
+class Blocked:
+    """``for var in 0, step, ...`` while var + step <= n, running ``main``
+    (which covers iterations var .. var + step - 1), then ``tail`` for each
+    remaining var < n."""
+    var: str
+    n: int
+    step: int
+    main: List[object]
+    tail: List[object]
+
+
+@dataclass
+class Lanes:
+    """A mapLocal loop run ``lanes`` adjacent iterations per work-item: for
+    base = lanes * work-item, base < n, base += lanes * work-items, ``body``
+    (which covers iterations base .. base + lanes - 1)."""
+    var: str
+    n: int
+    lanes: int
+    body: List[object]
+
+
+Cmd = Union[Decl, Assign, For, ParFor, Load, VLoad, SchedBarrier, Blocked, Lanes]

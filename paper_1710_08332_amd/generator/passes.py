@@ -1,0 +1,293 @@
+"""Optimisations of the imperative program, as program-to-program passes.
+
+Each pass keeps every arithmetic operation and, for each accumulator, the
+order of its updates: it only changes when reads happen and which work-item
+runs which independent iteration.  The passes run before emission, so the
+test suite executes their output on the CPU (against the oracle) exactly as
+the GPU runs it.
+
+1. ``extract_loads``: in a sequential loop of straight-line code, every read
+   of an array at a loop-dependent position, of an input or of an array the
+   loop does not write, becomes a private constant (``Load``) at the start of
+   the body.
+2. ``coarsen``: a mapLocal loop of at least 4 * 64 lanes, whose lanes are
+   straight-line code around such loops, runs 4 adjacent lanes per
+   work-item (``Lanes``): the lanes' commands are copied with their private
+   names renamed and their loops fused, each lane's steps in its own order
+   (lanes are independent iterations, Stage II).  Where the 4 lanes read 4
+   consecutive elements from an index that is a multiple of 4, one 16-byte
+   ``VLoad`` serves them.
+3. ``batch``: such a loop runs B iterations per round (``Blocked``): the
+   loads of all B iterations first, then the B steps in increasing order, so
+   B iterations' loads are in flight together.
+"""
+
+from __future__ import annotations
+
+from typing import Dict, List, Set
+
+from . import ir
+from .ir import (Assign, Blocked, Decl, For, IConst, IVar, Lanes, Load, ParFor, Ref,
+                 SchedBarrier, VLoad, iadd)
+
+LANES = 4
+BATCH_ELEMS = 32          # elements' worth of loads issued per round
+
+
+# ------------------------------------------------------------------ helpers
+
+def ix_uses(e, var: str) -> bool:
+    if isinstance(e, IVar):
+        return e.name == var
+    if isinstance(e, ir.IBin):
+        return ix_uses(e.a, var) or ix_uses(e.b, var)
+    return False
+
+
+def ix_replace(e, var: str, by):
+    if isinstance(e, IVar) and e.name == var:
+        return by
+    if isinstance(e, ir.IBin):
+        return ir.IBin(e.op, ix_replace(e.a, var, by), ix_replace(e.b, var, by))
+    return e
+
+
+def ex_ix(e, g):
+    """e with g applied to every index expression (positions and selectors)."""
+    if isinstance(e, Ref):
+        return e if e.idx is None else Ref(e.name, g(e.idx))
+    if isinstance(e, ir.Bin):
+        return ir.Bin(e.op, ex_ix(e.a, g), ex_ix(e.b, g))
+    if isinstance(e, ir.Un):
+        return ir.Un(e.op, ex_ix(e.a, g))
+    if isinstance(e, ir.Cast):
+        return ir.Cast(e.ctype, ex_ix(e.a, g))
+    if isinstance(e, ir.Select):
+        return ir.Select(g(e.sel), tuple(ex_ix(o, g) for o in e.options))
+    if isinstance(e, ir.Decode):
+        return ir.Decode(e.fmt, ex_ix(e.a, g))
+    return e
+
+
+def ex_refs(e, f):
+    """e with f applied to every Ref."""
+    if isinstance(e, Ref):
+        return f(e)
+    if isinstance(e, ir.Bin):
+        return ir.Bin(e.op, ex_refs(e.a, f), ex_refs(e.b, f))
+    if isinstance(e, ir.Un):
+        return ir.Un(e.op, ex_refs(e.a, f))
+    if isinstance(e, ir.Cast):
+        return ir.Cast(e.ctype, ex_refs(e.a, f))
+    if isinstance(e, ir.Select):
+        return ir.Select(e.sel, tuple(ex_refs(o, f) for o in e.options))
+    if isinstance(e, ir.Decode):
+        return ir.Decode(e.fmt, ex_refs(e.a, f))
+    return e
+
+
+def _straight(body) -> bool:
+    return all(isinstance(b, (Assign, Load, VLoad)) or
+               (isinstance(b, Decl) and b.space == "private") for b in body)
+
+
+def _rewrite(cmd, g_ix, ren: Dict[str, str]):
+    """A straight-line command with index map g_ix and private names renamed."""
+    def rn(r):
+        return Ref(ren.get(r.name, r.name), r.idx)
+    if isinstance(cmd, Decl):
+        return Decl(ren.get(cmd.name, cmd.name), cmd.ctype, cmd.size, cmd.space)
+    if isinstance(cmd, Assign):
+        return Assign(ren.get(cmd.name, cmd.name), None if cmd.idx is None else g_ix(cmd.idx),
+                      ex_refs(ex_ix(cmd.rhs, g_ix), rn), cmd.space, cmd.ctx)
+    if isinstance(cmd, (Load, VLoad)):
+        return type(cmd)(ren.get(cmd.name, cmd.name), cmd.ctype, cmd.buf, g_ix(cmd.idx), cmd.nt)
+    raise TypeError(f"not straight-line: {cmd!r}")
+
+
+def _defined(body) -> Set[str]:
+    out = set()
+    for b in body:
+        if isinstance(b, (Decl, Load, VLoad)):
+            out.add(b.name)
+        elif isinstance(b, (For, Blocked)):
+            out |= _defined(b.body if isinstance(b, For) else b.main + b.tail)
+    return out
+
+
+# ------------------------------------------------------------------ 1. loads
+
+def extract_loads(cmds, inputs: Set[str], streamed: Set[str], types: Dict[str, str], fresh):
+    out = []
+    for c in cmds:
+        if isinstance(c, For) and _straight(c.body):
+            out.append(For(c.var, c.n, _loads_first(c.body, c.var, inputs, streamed, types, fresh)))
+        elif isinstance(c, For):
+            out.append(For(c.var, c.n, extract_loads(c.body, inputs, streamed, types, fresh)))
+        elif isinstance(c, ParFor):
+            out.append(ParFor(c.level, c.var, c.n,
+                              extract_loads(c.body, inputs, streamed, types, fresh)))
+        else:
+            out.append(c)
+    return out
+
+
+def _loads_first(body, var, inputs, streamed, types, fresh):
+    written = {b.name for b in body if isinstance(b, Assign)}
+    regs: Dict[Ref, str] = {}
+    loads: List[Load] = []
+
+    def take(r):
+        if r.idx is None or not ix_uses(r.idx, var):
+            return r
+        if r.name not in inputs and r.name in written:
+            return r
+        if r not in regs:
+            regs[r] = fresh("ld")
+            loads.append(Load(regs[r], types[r.name], r.name, r.idx, r.name in streamed))
+        return Ref(regs[r], None)
+    rest = []
+    for b in body:
+        if isinstance(b, Assign):
+            rest.append(Assign(b.name, b.idx, ex_refs(b.rhs, take), b.space, b.ctx))
+        else:
+            rest.append(b)
+    return loads + rest
+
+
+# ------------------------------------------------------------------ 2. coarsen
+
+def _coarsenable(c: ParFor) -> bool:
+    if c.level != "local" or c.n % LANES or c.n < 64 * LANES:
+        return False
+    loops = [b for b in c.body if isinstance(b, For)]
+    if not loops or not all(_straight(b.body) for b in loops):
+        return False
+    if not any(isinstance(x, Load) for b in loops for x in b.body):
+        return False
+    return all(isinstance(b, (For, Assign)) or (isinstance(b, Decl) and b.space == "private")
+               for b in c.body)
+
+
+def _additive_once(e, var: str) -> int:
+    """How often var occurs, if only as a summand (else -1)."""
+    if isinstance(e, IVar):
+        return 1 if e.name == var else 0
+    if isinstance(e, IConst):
+        return 0
+    if e.op == "+":
+        a, b = _additive_once(e.a, var), _additive_once(e.b, var)
+        return -1 if a < 0 or b < 0 else a + b
+    return -1 if ix_uses(e, var) else 0
+
+
+def _aligned4(e, base: str) -> bool:
+    """e is a multiple of 4 for all values (base is one by construction)."""
+    if isinstance(e, IConst):
+        return e.v % 4 == 0
+    if isinstance(e, IVar):
+        return e.name == base
+    if e.op == "+":
+        return _aligned4(e.a, base) and _aligned4(e.b, base)
+    if e.op == "*":
+        return _aligned4(e.a, base) or _aligned4(e.b, base)
+    return False
+
+
+def coarsen(cmds, types: Dict[str, str], fresh):
+    out = []
+    for c in cmds:
+        if isinstance(c, ParFor) and _coarsenable(c):
+            out.append(_coarsened(c, types, fresh))
+        elif isinstance(c, ParFor):
+            out.append(ParFor(c.level, c.var, c.n, coarsen(c.body, types, fresh)))
+        elif isinstance(c, For):
+            out.append(For(c.var, c.n, coarsen(c.body, types, fresh)))
+        else:
+            out.append(c)
+    return out
+
+
+def _coarsened(c: ParFor, types, fresh) -> Lanes:
+    base = fresh(c.var + "q")
+    names = _defined(c.body)
+    ren = [{nm: f"{nm}_{j}" for nm in names} for j in range(LANES)]
+
+    def lane_ix(j):
+        by = iadd(IVar(base), j)
+        return lambda e: ix_replace(e, c.var, by)
+    body = []
+    for b in c.body:
+        if not isinstance(b, For):
+            body += [_rewrite(b, lane_ix(j), ren[j]) for j in range(LANES)]
+            continue
+        # loads of the 4 lanes that are 4 consecutive, 4-aligned elements
+        quad_of: Dict[str, str] = {}
+        vloads = []
+        for ld in (x for x in b.body if isinstance(x, Load)):
+            if types[ld.buf] in ("float", "unsigned") and _additive_once(ld.idx, c.var) == 1 \
+                    and _aligned4(ix_replace(ld.idx, c.var, IVar(base)), base):
+                q = fresh("vq")
+                vloads.append(VLoad(q, ld.ctype, ld.buf, ix_replace(ld.idx, c.var, IVar(base)),
+                                    ld.nt))
+                quad_of[ld.name] = q
+        fused = list(vloads)
+        for j in range(LANES):
+            alias = {f"{nm}_{j}": q for nm, q in quad_of.items()}
+
+            def comp(r, alias=alias, j=j):
+                return Ref(alias[r.name], IConst(j)) if r.name in alias else r
+            for x in b.body:
+                if isinstance(x, Load) and x.name in quad_of:
+                    continue                          # served by the VLoad
+                y = _rewrite(x, lane_ix(j), ren[j])
+                if isinstance(y, Assign):
+                    y = Assign(y.name, y.idx, ex_refs(y.rhs, comp), y.space, y.ctx)
+                fused.append(y)
+        body.append(For(b.var, b.n, fused))
+    return Lanes(base, c.n, LANES, body)
+
+
+# ------------------------------------------------------------------ 3. batch
+
+def batch(cmds, fresh):
+    out = []
+    for c in cmds:
+        if isinstance(c, For) and _straight(c.body):
+            out.append(_batched(c) or c)
+        elif isinstance(c, For):
+            out.append(For(c.var, c.n, batch(c.body, fresh)))
+        elif isinstance(c, ParFor):
+            out.append(ParFor(c.level, c.var, c.n, batch(c.body, fresh)))
+        elif isinstance(c, Lanes):
+            out.append(Lanes(c.var, c.n, c.lanes, batch(c.body, fresh)))
+        else:
+            out.append(c)
+    return out
+
+
+def _batched(c: For):
+    loads = [b for b in c.body if isinstance(b, (Load, VLoad)) and ix_uses(b.idx, c.var)]
+    if not loads:
+        return None
+    elems = sum(4 if isinstance(b, VLoad) else 1 for b in loads)
+    B = max(1, BATCH_ELEMS // elems)
+    if c.n < 2 * B:
+        return None
+    names = _defined(c.body)
+    first, rest = [], []
+    for u in range(B):
+        ren = {nm: f"{nm}_u{u}" for nm in names}
+
+        def shift(e, u=u):
+            return ix_replace(e, c.var, iadd(IVar(c.var), u))
+        for b in c.body:
+            y = _rewrite(b, shift, ren)
+            (first if isinstance(b, (Load, VLoad)) else rest).append(y)
+    return Blocked(c.var, c.n, B, first + [SchedBarrier()] + rest, c.body)
+
+
+def optimise(cmds, inputs: Set[str], streamed: Set[str], types: Dict[str, str], fresh):
+    cmds = extract_loads(cmds, inputs, streamed, types, fresh)
+    cmds = coarsen(cmds, types, fresh)
+    return batch(cmds, fresh)

@@ -49,7 +49,7 @@ import itertools
 from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional, Tuple, Union
 
-from . import ir
+from . import ir, passes
 from .ir import Assign, Decl, For, IX, ParFor, iadd, idiv, imod, imul
 from .lang import (MAPS, REDUCES, SPACES, Arr, Call, Lam, Lit, Name, Node, Num, Pair, Type,
                    Vec, check, parse)
@@ -614,7 +614,7 @@ class Program:
 
 
 def translate(text: str, inputs: Dict[str, Tuple[str, Tuple[int, ...]]], num: str = "f32",
-              name: str = "dpia") -> Program:
+              name: str = "dpia", optimise: bool = True) -> Program:
     """Expression text -> Program.  ``inputs`` maps each free name to its
     element type and shape; the result is written to ``out`` (stored
     component-wise for pairs: out_a, out_b)."""
@@ -633,10 +633,14 @@ def translate(text: str, inputs: Dict[str, Tuple[str, Tuple[int, ...]]], num: st
     if big or _max_extent(top) >= (1 << 31):
         # every index is computed in 32-bit int arithmetic
         raise TranslateError(f"arrays or loops of 2^31 elements or more ({big or 'a loop'})")
-    kernels = _split(top, name, frozenset(b.name for b in t.buffers if b.kind == "in"))
     types = {b.name: b.ctype for b in t.buffers}
     _collect_types(top, types)
-    src = _emit(kernels, t.buffers, types, t.dims)
+    if optimise:
+        top = passes.optimise(top, {b.name for b in t.buffers if b.kind == "in"},
+                              _streamed(t.buffers, t.dims), types, t.fresh)
+        _collect_types(top, types)
+    kernels = _split(top, name)
+    src = _emit(kernels, t.buffers, types)
     return Program(src, kernels, t.buffers, out_ty, types, dict(t.dims))
 
 
@@ -652,13 +656,15 @@ def _max_extent(cmds) -> int:
 
 def _collect_types(cmds, types):
     for c in cmds:
-        if isinstance(c, Decl):
+        if isinstance(c, (Decl, ir.Load, ir.VLoad)):
             types[c.name] = c.ctype
-        elif isinstance(c, (For, ParFor)):
+        elif isinstance(c, (For, ParFor, ir.Lanes)):
             _collect_types(c.body, types)
+        elif isinstance(c, ir.Blocked):
+            _collect_types(c.main + c.tail, types)
 
 
-def _split(top: list, name: str, inputs=frozenset()) -> List[Kernel]:
+def _split(top: list, name: str) -> List[Kernel]:
     kernels: List[Kernel] = []
     seq: list = []
 
@@ -670,7 +676,7 @@ def _split(top: list, name: str, inputs=frozenset()) -> List[Kernel]:
         if isinstance(c, ParFor) and c.level in ("workgroup", "global"):
             flush()
             kernels.append(Kernel(f"{name}_k{len(kernels)}", c.level, [c], c.n,
-                                  _local_width(c.body, inputs)))
+                                  _local_width(c.body)))
         elif isinstance(c, Decl) and c.space == "global":
             continue
         else:
@@ -679,21 +685,25 @@ def _split(top: list, name: str, inputs=frozenset()) -> List[Kernel]:
     return kernels
 
 
-def _local_width(body, inputs=frozenset()) -> int:
+def _local_width(body) -> int:
     """Work-items per work-group: enough for the widest coarsened mapLocal
-    (LANES lanes per work-item), else for the widest mapLocal.  Other
-    mapLocal loops are block-stride loops and run with any width."""
+    (Lanes), else for the widest mapLocal.  Other mapLocal loops are
+    block-stride loops and run with any width."""
     plain, coarse = [1], [0]
 
     def walk(cmds):
         for c in cmds:
-            if isinstance(c, ParFor) and c.level == "local":
-                if _coarsenable(c, inputs):
-                    coarse[0] = max(coarse[0], c.n // LANES)
-                else:
-                    plain[0] = max(plain[0], c.n)
-            if isinstance(c, (For, ParFor)):
+            if isinstance(c, ir.Lanes):
+                coarse[0] = max(coarse[0], c.n // c.lanes)
                 walk(c.body)
+            elif isinstance(c, ParFor):
+                if c.level == "local":
+                    plain[0] = max(plain[0], c.n)
+                walk(c.body)
+            elif isinstance(c, For):
+                walk(c.body)
+            elif isinstance(c, ir.Blocked):
+                walk(c.main + c.tail)
     walk(body)
     return coarse[0] if coarse[0] else plain[0]
 
@@ -718,7 +728,7 @@ def grid_size(k: Kernel, cus: int = 256) -> int:
 
 def _has_local_loop(body) -> bool:
     for c in body:
-        if isinstance(c, ParFor) and c.level == "local":
+        if isinstance(c, ir.Lanes) or (isinstance(c, ParFor) and c.level == "local"):
             return True
         if isinstance(c, (For, ParFor)) and _has_local_loop(c.body):
             return True
@@ -730,17 +740,16 @@ def _has_local_loop(body) -> bool:
 # is the policy measured best for the hand-written kernels (streamed dot
 # operands non-temporal, the rows of a binary32 gemv cached).
 STREAM_BYTES = 64 << 20
+_SIZE = {"float": 4, "unsigned": 4, "double": 8, "unsigned short": 2, "unsigned char": 1}
 
 
-def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str],
-          dims: Dict[str, tuple] = None) -> str:
-    dims = dims or {}
-    inputs = {b.name for b in buffers if b.kind == "in"}
-    size = {"float": 4, "unsigned": 4, "double": 8, "unsigned short": 2, "unsigned char": 1}
-    _STREAMED.clear()
-    _STREAMED.update(b.name for b in buffers
-                     if b.kind == "in" and len(dims.get(b.name, ())) == 1
-                     and b.elems * size.get(b.ctype, 4) >= STREAM_BYTES)
+def _streamed(buffers: List[Buffer], dims: Dict[str, tuple]) -> set:
+    return {b.name for b in buffers
+            if b.kind == "in" and len(dims.get(b.name, ())) == 1
+            and b.elems * _SIZE.get(b.ctype, 4) >= STREAM_BYTES}
+
+
+def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -> str:
     lines = ["#include <hip/hip_runtime.h>",
              "// generated from a DPIA expression: one operation per node, no contraction",
              "#pragma clang fp contract(off)", "", ir.DECODERS]
@@ -749,7 +758,7 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str],
     for k in kernels:
         body: List[str] = []
         shared: List[str] = []
-        _emit_block(k.body, body, shared, 1, types, inputs)
+        _emit_block(k.body, body, shared, 1, types)
         lines.append(f'extern "C" __global__ void __launch_bounds__({block_size(k)}) '
                      f"{k.name}({params}) {{")
         lines.extend("  " + s for s in shared)
@@ -759,8 +768,10 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str],
     return "\n".join(lines)
 
 
-def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict[str, str],
-                inputs=frozenset()):
+_VEC = {"float": "dpia_f4", "unsigned": "dpia_u4"}
+
+
+def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict[str, str]):
     pad = "  " * depth
     for c in cmds:
         if isinstance(c, Decl):
@@ -779,299 +790,56 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
                 out.append(f"{pad}__syncthreads();")
             else:
                 out.append(f"{pad}{lv} = {rhs};")
-        elif isinstance(c, For) and _batchable(c, inputs):
-            _emit_batched(c, out, shared, depth, types, inputs)
+        elif isinstance(c, ir.Load):
+            elem = f"{c.buf}[{ir.ix_c(c.idx)}]"
+            if c.nt:
+                elem = f"__builtin_nontemporal_load(&{elem})"
+            out.append(f"{pad}const {c.ctype} {c.name} = {elem};")
+        elif isinstance(c, ir.VLoad):
+            vt = _VEC[c.ctype]
+            ptr = f"reinterpret_cast<const {vt}*>({c.buf} + {ir.ix_c(c.idx)})"
+            val = f"__builtin_nontemporal_load({ptr})" if c.nt else f"*{ptr}"
+            out.append(f"{pad}const {vt} {c.name} = {val};")
+        elif isinstance(c, ir.SchedBarrier):
+            out.append(f"{pad}__builtin_amdgcn_sched_barrier(0);   // the loads above first")
+        elif isinstance(c, ir.Blocked):
+            out.append(f"{pad}int {c.var} = 0;")
+            out.append(f"{pad}for (; {c.var} + {c.step} <= {c.n}; {c.var} += {c.step}) {{")
+            _emit_block(c.main, out, shared, depth + 1, types)
+            out.append(f"{pad}}}")
+            out.append(f"{pad}for (; {c.var} < {c.n}; ++{c.var}) {{")
+            _emit_block(c.tail, out, shared, depth + 1, types)
+            out.append(f"{pad}}}")
         elif isinstance(c, For):
             out.append(f"{pad}for (int {c.var} = 0; {c.var} < {c.n}; ++{c.var}) {{")
-            _emit_block(c.body, out, shared, depth + 1, types, inputs)
+            _emit_block(c.body, out, shared, depth + 1, types)
             if _has_local_loop(c.body):
                 # a work-group-level loop around mapLocal: the next iteration
                 # may overwrite local memory this one still reads
                 out.append(f"{pad}  __syncthreads();")
             out.append(f"{pad}}}")
+        elif isinstance(c, ir.Lanes):
+            out.append(f"{pad}for (int {c.var} = threadIdx.x * {c.lanes}; {c.var} < {c.n};"
+                       f" {c.var} += blockDim.x * {c.lanes}) {{")
+            _emit_block(c.body, out, shared, depth + 1, types)
+            out.append(f"{pad}}}")
+            out.append(f"{pad}__syncthreads();")
         elif isinstance(c, ParFor):
             v, n = c.var, c.n
             if c.level == "workgroup":
                 out.append(f"{pad}for (int {v} = blockIdx.x; {v} < {n}; {v} += gridDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types, inputs)
+                _emit_block(c.body, out, shared, depth + 1, types)
                 out.append(f"{pad}  __syncthreads();")
                 out.append(f"{pad}}}")
-            elif c.level == "local" and _coarsenable(c, inputs):
-                _emit_coarsened(c, out, shared, depth, types, inputs)
-                out.append(f"{pad}__syncthreads();")
             elif c.level == "local":
                 out.append(f"{pad}for (int {v} = threadIdx.x; {v} < {n}; {v} += blockDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types, inputs)
+                _emit_block(c.body, out, shared, depth + 1, types)
                 out.append(f"{pad}}}")
                 out.append(f"{pad}__syncthreads();")
             else:
                 out.append(f"{pad}for (int {v} = blockIdx.x * blockDim.x + threadIdx.x; {v} < {n};"
                            f" {v} += gridDim.x * blockDim.x) {{")
-                _emit_block(c.body, out, shared, depth + 1, types, inputs)
+                _emit_block(c.body, out, shared, depth + 1, types)
                 out.append(f"{pad}}}")
         else:
             raise TranslateError(f"unknown command {c!r}")
-
-
-# ------------------------------------------------------------------ load batching
-# A sequential loop whose body is straight-line code (a fold step) reading the
-# read-only inputs at positions that depend on the loop index is emitted with
-# its input reads for B consecutive iterations issued first, then the B steps
-# in increasing order.  Only reads of inputs move (nothing writes them), so
-# every operation and its order are unchanged; the loads are in flight
-# together instead of one after another.
-
-BATCH_ELEMS = 32
-_STREAMED: set = set()      # names of the inputs read with non-temporal loads
-
-
-def _ix_uses(e, var: str) -> bool:
-    if isinstance(e, ir.IVar):
-        return e.name == var
-    if isinstance(e, ir.IBin):
-        return _ix_uses(e.a, var) or _ix_uses(e.b, var)
-    return False
-
-
-def _ix_sub(e, var: str, u: int):
-    if isinstance(e, ir.IVar) and e.name == var:
-        return iadd(e, u)
-    if isinstance(e, ir.IBin):
-        return ir.IBin(e.op, _ix_sub(e.a, var, u), _ix_sub(e.b, var, u))
-    return e
-
-
-def _ex_ix(e, g):
-    """Rebuilds expression e with g applied to every index expression (array
-    positions and Select selectors)."""
-    if isinstance(e, ir.Ref):
-        return e if e.idx is None else ir.Ref(e.name, g(e.idx))
-    if isinstance(e, ir.Bin):
-        return ir.Bin(e.op, _ex_ix(e.a, g), _ex_ix(e.b, g))
-    if isinstance(e, ir.Un):
-        return ir.Un(e.op, _ex_ix(e.a, g))
-    if isinstance(e, ir.Cast):
-        return ir.Cast(e.ctype, _ex_ix(e.a, g))
-    if isinstance(e, ir.Select):
-        return ir.Select(g(e.sel), tuple(_ex_ix(o, g) for o in e.options))
-    if isinstance(e, ir.Decode):
-        return ir.Decode(e.fmt, _ex_ix(e.a, g))
-    return e
-
-
-def _ex_map(e, f):
-    """Rebuilds expression e with f applied to every Ref."""
-    if isinstance(e, ir.Ref):
-        return f(e)
-    if isinstance(e, ir.Bin):
-        return ir.Bin(e.op, _ex_map(e.a, f), _ex_map(e.b, f))
-    if isinstance(e, ir.Un):
-        return ir.Un(e.op, _ex_map(e.a, f))
-    if isinstance(e, ir.Cast):
-        return ir.Cast(e.ctype, _ex_map(e.a, f))
-    if isinstance(e, ir.Select):
-        return ir.Select(e.sel, tuple(_ex_map(o, f) for o in e.options))
-    if isinstance(e, ir.Decode):
-        return ir.Decode(e.fmt, _ex_map(e.a, f))
-    return e
-
-
-def _loads(body, var: str, inputs) -> List[ir.Ref]:
-    """Array reads at loop-dependent positions that can be issued early: of
-    the read-only inputs, or of any array the loop body does not write."""
-    written = {c.name for c in body if isinstance(c, Assign)}
-    found: List[ir.Ref] = []
-
-    def visit(r):
-        if r.idx is not None and _ix_uses(r.idx, var) and r not in found and \
-                (r.name in inputs or r.name not in written):
-            found.append(r)
-        return r
-    for c in body:
-        if isinstance(c, Assign):
-            _ex_map(c.rhs, visit)
-    return found
-
-
-def _batchable(c: For, inputs) -> bool:
-    if not all(isinstance(b, (Decl, Assign)) for b in c.body):
-        return False
-    if any(isinstance(b, Decl) and b.space != "private" for b in c.body):
-        return False
-    loads = _loads(c.body, c.var, inputs)
-    return bool(loads) and c.n >= 2 * max(1, BATCH_ELEMS // len(loads))
-
-
-def _emit_batched(c: For, out, shared, depth, types, inputs, quads=()):
-    """``quads``: groups of 4 loads (as they appear in the body) known to read
-    4 consecutive elements from a 16-byte aligned position; each is read with
-    one 16-byte load."""
-    pad = "  " * depth
-    loads = _loads(c.body, c.var, inputs)
-    B = max(1, BATCH_ELEMS // len(loads))
-    k = c.var
-    out.append(f"{pad}int {k} = 0;")
-    out.append(f"{pad}for (; {k} + {B} <= {c.n}; {k} += {B}) {{")
-    regs = {}
-    in_quad = {r for q in quads for r in q}
-    for u in range(B):
-        for qi, q in enumerate(quads):
-            name = f"{k}_q{u}_{qi}"
-            idx0 = _ix_sub(q[0].idx, k, u)
-            vt = "dpia_f4" if types[q[0].name] == "float" else "dpia_u4"
-            ptr = f"reinterpret_cast<const {vt}*>({q[0].name} + {ir.ix_c(idx0)})"
-            load = f"__builtin_nontemporal_load({ptr})" if q[0].name in _STREAMED else f"*{ptr}"
-            out.append(f"{pad}  const {vt} {name} = {load};")
-            for j, r in enumerate(q):
-                regs[(u, ir.Ref(r.name, _ix_sub(r.idx, k, u)))] = f"{name}.{'xyzw'[j]}"
-        for j, r in enumerate(loads):
-            if r in in_quad:
-                continue
-            name = f"{k}_r{u}_{j}"
-            idx = _ix_sub(r.idx, k, u)
-            regs[(u, ir.Ref(r.name, idx))] = name
-            elem = f"{r.name}[{ir.ix_c(idx)}]"
-            if r.name in _STREAMED:
-                elem = f"__builtin_nontemporal_load(&{elem})"
-            out.append(f"{pad}  const {types[r.name]} {name} = {elem};")
-    out.append(f"{pad}  __builtin_amdgcn_sched_barrier(0);")
-    for u in range(B):
-        def reg(ref, u=u):
-            return ir.Ref(regs[(u, ref)], None) if (u, ref) in regs else ref
-        step = []
-        for b in c.body:
-            if isinstance(b, Assign):
-                # iteration k + u: every index moves (selectors included), then
-                # the reads issued above take the place of their loads
-                idx = _ix_sub(b.idx, k, u) if b.idx is not None else None
-                rhs = _ex_map(_ex_ix(b.rhs, lambda e, u=u: _ix_sub(e, k, u)), reg)
-                step.append(Assign(b.name, idx, rhs, b.space, b.ctx))
-            else:
-                step.append(b)
-        out.append(f"{pad}  {{")
-        _emit_block(step, out, shared, depth + 2, types, inputs)
-        out.append(f"{pad}  }}")
-    out.append(f"{pad}}}")
-    out.append(f"{pad}for (; {k} < {c.n}; ++{k}) {{")
-    _emit_block(c.body, out, shared, depth + 1, types, inputs)
-    out.append(f"{pad}}}")
-
-
-# ------------------------------------------------------------------ lane coarsening
-# A mapLocal loop whose lanes each fold read-only inputs (straight-line code
-# around sequential loops of straight-line code) runs LANES adjacent lanes per
-# work-item: the lanes' commands are copied with their private variables
-# renamed, and their fold loops are fused, each lane's steps still in its own
-# increasing order (the lanes are independent iterations, Stage II).  Where
-# the 4 lanes read 4 consecutive, 16-byte aligned input elements, one 16-byte
-# load serves them.  Nothing else changes: the same operations in the same
-# order per lane.
-
-LANES = 4
-
-
-def _straight(body) -> bool:
-    return all(isinstance(b, Assign) or (isinstance(b, Decl) and b.space == "private")
-               for b in body)
-
-
-def _coarsenable(c: ParFor, inputs) -> bool:
-    if c.level != "local" or c.n % LANES or c.n < 64 * LANES:
-        return False
-    folds = 0
-    for b in c.body:
-        if isinstance(b, For):
-            if not _straight(b.body):
-                return False
-            folds += _batchable(b, inputs)
-        elif not (isinstance(b, Assign) or (isinstance(b, Decl) and b.space == "private")):
-            return False
-    return folds > 0
-
-
-def _ix_replace(e, var: str, by):
-    if isinstance(e, ir.IVar) and e.name == var:
-        return by
-    if isinstance(e, ir.IBin):
-        return ir.IBin(e.op, _ix_replace(e.a, var, by), _ix_replace(e.b, var, by))
-    return e
-
-
-def _declared(body, acc: set):
-    for b in body:
-        if isinstance(b, Decl):
-            acc.add(b.name)
-        elif isinstance(b, For):
-            _declared(b.body, acc)
-    return acc
-
-
-def _lane_copy(body, var: str, by, ren: Dict[str, str]):
-    def rename(r):
-        return ir.Ref(ren.get(r.name, r.name), r.idx)
-    out = []
-    for b in body:
-        if isinstance(b, Decl):
-            out.append(Decl(ren.get(b.name, b.name), b.ctype, b.size, b.space))
-        elif isinstance(b, Assign):
-            rhs = _ex_map(_ex_ix(b.rhs, lambda e: _ix_replace(e, var, by)), rename)
-            out.append(Assign(ren.get(b.name, b.name),
-                              None if b.idx is None else _ix_replace(b.idx, var, by),
-                              rhs, b.space, b.ctx))
-        else:
-            out.append(For(b.var, b.n, _lane_copy(b.body, var, by, ren)))
-    return out
-
-
-def _additive_once(e, var: str) -> int:
-    """Occurrences of var if it appears only as a summand (else -1)."""
-    if isinstance(e, ir.IVar):
-        return 1 if e.name == var else 0
-    if isinstance(e, ir.IConst):
-        return 0
-    if e.op == "+":
-        a, b = _additive_once(e.a, var), _additive_once(e.b, var)
-        return -1 if a < 0 or b < 0 else a + b
-    return -1 if _ix_uses(e, var) else 0
-
-
-def _aligned4(e, base: str) -> bool:
-    """e is a multiple of 4 for every value of the loop variables (base is a
-    multiple of 4 by construction)."""
-    if isinstance(e, ir.IConst):
-        return e.v % 4 == 0
-    if isinstance(e, ir.IVar):
-        return e.name == base
-    if e.op == "+":
-        return _aligned4(e.a, base) and _aligned4(e.b, base)
-    if e.op == "*":
-        return _aligned4(e.a, base) or _aligned4(e.b, base)
-    return False
-
-
-def _emit_coarsened(c: ParFor, out, shared, depth, types, inputs):
-    pad = "  " * depth
-    base = c.var + "_q"
-    names = _declared(c.body, set())
-    copies = []
-    for j in range(LANES):
-        ren = {nm: f"{nm}_{j}" for nm in names}
-        copies.append(_lane_copy(c.body, c.var, iadd(ir.IVar(base), j), ren))
-    out.append(f"{pad}for (int {base} = threadIdx.x * {LANES}; {base} < {c.n};"
-               f" {base} += blockDim.x * {LANES}) {{")
-    for pos, b in enumerate(c.body):
-        if not isinstance(b, For):
-            _emit_block([cp[pos] for cp in copies], out, shared, depth + 1, types, inputs)
-            continue
-        fused = For(b.var, b.n, [x for cp in copies for x in cp[pos].body])
-        quads = []
-        for r in _loads(b.body, b.var, inputs):
-            if types[r.name] in ("float", "unsigned") and _additive_once(r.idx, c.var) == 1 \
-                    and _aligned4(_ix_replace(r.idx, c.var, ir.IVar(base)), base):
-                quads.append(tuple(ir.Ref(r.name, _ix_replace(r.idx, c.var, iadd(ir.IVar(base), j)))
-                                   for j in range(LANES)))
-        if _batchable(fused, inputs):
-            _emit_batched(fused, out, shared, depth + 1, types, inputs, tuple(quads))
-        else:
-            _emit_block([fused], out, shared, depth + 1, types, inputs)
-    out.append(f"{pad}}}")

@@ -1,8 +1,10 @@
 """Runs a generated program's imperative form on the CPU (test helper).
 
-Executes the commands the generator emits, kernel by kernel, with numpy
-scalars of the program's C types: parallel loops run their iterations one
-after another (their iterations are independent, Stage II), and code at
+Executes the commands the generator emits (after its optimisation passes:
+hoisted loads, 16-byte loads, blocked loops, coarsened lanes), kernel by
+kernel, with numpy scalars of the program's C types: parallel loops run their
+iterations one after another (their iterations are independent, Stage II),
+and code at
 work-group level runs once per work-group (every work-item would compute the
 same private values and make the same writes).  Each numeric node is one
 numpy operation on binary32 / binary64 / 32-bit unsigned scalars, so the
@@ -70,6 +72,29 @@ def _run(cmds, env, mem, types):
             mem[c.name] = np.zeros(max(1, c.size), NP[c.ctype])
         elif isinstance(c, ir.Assign):
             mem[c.name][0 if c.idx is None else _ix(c.idx, env)] = _ex(c.rhs, env, mem, types)
+        elif isinstance(c, ir.Load):
+            mem[c.name] = np.array([mem[c.buf][_ix(c.idx, env)]])
+        elif isinstance(c, ir.VLoad):
+            i = _ix(c.idx, env)
+            assert i % 4 == 0, "a 4-vector load at an index that is not a multiple of 4"
+            mem[c.name] = np.array(mem[c.buf][i:i + 4])
+            assert mem[c.name].size == 4, "a 4-vector load past the end of its array"
+        elif isinstance(c, ir.SchedBarrier):
+            pass
+        elif isinstance(c, ir.Blocked):
+            k = 0
+            while k + c.step <= c.n:
+                env[c.var] = k
+                _run(c.main, env, mem, types)
+                k += c.step
+            while k < c.n:
+                env[c.var] = k
+                _run(c.tail, env, mem, types)
+                k += 1
+        elif isinstance(c, ir.Lanes):
+            for base in range(0, c.n, c.lanes):
+                env[c.var] = base
+                _run(c.body, env, mem, types)
         else:
             for i in range(c.n):
                 env[c.var] = i

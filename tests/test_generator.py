@@ -203,3 +203,50 @@ def test_random_strategies_translate_to_the_oracle_value(seq, lanes_log, order, 
     x, y = disc(seed, n)
     prog = T.translate(S.dot_expr(n, p), {"xs": ("f32", (n,)), "ys": ("f32", (n,))})
     assert same(GI.run(prog, {"xs": x, "ys": y})["out"][0], S.dot(x, y, p))
+
+
+def _nodes(cmds, acc=None):
+    from paper_1710_08332_amd.generator import ir
+    acc = acc if acc is not None else set()
+    for c in cmds:
+        acc.add(type(c).__name__)
+        for attr in ("body", "main", "tail"):
+            if hasattr(c, attr):
+                _nodes(getattr(c, attr), acc)
+    return acc
+
+
+@pytest.mark.parametrize("p,want", [
+    (S.Plan(seq=64, lanes=256, order="strided"), {"Lanes", "VLoad", "Blocked"}),
+    (S.Plan(seq=32, lanes=256, order="contiguous", combine="seq"), {"Lanes", "Blocked"}),
+    (S.Plan(seq=32, lanes=256, order="strided", accum="sum2"), {"Lanes", "VLoad", "Blocked"}),
+    (S.Plan(seq=48, lanes=256, order="strided", accum="kahan", final_f64=True),
+     {"Lanes", "VLoad", "Blocked"}),
+    (S.Plan(seq=4, lanes=64, order="strided"), {"Blocked"}),              # 64 chunks: the fold
+    (S.Plan(seq=2, lanes=16, order="strided", vec=4), {"Blocked"}),       # asScalar selectors
+], ids=str)
+def test_optimisation_passes_keep_the_oracle_value(p, want):
+    # sizes that make the passes fire: coarsened lanes with 16-byte loads,
+    # blocked folds, the blocked one-work-item fold of many chunk values
+    # (whose asScalar reads select components by index)
+    chunks = 2 if p.lanes >= 256 else (64 if p.vec == 1 else 16)
+    n = p.chunk * chunks
+    x, y = disc(90, n)
+    prog = T.translate(S.dot_expr(n, p), {"xs": ("f32", (n,)), "ys": ("f32", (n,))})
+    assert want <= _nodes([c for k in prog.kernels for c in k.body])
+    assert same(GI.run(prog, {"xs": x, "ys": y})["out"][0], S.dot(x, y, p))
+
+
+def test_optimised_gemv_rows_keep_the_oracle_value():
+    p = S.Plan(seq=16, lanes=256, order="strided", rows=2)
+    m, k = 4, p.chunk
+    g = np.random.default_rng(91)
+    A = g.standard_normal((m, k)).astype(np.float32)
+    x = g.standard_normal(k).astype(np.float32)
+    prog = T.translate(S.gemv_expr(m, k, p), {"A": ("f32", (m, k)), "x": ("f32", (k,))})
+    assert {"Lanes", "VLoad", "Blocked"} <= _nodes([c for kk in prog.kernels for c in kk.body])
+    assert same(GI.run(prog, {"A": A, "x": x})["out"], S.gemv(A, x, p))
+    plain = T.translate(S.gemv_expr(m, k, p), {"A": ("f32", (m, k)), "x": ("f32", (k,))},
+                        optimise=False)
+    assert "Lanes" not in _nodes([c for kk in plain.kernels for c in kk.body])
+    assert same(GI.run(plain, {"A": A, "x": x})["out"], S.gemv(A, x, p))
