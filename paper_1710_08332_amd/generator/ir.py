@@ -142,23 +142,23 @@ class Decode:
 
 Ex = Union[Lit, Ref, Bin, Un, Cast, Select, Decode]
 
-# Device functions the emitted code may call, written from the formats'
-# definitions: bfloat16 is the upper half of a binary32; OCP fp8 E4M3 has a
-# sign bit, 4 exponent bits with bias 7 and 3 mantissa bits, exponent 0
-# holds the subnormals m * 2^-9, S.1111.111 is NaN and there are no
-# infinities.
+# Device functions the emitted code may call.  bfloat16 is the upper half of
+# a binary32.  OCP fp8 E4M3 (sign bit, 4 exponent bits with bias 7, 3
+# mantissa bits, subnormals m * 2^-9 at exponent 0, S.1111.111 NaN, no
+# infinities) is decoded by gfx950's converter, one instruction; the tests
+# check it against the format definition for every code.
 DECODERS = """typedef float dpia_f4 __attribute__((ext_vector_type(4)));
 typedef unsigned dpia_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned short dpia_h4 __attribute__((ext_vector_type(4)));
+typedef unsigned short dpia_h8 __attribute__((ext_vector_type(8)));
+typedef unsigned char dpia_b4 __attribute__((ext_vector_type(4)));
+typedef unsigned char dpia_b8 __attribute__((ext_vector_type(8)));
+typedef unsigned char dpia_b16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ float dpia_bf16(unsigned short c) {
   return __uint_as_float(static_cast<unsigned>(c) << 16);
 }
 __device__ __forceinline__ float dpia_fp8(unsigned char c) {
-  const unsigned e = (c >> 3) & 15u, m = c & 7u;
-  float v;
-  if (e == 15u && m == 7u) v = __uint_as_float(0x7fc00000u);
-  else if (e == 0u) v = static_cast<float>(m) * 0x1p-9f;
-  else v = __uint_as_float(((e + 120u) << 23) | (m << 20));
-  return (c & 0x80u) ? -v : v;
+  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(c), 0);
 }
 """
 
@@ -254,13 +254,15 @@ class Load:
 
 @dataclass
 class VLoad:
-    """A private 4-vector ``name`` = buf[idx .. idx+3], read at once; idx is a
-    multiple of 4.  Its components are Ref(name, IConst(j))."""
+    """A private vector ``name`` = buf[idx .. idx + width - 1], read at once
+    (at most 16 bytes); idx is a multiple of width.  Its components are
+    Ref(name, IConst(j))."""
     name: str
     ctype: str
     buf: str
     idx: IX
     nt: bool = False
+    width: int = 4
 
 
 @dataclass

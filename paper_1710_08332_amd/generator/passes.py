@@ -10,13 +10,14 @@ the GPU runs it.
    of an array at a loop-dependent position, of an input or of an array the
    loop does not write, becomes a private constant (``Load``) at the start of
    the body.
-2. ``coarsen``: a mapLocal loop of at least 4 * 64 lanes, whose lanes are
-   straight-line code around such loops, runs 4 adjacent lanes per
-   work-item (``Lanes``): the lanes' commands are copied with their private
-   names renamed and their loops fused, each lane's steps in its own order
-   (lanes are independent iterations, Stage II).  Where the 4 lanes read 4
-   consecutive elements from an index that is a multiple of 4, one 16-byte
-   ``VLoad`` serves them.
+2. ``coarsen``: a mapLocal loop whose lanes are straight-line code around
+   such loops runs F adjacent lanes per work-item (``Lanes``; F = 16 bytes
+   of the narrowest loaded element: 4 binary32, 8 bf16 or 16 fp8 lanes, and
+   at least 64 work-items): the lanes' commands are copied with their
+   private names renamed and their loops fused, each lane's steps in its own
+   order (lanes are independent iterations, Stage II).  Where w lanes read w
+   consecutive elements from an index that is a multiple of w, one load of
+   up to 16 bytes (``VLoad``) serves them.
 3. ``batch``: such a loop runs B iterations per round (``Blocked``): the
    loads of all B iterations first, then the B steps in increasing order, so
    B iterations' loads are in flight together.
@@ -100,8 +101,11 @@ def _rewrite(cmd, g_ix, ren: Dict[str, str]):
     if isinstance(cmd, Assign):
         return Assign(ren.get(cmd.name, cmd.name), None if cmd.idx is None else g_ix(cmd.idx),
                       ex_refs(ex_ix(cmd.rhs, g_ix), rn), cmd.space, cmd.ctx)
-    if isinstance(cmd, (Load, VLoad)):
-        return type(cmd)(ren.get(cmd.name, cmd.name), cmd.ctype, cmd.buf, g_ix(cmd.idx), cmd.nt)
+    if isinstance(cmd, Load):
+        return Load(ren.get(cmd.name, cmd.name), cmd.ctype, cmd.buf, g_ix(cmd.idx), cmd.nt)
+    if isinstance(cmd, VLoad):
+        return VLoad(ren.get(cmd.name, cmd.name), cmd.ctype, cmd.buf, g_ix(cmd.idx), cmd.nt,
+                     cmd.width)
     raise TypeError(f"not straight-line: {cmd!r}")
 
 
@@ -157,16 +161,31 @@ def _loads_first(body, var, inputs, streamed, types, fresh):
 
 # ------------------------------------------------------------------ 2. coarsen
 
-def _coarsenable(c: ParFor) -> bool:
-    if c.level != "local" or c.n % LANES or c.n < 64 * LANES:
-        return False
+_ESIZE = {"float": 4, "unsigned": 4, "double": 8, "unsigned short": 2, "unsigned char": 1}
+
+
+def _lanes_for(c: ParFor, types) -> int:
+    """Lanes per work-item for a mapLocal loop, or 0 to leave it alone: 16
+    bytes of the narrowest element its fold loops load (4 lanes of binary32,
+    8 of bf16, 16 of fp8), fewer if the loop is too short to keep 64
+    work-items busy."""
+    if c.level != "local":
+        return 0
     loops = [b for b in c.body if isinstance(b, For)]
     if not loops or not all(_straight(b.body) for b in loops):
-        return False
-    if not any(isinstance(x, Load) for b in loops for x in b.body):
-        return False
-    return all(isinstance(b, (For, Assign)) or (isinstance(b, Decl) and b.space == "private")
-               for b in c.body)
+        return 0
+    loads = [x for b in loops for x in b.body if isinstance(x, Load)]
+    if not loads:
+        return 0
+    if not all(isinstance(b, (For, Assign)) or (isinstance(b, Decl) and b.space == "private")
+               for b in c.body):
+        return 0
+    F = min(16, 16 // min(_ESIZE.get(types[x.buf], 4) for x in loads))
+    while F >= LANES:
+        if c.n % F == 0 and c.n >= 64 * F:
+            return F
+        F //= 2
+    return 0
 
 
 def _additive_once(e, var: str) -> int:
@@ -181,24 +200,24 @@ def _additive_once(e, var: str) -> int:
     return -1 if ix_uses(e, var) else 0
 
 
-def _aligned4(e, base: str) -> bool:
-    """e is a multiple of 4 for all values (base is one by construction)."""
+def _aligned(e, base: str, w: int) -> bool:
+    """e is a multiple of w for all values (base is one by construction)."""
     if isinstance(e, IConst):
-        return e.v % 4 == 0
+        return e.v % w == 0
     if isinstance(e, IVar):
         return e.name == base
     if e.op == "+":
-        return _aligned4(e.a, base) and _aligned4(e.b, base)
+        return _aligned(e.a, base, w) and _aligned(e.b, base, w)
     if e.op == "*":
-        return _aligned4(e.a, base) or _aligned4(e.b, base)
+        return _aligned(e.a, base, w) or _aligned(e.b, base, w)
     return False
 
 
 def coarsen(cmds, types: Dict[str, str], fresh):
     out = []
     for c in cmds:
-        if isinstance(c, ParFor) and _coarsenable(c):
-            out.append(_coarsened(c, types, fresh))
+        if isinstance(c, ParFor) and _lanes_for(c, types):
+            out.append(_coarsened(c, _lanes_for(c, types), types, fresh))
         elif isinstance(c, ParFor):
             out.append(ParFor(c.level, c.var, c.n, coarsen(c.body, types, fresh)))
         elif isinstance(c, For):
@@ -208,10 +227,10 @@ def coarsen(cmds, types: Dict[str, str], fresh):
     return out
 
 
-def _coarsened(c: ParFor, types, fresh) -> Lanes:
+def _coarsened(c: ParFor, F: int, types, fresh) -> Lanes:
     base = fresh(c.var + "q")
     names = _defined(c.body)
-    ren = [{nm: f"{nm}_{j}" for nm in names} for j in range(LANES)]
+    ren = [{nm: f"{nm}_{j}" for nm in names} for j in range(F)]
 
     def lane_ix(j):
         by = iadd(IVar(base), j)
@@ -219,33 +238,41 @@ def _coarsened(c: ParFor, types, fresh) -> Lanes:
     body = []
     for b in c.body:
         if not isinstance(b, For):
-            body += [_rewrite(b, lane_ix(j), ren[j]) for j in range(LANES)]
+            body += [_rewrite(b, lane_ix(j), ren[j]) for j in range(F)]
             continue
-        # loads of the 4 lanes that are 4 consecutive, 4-aligned elements
-        quad_of: Dict[str, str] = {}
+        # the F lanes' loads of consecutive elements: groups of w lanes (w
+        # elements, at most 16 bytes) from an index that is a multiple of w
+        vec_of: Dict[tuple, tuple] = {}              # (load name, lane) -> (vector, component)
         vloads = []
         for ld in (x for x in b.body if isinstance(x, Load)):
-            if types[ld.buf] in ("float", "unsigned") and _additive_once(ld.idx, c.var) == 1 \
-                    and _aligned4(ix_replace(ld.idx, c.var, IVar(base)), base):
+            w = min(F, 16 // _ESIZE.get(types[ld.buf], 4))
+            if w < 2 or _additive_once(ld.idx, c.var) != 1 or \
+                    not _aligned(ix_replace(ld.idx, c.var, IVar(base)), base, w):
+                continue
+            for g in range(F // w):
                 q = fresh("vq")
-                vloads.append(VLoad(q, ld.ctype, ld.buf, ix_replace(ld.idx, c.var, IVar(base)),
-                                    ld.nt))
-                quad_of[ld.name] = q
+                vloads.append(VLoad(q, ld.ctype, ld.buf,
+                                    ix_replace(ld.idx, c.var, iadd(IVar(base), g * w)), ld.nt, w))
+                for i in range(w):
+                    vec_of[(ld.name, g * w + i)] = (q, i)
         fused = list(vloads)
-        for j in range(LANES):
-            alias = {f"{nm}_{j}": q for nm, q in quad_of.items()}
+        for j in range(F):
+            alias = {f"{nm}_{j}": vec_of[(nm, jj)] for (nm, jj) in vec_of if jj == j}
 
-            def comp(r, alias=alias, j=j):
-                return Ref(alias[r.name], IConst(j)) if r.name in alias else r
+            def comp(r, alias=alias):
+                if r.name in alias:
+                    q, i = alias[r.name]
+                    return Ref(q, IConst(i))
+                return r
             for x in b.body:
-                if isinstance(x, Load) and x.name in quad_of:
-                    continue                          # served by the VLoad
+                if isinstance(x, Load) and (x.name, j) in vec_of:
+                    continue                          # served by a vector load
                 y = _rewrite(x, lane_ix(j), ren[j])
                 if isinstance(y, Assign):
                     y = Assign(y.name, y.idx, ex_refs(y.rhs, comp), y.space, y.ctx)
                 fused.append(y)
         body.append(For(b.var, b.n, fused))
-    return Lanes(base, c.n, LANES, body)
+    return Lanes(base, c.n, F, body)
 
 
 # ------------------------------------------------------------------ 3. batch
@@ -270,7 +297,7 @@ def _batched(c: For):
     loads = [b for b in c.body if isinstance(b, (Load, VLoad)) and ix_uses(b.idx, c.var)]
     if not loads:
         return None
-    elems = sum(4 if isinstance(b, VLoad) else 1 for b in loads)
+    elems = sum(b.width if isinstance(b, VLoad) else 1 for b in loads)
     B = max(1, BATCH_ELEMS // elems)
     if c.n < 2 * B:
         return None

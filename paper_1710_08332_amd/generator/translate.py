@@ -768,7 +768,9 @@ def _emit(kernels: List[Kernel], buffers: List[Buffer], types: Dict[str, str]) -
     return "\n".join(lines)
 
 
-_VEC = {"float": "dpia_f4", "unsigned": "dpia_u4"}
+_VEC = {("float", 4): "dpia_f4", ("unsigned", 4): "dpia_u4", ("unsigned short", 4): "dpia_h4",
+        ("unsigned short", 8): "dpia_h8", ("unsigned char", 4): "dpia_b4",
+        ("unsigned char", 8): "dpia_b8", ("unsigned char", 16): "dpia_b16"}
 
 
 def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict[str, str]):
@@ -796,7 +798,7 @@ def _emit_block(cmds, out: List[str], shared: List[str], depth: int, types: Dict
                 elem = f"__builtin_nontemporal_load(&{elem})"
             out.append(f"{pad}const {c.ctype} {c.name} = {elem};")
         elif isinstance(c, ir.VLoad):
-            vt = _VEC[c.ctype]
+            vt = _VEC[(c.ctype, c.width)]
             ptr = f"reinterpret_cast<const {vt}*>({c.buf} + {ir.ix_c(c.idx)})"
             val = f"__builtin_nontemporal_load({ptr})" if c.nt else f"*{ptr}"
             out.append(f"{pad}const {vt} {c.name} = {val};")

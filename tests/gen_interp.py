@@ -75,10 +75,11 @@ def _run(cmds, env, mem, types):
         elif isinstance(c, ir.Load):
             mem[c.name] = np.array([mem[c.buf][_ix(c.idx, env)]])
         elif isinstance(c, ir.VLoad):
-            i = _ix(c.idx, env)
-            assert i % 4 == 0, "a 4-vector load at an index that is not a multiple of 4"
-            mem[c.name] = np.array(mem[c.buf][i:i + 4])
-            assert mem[c.name].size == 4, "a 4-vector load past the end of its array"
+            i, w = _ix(c.idx, env), c.width
+            assert i % w == 0, "a vector load at an index that is not a multiple of its width"
+            assert w * mem[c.buf].itemsize <= 16, "a vector load of more than 16 bytes"
+            mem[c.name] = np.array(mem[c.buf][i:i + w])
+            assert mem[c.name].size == w, "a vector load past the end of its array"
         elif isinstance(c, ir.SchedBarrier):
             pass
         elif isinstance(c, ir.Blocked):

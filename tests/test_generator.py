@@ -250,3 +250,31 @@ def test_optimised_gemv_rows_keep_the_oracle_value():
                         optimise=False)
     assert "Lanes" not in _nodes([c for kk in plain.kernels for c in kk.body])
     assert same(GI.run(plain, {"A": A, "x": x})["out"], S.gemv(A, x, p))
+
+
+@pytest.mark.parametrize("fmt,lanes", [("bf16", 512), ("fp8", 1024)])
+def test_optimised_low_precision_rows_keep_the_oracle_value(fmt, lanes):
+    # 8 bf16 or 16 fp8 lanes per work-item, the codes read 16 bytes at a time
+    from paper_1710_08332_amd import STRIDED, Strategy
+    from paper_1710_08332_amd.generator import strategies as P
+    s = Strategy(seq_len=2, local_size=lanes, order=STRIDED)
+    m, k = 3, 2 * lanes
+    g = np.random.default_rng(92)
+    x = g.standard_normal(k).astype(np.float32)
+    if fmt == "bf16":
+        codes = g.integers(0, 2 ** 16, (m, k)).astype(np.uint16)
+        codes[(codes & 0x7F80) == 0x7F80] = 0x3F80
+        inputs = {"A": ("u16", (m, k)), "x": ("f32", (k,))}
+        feed, scale = {"A": codes, "x": x}, None
+    else:
+        codes = g.integers(0, 256, (m, k)).astype(np.uint8)
+        codes[(codes & 0x7F) == 0x7F] = 0x38
+        scale = g.random(m, dtype=np.float32) + np.float32(0.5)
+        inputs = {"A": ("u8", (m, k)), "x": ("f32", (k,)), "scale": ("f32", (m,))}
+        feed = {"A": codes, "x": x, "scale": scale}
+    prog = T.translate(P.gemv_text(s, m, k, fmt), inputs)
+    body = [c for kk in prog.kernels for c in kk.body]
+    assert {"Lanes", "VLoad"} <= _nodes(body)
+    want = S.gemv(codes, x, S.Plan(seq=2, lanes=lanes, order="strided"), a_format=fmt,
+                  scale=scale)
+    assert same(GI.run(prog, feed)["out"], want)
