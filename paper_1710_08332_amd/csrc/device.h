@@ -222,6 +222,17 @@ struct OpBatch<Op, decltype(void(Op::kBatchElems))> {
   static constexpr int E = Op::kBatchElems;
 };
 
+// Views whose loads can be kept as loaded until the fold (kRaw: Raw<NV>,
+// load_raw, expand), so that a batch in flight holds narrow codes.
+template <class V, class = void>
+struct HasRaw {
+  static constexpr bool value = false;
+};
+template <class V>
+struct HasRaw<V, decltype(void(V::kRaw))> {
+  static constexpr bool value = V::kRaw;
+};
+
 // `limit` is the number of chunk elements that exist (W for a full chunk).
 // A chunk past the end of the data is the zero-extended chunk of the
 // expression; a missing element would contribute (0 * 0) + acc = acc (or
@@ -265,13 +276,28 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
   }
   const int nb = nfull / U;
   for (int j = 0; j < nb; ++j) {
-    Term z[U][NV];
     const int o = start + j * U * step;
+    if constexpr (HasRaw<View>::value) {
+      // the batch holds operands as loaded; each group is expanded (decoded)
+      // just before its fold
+      typename View::template Raw<NV> r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) view.template load<NV>(o + u * step, z[u]);
-    __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
+      for (int u = 0; u < U; ++u) view.template load_raw<NV>(o + u * step, r[u]);
+      __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
 #pragma unroll
-    for (int u = 0; u < U; ++u) fold_vec(z[u], NV);
+      for (int u = 0; u < U; ++u) {
+        Term z[NV];
+        View::template expand<NV>(r[u], z);
+        fold_vec(z, NV);
+      }
+    } else {
+      Term z[U][NV];
+#pragma unroll
+      for (int u = 0; u < U; ++u) view.template load<NV>(o + u * step, z[u]);
+      __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
+#pragma unroll
+      for (int u = 0; u < U; ++u) fold_vec(z[u], NV);
+    }
   }
   for (int i = nb * U; i < nfull; ++i) {
     Term z[NV];

@@ -45,22 +45,26 @@ __device__ __forceinline__ void row_block_folds(const Op& op, const int64_t (&ro
   const int start = t * NV;
   int k = 0;
   for (; k + U <= nfull; k += U) {
-    float xv[U][NV], av[U][RB][NV];
+    float xv[U][NV];
+    typename Op::Code ca[U][RB][NV];   // codes: decoded only when folded
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t c = col0 + start + static_cast<int64_t>(k + u) * L;
       op.template load_x<NV>(c, xv[u]);
 #pragma unroll
-      for (int b = 0; b < RB; ++b) op.template load_a<NV>(row[b], lda, c, av[u][b]);
+      for (int b = 0; b < RB; ++b) op.template load_codes<NV>(row[b], lda, c, ca[u][b]);
     }
     __builtin_amdgcn_sched_barrier(0);   // issue the whole batch first
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int b = 0; b < RB; ++b)
+      for (int b = 0; b < RB; ++b) {
+        float av[NV];
+        Op::template decode<NV>(ca[u][b], av);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          acc[b][v] = Op::step(typename Op::Term{av[u][b][v], xv[u][v]}, acc[b][v]);
+          acc[b][v] = Op::step(typename Op::Term{av[v], xv[u][v]}, acc[b][v]);
+      }
   }
   for (; k < nfull; ++k) {
     const int64_t c = col0 + start + static_cast<int64_t>(k) * L;

@@ -189,27 +189,56 @@ struct GemvF32Acc {
       return o == 0 ? reinterpret_cast<const float*>(a) : x;
     }
     __device__ static Term term(const f32x4 (&v)[2], int i) { return Term{v[0][i], v[1][i]}; }
+    // NV elements as loaded: A's codes and x's values.  A batch of loads in
+    // flight holds these (1 or 2 bytes per element for the narrow formats)
+    // and decodes each group just before it is folded (expand).
+    static constexpr bool kRaw = true;
+    template <int NV>
+    struct Raw {
+      E a[NV];
+      float x[NV];
+    };
+    template <int NV>
+    __device__ __forceinline__ void load_raw(int off, Raw<NV>& r) const {
+      vload<E, NV, kStreamA>(a + off, r.a);
+      vload<float, NV, false>(x + off, r.x);   // x is reused by every row: cached
+    }
+    template <int NV>
+    __device__ __forceinline__ static void expand(const Raw<NV>& r, Term (&z)[NV]) {
+      float fa[NV];
+      Decode::template run<NV>(r.a, fa);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) z[i] = Term{fa[i], r.x[i]};
+    }
     template <int NV>
     __device__ __forceinline__ void load(int off, Term (&z)[NV]) const {
-      E ca[NV];
-      float fa[NV], b[NV];
-      vload<E, NV, kStreamA>(a + off, ca);
-      vload<float, NV, false>(x + off, b);   // x is reused by every row: cached
-      Decode::template run<NV>(ca, fa);
-#pragma unroll
-      for (int i = 0; i < NV; ++i) z[i] = Term{fa[i], b[i]};
+      Raw<NV> r;
+      load_raw<NV>(off, r);
+      expand<NV>(r, z);
     }
   };
   static constexpr bool kRowBlockable = true;
   // Row blocking: NV decoded elements of row `r` (part p, offset off), and
   // NV elements of x at the same offset, loaded separately so that one x
   // load can serve several rows.
+  // (The codes are loaded and decoded separately, so that a batch of loads
+  // in flight holds codes, not decoded binary32 values.)
+  using Code = E;
+  template <int NV>
+  __device__ __forceinline__ void load_codes(int64_t r, int64_t lda, int64_t col,
+                                             E (&c)[NV]) const {
+    vload<E, NV, kStreamA>(A + r * lda + col, c);
+  }
+  template <int NV>
+  __device__ __forceinline__ static void decode(const E (&c)[NV], float (&f)[NV]) {
+    Decode::template run<NV>(c, f);
+  }
   template <int NV>
   __device__ __forceinline__ void load_a(int64_t r, int64_t lda, int64_t col,
                                          float (&f)[NV]) const {
     E c[NV];
-    vload<E, NV>(A + r * lda + col, c);
-    Decode::template run<NV>(c, f);
+    load_codes<NV>(r, lda, col, c);
+    decode<NV>(c, f);
   }
   template <int NV>
   __device__ __forceinline__ void load_x(int64_t col, float (&f)[NV]) const {
