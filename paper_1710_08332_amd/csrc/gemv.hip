@@ -135,8 +135,10 @@ __global__ void __launch_bounds__(256) gemv_block_kernel(Op op, GemvArgs a) {
   }
 }
 
-template <class Op, int ORDER, int NV, int COMBINE>
-__global__ void __launch_bounds__(1024) gemv_kernel(Op op, GemvArgs a) {
+// MAXT: the largest work-group it is launched with (256 or 1024); the
+// 256-thread build may use twice the registers of the 1024-thread one.
+template <class Op, int ORDER, int NV, int COMBINE, int MAXT>
+__global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -214,7 +216,8 @@ hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipS
     constexpr int COMBINE = decltype(comb)::value;
     return with_nv<MAXNV>(p.nv, [&](auto nvc) {
       constexpr int NV = decltype(nvc)::value;
-      auto kern = gemv_kernel<Op, ORDER, NV, COMBINE>;
+      auto kern = p.wg_threads <= 256 ? gemv_kernel<Op, ORDER, NV, COMBINE, 256>
+                                      : gemv_kernel<Op, ORDER, NV, COMBINE, 1024>;
       Op op_copy = op;
       void* args[] = {&op_copy, &a};
       return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
