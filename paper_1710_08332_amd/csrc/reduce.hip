@@ -187,6 +187,12 @@ hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, vo
   return launch_fold<Op, FINAL>(p.values, ws, out, out_f64, stream);
 }
 
+// Plain binary32 dots whose strided lanes form teams narrower than 1024
+// lanes use the deeper load batch (DotF32Deep).
+inline bool deep_dot(const Plan& p) {
+  return p.order == DPIA_ORDER_STRIDED && p.L < 1024;
+}
+
 // Calls f(op, final-kind constant) for the operation and accumulation of a plan.
 template <class F>
 hipError_t with_reduction(const Plan& p, const void* x, const void* y, F&& f) {
@@ -205,6 +211,9 @@ hipError_t with_reduction(const Plan& p, const void* x, const void* y, F&& f) {
     if (p.final_f64) return f(op, ic<kFinalSum2_64>{});
     return f(op, ic<kFinalSum2_32>{});
   }
+  if (deep_dot(p))
+    return f(DotF32Deep{{static_cast<const float*>(x), static_cast<const float*>(y)}},
+             ic<kFinalPlain>{});
   return f(DotF32{static_cast<const float*>(x), static_cast<const float*>(y)},
            ic<kFinalPlain>{});
 }
@@ -264,8 +273,10 @@ extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n
     }
   } else {
     if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
-    e = launch_reduce<DotF32, kFinalPlain>(
-        p, DotF32{static_cast<const float*>(x), static_cast<const float*>(y)}, out, 0, ws, hs);
+    const float* xf = static_cast<const float*>(x);
+    const float* yf = static_cast<const float*>(y);
+    e = deep_dot(p) ? launch_reduce<DotF32Deep, kFinalPlain>(p, DotF32Deep{{xf, yf}}, out, 0, ws, hs)
+                    : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, ws, hs);
   }
   if (e != hipSuccess) return hip_fail(e, "dpia_dot launch");
   clear_detail();
