@@ -364,13 +364,19 @@ __device__ __forceinline__ void wave_lds_order() {
 
 // `stage`: this wavefront's region of 2 * 64 rows of kStageRow floats.  Every
 // work-item of the wavefront calls this (inactive lanes fold nothing but
-// still load their share of the other rows).
-template <class Op, class View>
+// still load their share of the other rows).  VEC > 1: the lane is a vector
+// lane whose row holds C vectors (C * VEC elements); element e of the row
+// belongs to component e % VEC, and each component folds its elements in
+// increasing index (kStage is a multiple of VEC).
+template <class Op, int VEC = 1, class View>
 __device__ __forceinline__ void contiguous_staged(const View& view, bool active, int t, int C,
-                                                  int limit, typename Op::T& acc,
+                                                  int limit, typename Op::T (&acc)[VEC],
                                                   float* stage) {
+  static_assert(4 % VEC == 0, "a staged 16-byte part holds whole vectors");
   constexpr int NOPS = View::kOps;
-  acc = Op::Arith::zero();
+#pragma unroll
+  for (int j = 0; j < VEC; ++j) acc[j] = Op::Arith::zero();
+  C *= VEC;                                     // elements per lane row
   const int lane = threadIdx.x & (kWave - 1);
   int have = limit - t * C;                     // elements of this lane's row that exist
   have = active ? (have < 0 ? 0 : (have > C ? C : have)) : 0;
@@ -418,7 +424,7 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
         for (int o = 0; o < NOPS; ++o)
           v[o] = *reinterpret_cast<const f32x4*>(stage + (o * kWave + lane) * kStageRow + j * 4);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = Op::step(View::term(v, i), acc);
+        for (int i = 0; i < 4; ++i) acc[i % VEC] = Op::step(View::term(v, i), acc[i % VEC]);
       }
     }
     wave_lds_order();
@@ -436,7 +442,7 @@ __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool act
   typename Op::T acc[NL];
   if constexpr (ORDER == kContiguous && View::kStageable) {
     if (stage != nullptr) {
-      contiguous_staged<Op>(view, active, t, C, limit, acc[0], stage);
+      contiguous_staged<Op, 1>(view, active, t, C, limit, acc, stage);
       return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
     }
   }
@@ -465,17 +471,26 @@ struct ShiftedView {
 // out[g * cv ...], cv = VEC, or L * VEC uncombined, in lane then component
 // order (asScalar VEC of the join).  All threads of the work-group call this
 // together (the combine has barriers).
+// `stage`: as for chunk_value (the contiguous order, staged per wavefront).
 template <class Op, int ORDER, int NV, int COMBINE, int VEC, class View>
 __device__ __forceinline__ void chunk_values_wide(const View& view, bool active, int t, int team,
                                                   int L, int C, int limit,
                                                   typename Op::T* scratch, typename Op::T* out,
-                                                  int64_t g) {
+                                                  int64_t g, float* stage = nullptr) {
   using T = typename Op::T;
+  constexpr bool kStaged = ORDER == kContiguous && View::kStageable;
   if constexpr (VEC == 1) {
     static_assert(COMBINE == kNone, "scalar combined chunks use chunk_value");
     constexpr int NL = (ORDER == kStrided) ? NV : 1;
     T acc[NL];
-    lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
+    if constexpr (kStaged) {
+      if (stage != nullptr)
+        contiguous_staged<Op, 1>(view, active, t, C, limit, acc, stage);
+      else
+        lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
+    } else {
+      lane_folds<Op, ORDER, NV>(view, active, t, L, C, limit, acc);
+    }
     if (active) {
       const int64_t lane0 = g * L + (ORDER == kStrided ? t * NV : t);
 #pragma unroll
@@ -492,10 +507,20 @@ __device__ __forceinline__ void chunk_values_wide(const View& view, bool active,
       // vector lane t takes vectors t*C .. t*C + C-1: within the lane's row of
       // VEC*C elements, component j takes elements j, j + VEC, ..., the
       // strided order over VEC lanes
-      const int base = t * VEC * C;
-      int have = limit - base;
-      have = have < 0 ? 0 : (have > VEC * C ? VEC * C : have);
-      lane_folds<Op, kStrided, VEC>(ShiftedView<View>{view, base}, active, 0, VEC, C, have, acc);
+      bool staged = false;
+      if constexpr (kStaged) {
+        if (stage != nullptr) {
+          contiguous_staged<Op, VEC>(view, active, t, C, limit, acc, stage);
+          staged = true;
+        }
+      }
+      if (!staged) {
+        const int base = t * VEC * C;
+        int have = limit - base;
+        have = have < 0 ? 0 : (have > VEC * C ? VEC * C : have);
+        lane_folds<Op, kStrided, VEC>(ShiftedView<View>{view, base}, active, 0, VEC, C, have,
+                                      acc);
+      }
     }
     if constexpr (COMBINE == kNone) {
       if (active) {

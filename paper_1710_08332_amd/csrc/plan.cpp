@@ -218,10 +218,11 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     lds = static_cast<size_t>(q.teams_per_wg) * (q.team / 64) * q.acc_bytes;
   }
   // The contiguous order with binary32 operands is staged through LDS, one
-  // wavefront at a time, when every lane holds whole tiles and the
-  // work-group is whole wavefronts, at most 256 threads.
-  q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 && V == 1 &&
-            q.combine != DPIA_COMBINE_NONE && q.C % kStage == 0 && q.wg_threads <= 256 &&
+  // wavefront at a time, when every lane's row (C elements, or C vectors of
+  // 4) holds whole tiles and the work-group is whole wavefronts, at most 256
+  // threads.
+  q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 &&
+            (V == 1 || V == 4) && (q.C * V) % kStage == 0 && q.wg_threads <= 256 &&
             q.wg_threads % 64 == 0;
   q.stage_off = 0;
   if (q.stage) {

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
       if (active && t == 0) partials[g] = v;
     } else {
       chunk_values_wide<Op, ORDER, NV, COMBINE, VEC>(view, active, t, a.team, a.L, a.C, limit,
-                                                     scratch, partials, g);
+                                                     scratch, partials, g, stage);
     }
   }
   if (a.one_pass) {
