@@ -196,11 +196,11 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   } else {
     q.teams_per_wg = q.team >= 256 ? 1 : 256 / q.team;
 #if DPIA_MIN_WORKGROUPS
-    // few chunks: fewer chunks per work-group, so that they spread over
-    // more compute units (which work-group evaluates a chunk is free;
-    // measured on the Sec. 6.2 form, 128 chunks of 64 lanes: 3.4% -> 7.8%
-    // of peak)
-    while (q.teams_per_wg > 1 &&
+    // few chunks: fewer chunks per work-group, down to one wavefront per
+    // work-group, so that they spread over more compute units (which
+    // work-group evaluates a chunk is free; measured on the Sec. 6.2 form,
+    // 128 chunks of 64 lanes: 3.4% -> 7.8% of peak)
+    while (q.teams_per_wg > 1 && (q.teams_per_wg / 2) * q.team >= 64 &&
            (q.items + q.teams_per_wg - 1) / q.teams_per_wg < DPIA_MIN_WORKGROUPS)
       q.teams_per_wg /= 2;
 #endif
@@ -240,7 +240,8 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     lds = q.stage ? static_cast<size_t>(q.wg_threads / 64) * 64 * (q.scal_tile + 4) * sizeof(float)
                   : 0;
   }
-  if (op == DPIA_OP_DOT || op == DPIA_OP_ASUM) {
+  if ((op == DPIA_OP_DOT || op == DPIA_OP_ASUM) && q.passes == 1) {
+    // the last work-group of a 1-pass launch runs the final fold
     size_t fold = static_cast<size_t>(kFoldBlock) * q.acc_bytes;
     if (fold > lds) lds = fold;
   }

@@ -56,6 +56,26 @@ def test_dot_and_asum_bit_exact(strat, passes):
     assert_same_bits(gpu_asum(x, s), S.asum(x, plan), f"asum n={n}")
 
 
+# Small teams over many chunks: several teams share a work-group (few chunks
+# are spread one wavefront per work-group, so the small cases above run
+# unpacked) and the last work-group and the last chunk are only partly
+# filled.
+@pytest.mark.parametrize("strat", [(4, 16, C_, TREE), (4, 16, T_, TREE), (2, 32, T_, SEQ),
+                                   (16, 16, C_, TREE), (16, 16, C_, SEQ)], ids=_ids)
+@pytest.mark.parametrize("passes", [1, 2])
+def test_packed_small_teams_with_ragged_last_workgroup(strat, passes):
+    C, L, order, comb = strat
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, passes=passes)
+    W = C * L
+    n = W * 4101 + W // 3 + 1
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    plan = to_plan(s)
+    assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, plan), f"dot packed n={n}")
+    xd, yd = discriminating(11, n)
+    assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, plan), f"dot packed cancelling n={n}")
+    assert_same_bits(gpu_asum(x, s), S.asum(x, plan), f"asum packed n={n}")
+
+
 def test_config1_dot_and_asum_at_full_size():
     # N = 2^20, split 4096 -> mapWorkgroup (split 256 -> mapLocal reduceSeq)
     # -> tree in local memory -> second-pass reduceSeq
