@@ -131,6 +131,68 @@ def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
                       f"repetitions, {el:.1f} s, numpy single thread"}, parity
 
 
+class TimingEvents:
+    """HIP events for timing only, created with hipEventDisableSystemFence:
+    recording them skips the system-scope cache write-back and invalidate
+    that a default event performs, which perturbs the work around it.  They
+    come from the HIP runtime torch has loaded (so they share its streams);
+    where that library cannot be found, torch's events are used."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, n):
+        import ctypes
+        import torch
+        self._ct = ctypes
+        self.hip = None
+        try:
+            with open("/proc/self/maps") as f:
+                paths = [ln.split()[-1] for ln in f if "libamdhip64" in ln]
+            self.hip = ctypes.CDLL(paths[0]) if paths else None
+        except OSError:
+            self.hip = None
+        self.pairs = []
+        for _ in range(n):
+            if self.hip is None:
+                self.pairs.append((torch.cuda.Event(enable_timing=True),
+                                   torch.cuda.Event(enable_timing=True)))
+                continue
+            pair = []
+            for _ in range(2):
+                e = ctypes.c_void_p()
+                if self.hip.hipEventCreateWithFlags(ctypes.byref(e), ctypes.c_uint(
+                        self.DISABLE_SYSTEM_FENCE)) != 0:
+                    raise RuntimeError("hipEventCreateWithFlags failed")
+                pair.append(e)
+            self.pairs.append(tuple(pair))
+        self.kind = "hip events without system fence" if self.hip else "torch events"
+
+    def record(self, i, which):
+        import torch
+        e = self.pairs[i][which]
+        if self.hip is None:
+            e.record()
+        elif self.hip.hipEventRecord(e, self._ct.c_void_p(
+                torch.cuda.current_stream().cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def elapsed_ms(self, i):
+        a, b = self.pairs[i]
+        if self.hip is None:
+            return a.elapsed_time(b)
+        ms = self._ct.c_float()
+        if self.hip.hipEventElapsedTime(self._ct.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def close(self):
+        if self.hip is not None:
+            for a, b in self.pairs:
+                self.hip.hipEventDestroy(a)
+                self.hip.hipEventDestroy(b)
+            self.pairs = []
+
+
 def _line(**kw):
     print(json.dumps(kw), flush=True)
 
@@ -649,12 +711,12 @@ def main():
 
     # one step: the dot's two passes (chunk values, then their ordered fold)
     # and the gemv, all on torch's current stream
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record()
+    def step(i=None):
+        if i is not None:
+            timer.record(i, 0)
         dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals)
-        if ev is not None:
-            ev[1].record()
+        if i is not None:
+            timer.record(i, 1)
         dp.fold(dp.OP_DOT, DOT_STRATEGY, chunk_vals, N_DOT, dp.F32, out=out)
         dp.gemv(At, xvt, GEMV_STRATEGY, y=yg)
 
@@ -670,15 +732,16 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    timer = TimingEvents(args.steps)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(evs[i])
+        step(i)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    dot_ms = [a.elapsed_time(b) for a, b in evs]
+    dot_ms = [timer.elapsed_ms(i) for i in range(args.steps)]
     dot_avg_s = float(np.mean(dot_ms)) / 1e3
+    timer_kind = timer.kind
+    timer.close()
 
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
@@ -713,6 +776,7 @@ def main():
             "frac": round(achieved / PEAK_GBPS, 4),
             "traffic": measured_traffic(),
             "avg_kernel_us": round(dot_avg_s * 1e6, 3),
+            "timed_with": timer_kind + " around each first-pass launch",
         },
     }
     if not args.no_cpu_baseline:
