@@ -53,6 +53,7 @@ import time
 import numpy as np
 
 import paper_1710_08332_amd as dp
+from paper_1710_08332_amd.timing import TimingEvents
 
 METRIC = "HBM GB/s (% of peak) for dot/asum/gemv per strategy; batched vs plain"
 PEAK_GBPS = 8000.0   # MI355X HBM3E, published
@@ -129,68 +130,6 @@ def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
     return {"value": round(value, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"the full step (dot 2^26 + gemv 8192^2, same strategies) x {reps} "
                       f"repetitions, {el:.1f} s, numpy single thread"}, parity
-
-
-class TimingEvents:
-    """HIP events for timing only, created with hipEventDisableSystemFence:
-    recording them skips the system-scope cache write-back and invalidate
-    that a default event performs, which perturbs the work around it.  They
-    come from the HIP runtime torch has loaded (so they share its streams);
-    where that library cannot be found, torch's events are used."""
-
-    DISABLE_SYSTEM_FENCE = 0x20000000
-
-    def __init__(self, n):
-        import ctypes
-        import torch
-        self._ct = ctypes
-        self.hip = None
-        try:
-            with open("/proc/self/maps") as f:
-                paths = [ln.split()[-1] for ln in f if "libamdhip64" in ln]
-            self.hip = ctypes.CDLL(paths[0]) if paths else None
-        except OSError:
-            self.hip = None
-        self.pairs = []
-        for _ in range(n):
-            if self.hip is None:
-                self.pairs.append((torch.cuda.Event(enable_timing=True),
-                                   torch.cuda.Event(enable_timing=True)))
-                continue
-            pair = []
-            for _ in range(2):
-                e = ctypes.c_void_p()
-                if self.hip.hipEventCreateWithFlags(ctypes.byref(e), ctypes.c_uint(
-                        self.DISABLE_SYSTEM_FENCE)) != 0:
-                    raise RuntimeError("hipEventCreateWithFlags failed")
-                pair.append(e)
-            self.pairs.append(tuple(pair))
-        self.kind = "hip events without system fence" if self.hip else "torch events"
-
-    def record(self, i, which):
-        import torch
-        e = self.pairs[i][which]
-        if self.hip is None:
-            e.record()
-        elif self.hip.hipEventRecord(e, self._ct.c_void_p(
-                torch.cuda.current_stream().cuda_stream)) != 0:
-            raise RuntimeError("hipEventRecord failed")
-
-    def elapsed_ms(self, i):
-        a, b = self.pairs[i]
-        if self.hip is None:
-            return a.elapsed_time(b)
-        ms = self._ct.c_float()
-        if self.hip.hipEventElapsedTime(self._ct.byref(ms), a, b) != 0:
-            raise RuntimeError("hipEventElapsedTime failed")
-        return ms.value
-
-    def close(self):
-        if self.hip is not None:
-            for a, b in self.pairs:
-                self.hip.hipEventDestroy(a)
-                self.hip.hipEventDestroy(b)
-            self.pairs = []
 
 
 def _line(**kw):

@@ -89,22 +89,24 @@ def valid(s: Strategy, op: int, dtype: int, m: int, n: int) -> bool:
 def time_us(fn: Callable[[], object], reps: int = 20, warmup: int = 3,
             between: Callable[[], object] = None) -> Tuple[float, float, float]:
     """(median, p10, p90) in microseconds of ``fn`` on torch's current stream,
-    with HIP events around each call.  ``between`` (untimed) runs before every
-    timed call, e.g. to evict the last-level cache."""
+    with timing-only HIP events around each call (see ``timing``).
+    ``between`` (untimed) runs before every timed call, e.g. to evict the
+    last-level cache."""
     import torch
+    from .timing import TimingEvents
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for a, b in ev:
+    ev = TimingEvents(reps)
+    for i in range(reps):
         if between is not None:
             between()
-        a.record()
+        ev.record(i, 0)
         fn()
-        b.record()
+        ev.record(i, 1)
     torch.cuda.synchronize()
-    ts = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    ts = sorted(ev.elapsed_ms(i) * 1e3 for i in range(reps))
+    ev.close()
     q = statistics.quantiles(ts, n=10) if len(ts) >= 2 else [ts[0]] * 9
     return statistics.median(ts), q[0], q[-1]
 
