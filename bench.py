@@ -29,7 +29,9 @@ Other workloads (one JSON line per measured item, not the headline):
                           launches (eager, graph) against one batched run
                           (eager, graph)
     --workload scal       scal y = alpha x, N = 2^26, under strided and
-                          contiguous strategies, out of place and in place
+                          contiguous strategies, out of place and in place;
+                          and the BLAS gemv y := alpha A x + beta y beside
+                          y = A x (binary32, 8192^2 and 16384^2)
     --workload vector     dot N = 2^26 under vector (asVector 4) strategies,
                           among them the dot expression of Sec. 6.2 (float4
                           views, 64 work-items folding 2048 vectors each, no
@@ -482,6 +484,49 @@ def workload_scal(args):
     xt.copy_(torch.from_numpy(x))
     dp.scal(float(alpha), xt, strategies[0], y=yt)
     torch.cuda.synchronize()
+    # the BLAS gemv y := alpha A x + beta y beside the plain y = A x, binary32
+    # 8192^2 (the headline strategy) and 16384^2, cache evicted before each call
+    blas_out = {}
+    for mk, gs in ((8192, GEMV_STRATEGY),
+                   (16384, dp.Strategy(seq_len=32, local_size=512, order=dp.STRIDED,
+                                       wg_combine=dp.TREE))):
+        A, xv = synthetic.gemv_inputs(mk, mk, synthetic.SEEDS["scale"])
+        At, xvt = torch.from_numpy(A).cuda(), torch.from_numpy(xv).cuda()
+        y0 = torch.from_numpy(synthetic.dot_inputs(mk, synthetic.SEEDS["scale"] + 1)[0]).cuda()
+        yb = torch.empty_like(y0)
+        for form, a_, b_, nbytes in (("y = A x", 1.0, 0.0, 4 * (mk * mk + 2 * mk)),
+                                     ("y := 1.3 A x - 2.1 y", 1.3, -2.1, 4 * (mk * mk + 3 * mk))):
+            def run():
+                if b_ == 0.0:
+                    dp.gemv(At, xvt, gs, y=yb)
+                else:      # in place: y grows by about 2.1x per call, far from overflow
+                    dp.gemv_blas(a_, At, xvt, b_, yb, gs)
+            yb.copy_(y0)
+            med, p10, p90 = time_us(run, reps=20, between=evict)
+            _line(workload="scal", op="gemv_blas" if b_ else "gemv", m=mk, k=mk, form=form,
+                  strategy=strategy_text(gs, gemv=True), us=round(med, 2), p10=round(p10, 2),
+                  p90=round(p90, 2), gbs=_gbs(nbytes, med),
+                  pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1))
+            if mk == 8192:
+                yb.copy_(y0)
+                run()
+                blas_out[form] = yb.cpu().numpy()
+        if mk == 8192:
+            blas_in = (A, xv, y0.cpu().numpy(), gs)
+        del At
+    if not args.no_cpu_baseline:
+        from oracle import strategies as S
+        from tests.gpu_util import to_plan
+        A, xv, y0h, gs = blas_in
+        t0 = time.perf_counter()
+        want = S.gemv_blas(np.float32(1.3), A, xv, np.float32(-2.1), y0h, to_plan(gs))
+        el = time.perf_counter() - t0
+        _line(workload="scal", op="gemv_blas", cpu_baseline={"kind": "oracle", "cores": 1,
+                                                             "sample": "8192^2, one call",
+                                                             "seconds": round(el, 2)},
+              parity={"bit_exact": bool(np.array_equal(
+                  blas_out["y := 1.3 A x - 2.1 y"].view(np.uint32),
+                  np.asarray(want, np.float32).view(np.uint32)))})
     if not args.no_cpu_baseline:
         from oracle import strategies as S
         m = 1 << 22                                  # a 4 Mi-element prefix: ~1 s of oracle work
