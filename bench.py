@@ -613,8 +613,9 @@ def workload_generated(args):
         ("gemv", "generated", lambda: gg.run({"A": At, "x": xvt}, gout), GEMV_BYTES),
         ("gemv", "library", lambda: dp.gemv(At, xvt, GEMV_STRATEGY, y=yg), GEMV_BYTES),
     ]
-    # low-precision gemv 16384 x 16384, C=16 L=1024 strided tree
-    big = dp.Strategy(seq_len=16, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE)
+    # low-precision gemv 16384 x 16384, C=16 L=1024 strided tree, 2 rows per work-group
+    big = dp.Strategy(seq_len=16, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
+                      rows_per_wg=2)
     A16, xv16 = synthetic.gemv_inputs(16384, 16384, synthetic.SEEDS["precision"])
     xv16t = torch.from_numpy(xv16).cuda()
     c16 = torch.from_numpy(synthetic.quantise_bf16(A16).view(np.int16)).cuda()

@@ -65,7 +65,7 @@ def programs() -> List[Tuple[str, str, Dict, str]]:
     # low-precision gemv: small (parity) and 16384 x 16384 (speed), and every
     # storage code through the generated decoders
     lp = Strategy(seq_len=4, local_size=64, order=STRIDED, rows_per_wg=2)
-    big = Strategy(seq_len=16, local_size=1024, order=STRIDED)
+    big = Strategy(seq_len=16, local_size=1024, order=STRIDED, rows_per_wg=2)
     for fmt, et in (("bf16", "u16"), ("fp8", "u8")):
         ins = {"A": (et, (64, 256)), "x": ("f32", (256,))}
         bins = {"A": (et, (16384, 16384)), "x": ("f32", (16384,))}

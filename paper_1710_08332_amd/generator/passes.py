@@ -21,6 +21,14 @@ the GPU runs it.
 3. ``batch``: such a loop runs B iterations per round (``Blocked``): the
    loads of all B iterations first, then the B steps in increasing order, so
    B iterations' loads are in flight together.
+
+Before these, ``pair_rows`` runs two iterations of a work-group's
+sequential loop at once where they share operand reads (a gemv's rows
+reading the same x with A in a 1- or 2-byte format): the two iterations'
+commands are copied with their names renamed, and their parallel and
+sequential loops fused position by position, so that ``extract_loads``
+finds each shared read once.  The two iterations are independent (the
+loop is a ``map``), and each keeps its own operations in its own order.
 """
 
 from __future__ import annotations
@@ -116,6 +124,106 @@ def _defined(body) -> Set[str]:
             out.add(b.name)
         elif isinstance(b, (For, Blocked)):
             out |= _defined(b.body if isinstance(b, For) else b.main + b.tail)
+    return out
+
+
+# ------------------------------------------------------------------ 0. rows
+
+def _deep_defined(body) -> Set[str]:
+    out = set()
+    for b in body:
+        if isinstance(b, Decl):
+            out.add(b.name)
+        elif isinstance(b, (For, ParFor)):
+            out |= _deep_defined(b.body)
+    return out
+
+
+def _deep_rewrite(cmd, g_ix, ren: Dict[str, str]):
+    """cmd (declarations, assignments and loops) with index map g_ix and the
+    names in ren renamed."""
+    if isinstance(cmd, For):
+        return For(cmd.var, cmd.n, [_deep_rewrite(b, g_ix, ren) for b in cmd.body])
+    if isinstance(cmd, ParFor):
+        return ParFor(cmd.level, cmd.var, cmd.n, [_deep_rewrite(b, g_ix, ren) for b in cmd.body])
+    return _rewrite(cmd, g_ix, ren)
+
+
+def _jam(b0, b1):
+    """Two copies of one command list, run together: loops at the same
+    position fused (copy 0's commands, then copy 1's, per iteration), other
+    commands one after the other."""
+    out = []
+    for x0, x1 in zip(b0, b1):
+        if isinstance(x0, ParFor) and x0.level == "local":
+            out.append(ParFor(x0.level, x0.var, x0.n, _jam(x0.body, x1.body)))
+        elif isinstance(x0, For):
+            out.append(For(x0.var, x0.n, _jam(x0.body, x1.body)))
+        else:
+            out += [x0, x1]
+    return out
+
+
+def _shared_narrow_reads(loop: For, inputs: Set[str], types) -> bool:
+    """The loop's lane folds read an input at positions that do not depend
+    on the loop variable (shared by its iterations) beside an input of 1 or
+    2 bytes per element that they do depend on."""
+    shared, narrow = False, False
+
+    def refs(e, acc):
+        if isinstance(e, Ref):
+            acc.append(e)
+        elif isinstance(e, (ir.Bin,)):
+            refs(e.a, acc)
+            refs(e.b, acc)
+        elif isinstance(e, (ir.Un, ir.Cast, ir.Decode)):
+            refs(e.a, acc)
+        elif isinstance(e, ir.Select):
+            for o in e.options:
+                refs(o, acc)
+        return acc
+
+    def walk(body, in_lanes):
+        nonlocal shared, narrow
+        for b in body:
+            if isinstance(b, ParFor):
+                walk(b.body, in_lanes or b.level == "local")
+            elif isinstance(b, For):
+                walk(b.body, in_lanes)
+            elif isinstance(b, Assign) and in_lanes:
+                for r in refs(b.rhs, []):
+                    if r.idx is None or r.name not in inputs:
+                        continue
+                    if ix_uses(r.idx, loop.var):
+                        narrow = narrow or _ESIZE.get(types[r.name], 4) <= 2
+                    else:
+                        shared = True
+    walk(loop.body, False)
+    return shared and narrow
+
+
+def pair_rows(cmds, inputs: Set[str], types: Dict[str, str], in_group: bool = False):
+    out = []
+    for c in cmds:
+        if isinstance(c, ParFor):
+            out.append(ParFor(c.level, c.var, c.n,
+                              pair_rows(c.body, inputs, types, c.level == "workgroup")))
+        elif (isinstance(c, For) and in_group and c.n >= 2 and c.n % 2 == 0 and
+              any(isinstance(b, ParFor) for b in c.body) and
+              _shared_narrow_reads(c, inputs, types)):
+            names = _deep_defined(c.body)
+            copies = []
+            for j in range(2):
+                ren = {nm: f"{nm}_r{j}" for nm in names}
+                for nm in names:
+                    if nm in types:
+                        types[ren[nm]] = types[nm]
+                row = iadd(ir.imul(IVar(c.var), 2), j)
+                copies.append([_deep_rewrite(b, lambda e, row=row: ix_replace(e, c.var, row), ren)
+                               for b in c.body])
+            out.append(For(c.var, c.n // 2, _jam(copies[0], copies[1])))
+        else:
+            out.append(c)
     return out
 
 
@@ -315,6 +423,7 @@ def _batched(c: For):
 
 
 def optimise(cmds, inputs: Set[str], streamed: Set[str], types: Dict[str, str], fresh):
+    cmds = pair_rows(cmds, inputs, types)
     cmds = extract_loads(cmds, inputs, streamed, types, fresh)
     cmds = coarsen(cmds, types, fresh)
     return batch(cmds, fresh)

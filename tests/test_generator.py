@@ -278,3 +278,69 @@ def test_optimised_low_precision_rows_keep_the_oracle_value(fmt, lanes):
     want = S.gemv(codes, x, S.Plan(seq=2, lanes=lanes, order="strided"), a_format=fmt,
                   scale=scale)
     assert same(GI.run(prog, feed)["out"], want)
+
+
+@pytest.mark.parametrize("fmt,rows", [("bf16", 2), ("fp8", 4), ("bf16", 6)])
+def test_paired_low_precision_rows_share_x_and_keep_the_oracle_value(fmt, rows, monkeypatch):
+    # a work-group's rows of bf16 / fp8 codes run two at a time, so each x
+    # read serves both: as many x loads per round as one row had, half the
+    # rounds, the same bits
+    from paper_1710_08332_amd import STRIDED, Strategy
+    from paper_1710_08332_amd.generator import passes
+    from paper_1710_08332_amd.generator import strategies as P
+    lanes = 512
+    s = Strategy(seq_len=2, local_size=lanes, order=STRIDED, rows_per_wg=rows)
+    m, k = 2 * rows, 2 * lanes
+    g = np.random.default_rng(93)
+    x = g.standard_normal(k).astype(np.float32)
+    if fmt == "bf16":
+        codes = g.integers(0, 2 ** 16, (m, k)).astype(np.uint16)
+        codes[(codes & 0x7F80) == 0x7F80] = 0x3F80
+        inputs = {"A": ("u16", (m, k)), "x": ("f32", (k,))}
+        feed, scale = {"A": codes, "x": x}, None
+    else:
+        codes = g.integers(0, 256, (m, k)).astype(np.uint8)
+        codes[(codes & 0x7F) == 0x7F] = 0x38
+        scale = g.random(m, dtype=np.float32) + np.float32(0.5)
+        inputs = {"A": ("u8", (m, k)), "x": ("f32", (k,)), "scale": ("f32", (m,))}
+        feed = {"A": codes, "x": x, "scale": scale}
+    text = P.gemv_text(s, m, k, fmt)
+    want = S.gemv(codes, x, S.Plan(seq=2, lanes=lanes, order="strided", rows=rows),
+                  a_format=fmt, scale=scale)
+    paired = T.translate(text, inputs)
+    assert same(GI.run(paired, feed)["out"], want)
+    monkeypatch.setattr(passes, "pair_rows", lambda cmds, *a, **kw: cmds)
+    single = T.translate(text, inputs)
+    assert same(GI.run(single, feed)["out"], want)
+
+    def row_loops(prog):
+        return [c.n for c in _flat(prog.kernels[0].body) if type(c).__name__ == "For"
+                and c.var.startswith("k") and any(type(b).__name__ in ("ParFor", "Lanes")
+                                                  for b in c.body)]
+    names = {c.name for c in _flat(paired.kernels[0].body) if hasattr(c, "name")}
+    assert any(n.endswith("_r1") for n in names)
+    assert row_loops(paired) == [rows // 2] and row_loops(single) == [rows]
+    # per load of A's codes, half as many loads of x
+    def ratio(prog):
+        loads = [c for c in _flat(prog.kernels[0].body) if type(c).__name__ in ("Load", "VLoad")]
+        return (sum(c.buf == "x" for c in loads) / sum(c.buf == "A" for c in loads))
+    assert ratio(paired) * 2 == ratio(single)
+
+
+def _flat(cmds, acc=None):
+    acc = acc if acc is not None else []
+    for c in cmds:
+        acc.append(c)
+        for attr in ("body", "main", "tail"):
+            if hasattr(c, attr):
+                _flat(getattr(c, attr), acc)
+    return acc
+
+
+def test_binary32_rows_are_not_paired():
+    # the hand-written kernels pair rows only for 1- and 2-byte elements
+    p = S.Plan(seq=16, lanes=256, order="strided", rows=2)
+    m, k = 4, p.chunk
+    prog = T.translate(S.gemv_expr(m, k, p), {"A": ("f32", (m, k)), "x": ("f32", (k,))})
+    names = {c.name for kk in prog.kernels for c in _flat(kk.body) if hasattr(c, "name")}
+    assert not any(n.endswith("_r1") for n in names)

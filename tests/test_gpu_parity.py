@@ -708,3 +708,30 @@ def test_generated_low_precision_gemv_equals_oracle_and_library(fmt):
     assert_same_bits(got, gpu_gemv(codes, x, s, a_dtype=adt, scale=scale),
                      f"generated {fmt} gemv vs library")
     prog.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_generated_low_precision_gemv_at_full_size_with_paired_rows(fmt):
+    # 16384 x 16384, two rows per work-group run together by the generated
+    # kernel: bit-exact against the library, and against the oracle on a
+    # sample of rows (rows are independent)
+    import torch
+    s = dp.Strategy(seq_len=16, local_size=1024, order=T_, rows_per_wg=2)
+    A, x = synthetic.gemv_inputs(16384, 16384, synthetic.SEEDS["precision"])
+    if fmt == "bf16":
+        codes, scale, adt = synthetic.quantise_bf16(A), None, dp.BF16
+        feed = {"A": cuda(codes.view(np.int16)), "x": cuda(x)}
+    else:
+        (codes, scale), adt = synthetic.quantise_fp8_rows(A), dp.FP8_E4M3
+        feed = {"A": cuda(codes), "x": cuda(x), "scale": cuda(scale)}
+    del A
+    prog = _generated(f"gemv_{fmt}_16384")
+    got = prog.run(feed)["out"].cpu().numpy()
+    torch.cuda.synchronize()
+    prog.close()
+    assert_same_bits(got, gpu_gemv(codes, x, s, a_dtype=adt, scale=scale),
+                     f"generated {fmt} 16384^2 vs library")
+    rows = np.random.default_rng(5).choice(16384, 48, replace=False)
+    want = S.gemv(codes[rows], x, to_plan(s.with_(rows_per_wg=1)), a_format=fmt,
+                  scale=None if scale is None else scale[rows])
+    assert_same_bits(got[rows], want, f"generated {fmt} 16384^2 vs oracle, sampled rows")
