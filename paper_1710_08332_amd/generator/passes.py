@@ -20,7 +20,7 @@ the GPU runs it.
    up to 16 bytes (``VLoad``) serves them.
 3. ``batch``: such a loop runs B iterations per round (``Blocked``): the
    loads of all B iterations first, then the B steps in increasing order, so
-   B iterations' loads are in flight together.
+   B iterations' loads (128 bytes per work-item) are in flight together.
 
 Before these, ``pair_rows`` runs two iterations of a work-group's
 sequential loop at once where they share operand reads (a gemv's rows
@@ -40,7 +40,7 @@ from .ir import (Assign, Blocked, Decl, For, IConst, IVar, Lanes, Load, ParFor, 
                  SchedBarrier, VLoad, iadd)
 
 LANES = 4
-BATCH_ELEMS = 32          # elements' worth of loads issued per round
+BATCH_BYTES = 128         # bytes of loads per work-item issued per round
 
 
 # ------------------------------------------------------------------ helpers
@@ -405,8 +405,8 @@ def _batched(c: For):
     loads = [b for b in c.body if isinstance(b, (Load, VLoad)) and ix_uses(b.idx, c.var)]
     if not loads:
         return None
-    elems = sum(b.width if isinstance(b, VLoad) else 1 for b in loads)
-    B = max(1, BATCH_ELEMS // elems)
+    nbytes = sum((b.width if isinstance(b, VLoad) else 1) * _ESIZE.get(b.ctype, 4) for b in loads)
+    B = max(1, BATCH_BYTES // nbytes)
     if c.n < 2 * B:
         return None
     names = _defined(c.body)
