@@ -17,9 +17,12 @@ constexpr int kFoldBlock = 2048;
 // Alignment of the sections of a workspace.
 constexpr size_t kWsAlign = 256;
 // LDS staging of the contiguous order: elements per lane per tile, and the
-// LDS row stride in floats (80 bytes: an odd number of 16-byte units).
+// LDS row stride in floats (144 bytes: an odd number of 16-byte units).  A
+// tile of 32 binary32 elements is one 128-byte line of each lane's row:
+// measured on the contiguous dot at 2^26 (L=256, C=64..1024), 32 runs at
+// 65-75% of peak, 16 at 39-46% and 64 at 51-77% (needing 256 registers).
 #ifndef DPIA_STAGE
-#define DPIA_STAGE 16
+#define DPIA_STAGE 32
 #endif
 constexpr int kStage = DPIA_STAGE;
 constexpr int kStageRow = kStage + 4;

@@ -32,8 +32,10 @@ struct ReduceArgs {
   void* out;
 };
 
-template <class Op, int ORDER, int NV, int COMBINE, int FINAL, int VEC>
-__global__ void __launch_bounds__(1024) reduce_kernel(Op op, ReduceArgs a) {
+// MAXT: the largest work-group it is launched with (256 or 1024); the
+// 256-thread build may use more registers than the 1024-thread one.
+template <class Op, int ORDER, int NV, int COMBINE, int FINAL, int VEC, int MAXT>
+__global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
   using T = typename Op::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int is_last;
@@ -155,7 +157,8 @@ hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipSt
     constexpr int COMBINE = decltype(comb)::value;
     constexpr int NV = decltype(nvc)::value;
     constexpr int VEC = decltype(vec)::value;
-    auto kern = reduce_kernel<Op, ORDER, NV, COMBINE, FINAL, VEC>;
+    auto kern = p.wg_threads <= 256 ? reduce_kernel<Op, ORDER, NV, COMBINE, FINAL, VEC, 256>
+                                    : reduce_kernel<Op, ORDER, NV, COMBINE, FINAL, VEC, 1024>;
     Op op_copy = op;
     ReduceArgs a_copy = a;
     void* args[] = {&op_copy, &a_copy};
