@@ -202,6 +202,25 @@ def _shared_narrow_reads(loop: For, inputs: Set[str], types) -> bool:
     return shared and narrow
 
 
+def _independent(loop: For) -> bool:
+    """No iteration of the loop reads what another writes: every assignment
+    targets a name declared in the body or a global array at a position
+    that depends on the loop variable (a map's output, not a reduction's
+    accumulator)."""
+    local = _deep_defined(loop.body)
+
+    def ok(body):
+        for b in body:
+            if isinstance(b, (For, ParFor)):
+                if not ok(b.body):
+                    return False
+            elif isinstance(b, Assign) and b.name not in local:
+                if b.space != "global" or b.idx is None or not ix_uses(b.idx, loop.var):
+                    return False
+        return True
+    return ok(loop.body)
+
+
 def pair_rows(cmds, inputs: Set[str], types: Dict[str, str], in_group: bool = False):
     out = []
     for c in cmds:
@@ -209,7 +228,7 @@ def pair_rows(cmds, inputs: Set[str], types: Dict[str, str], in_group: bool = Fa
             out.append(ParFor(c.level, c.var, c.n,
                               pair_rows(c.body, inputs, types, c.level == "workgroup")))
         elif (isinstance(c, For) and in_group and c.n >= 2 and c.n % 2 == 0 and
-              any(isinstance(b, ParFor) for b in c.body) and
+              any(isinstance(b, ParFor) for b in c.body) and _independent(c) and
               _shared_narrow_reads(c, inputs, types)):
             names = _deep_defined(c.body)
             copies = []

@@ -344,3 +344,22 @@ def test_binary32_rows_are_not_paired():
     prog = T.translate(S.gemv_expr(m, k, p), {"A": ("f32", (m, k)), "x": ("f32", (k,))})
     names = {c.name for kk in prog.kernels for c in _flat(kk.body) if hasattr(c, "name")}
     assert not any(n.endswith("_r1") for n in names)
+
+
+def test_a_reduction_over_rows_is_not_paired():
+    # a reduceSeq over a work-group's rows carries its accumulator from row
+    # to row: pairing would reorder its updates, so the pass leaves it alone
+    import synthetic
+    text = ("(mapWorkgroup (lam (rows) (reduceSeq (lam (row acc) (+ (reduceSeq (lam (e a)"
+            " (+ e a)) 0 (mapLocal (lam (p) (* (bf16 (fst p)) (snd p))) (zip row x))) acc))"
+            " 0 rows)) (split 2 A))")
+    inputs = {"A": ("u16", (4, 256)), "x": ("f32", (256,))}
+    prog = T.translate(text, inputs)
+    names = {c.name for c in _flat(prog.kernels[0].body) if hasattr(c, "name")}
+    assert not any(n.endswith("_r1") for n in names)
+    g = np.random.default_rng(94)
+    A = synthetic.quantise_bf16(g.standard_normal((4, 256)).astype(np.float32))
+    x = g.standard_normal(256).astype(np.float32)
+    feed = {"A": A, "x": x}
+    want = np.atleast_1d(eval_numpy.evaluate(text, feed, num="f32"))
+    assert same(GI.run(prog, feed)["out"], want)
