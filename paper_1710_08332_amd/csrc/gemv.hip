@@ -238,6 +238,17 @@ using namespace dpia;
 // dominate the traffic through the vector caches.
 static constexpr int kRowBlock = DPIA_ROW_BLOCK;
 
+// fp8 rows: 4 rows per team where that still gives one or two work-groups
+// per compute unit, else 2.  Measured at 16384^2 (cache evicted), 4 rows
+// per team: C=64 L=256 66.0 -> 52.8 us, C=32 L=512 68.4 -> 58.8 us (256
+// and 512 work-groups); slower where it leaves 128 work-groups (C=128
+// L=128: 57.4 -> 67.9 us) or 1024 (C=16 L=1024: 58.6 -> 68.5 us).
+static int fp8_row_block(const Plan& p, int64_t m) {
+  const int64_t wgs4 = (m + int64_t(p.teams_per_wg) * 4 - 1) / (int64_t(p.teams_per_wg) * 4);
+  const int64_t cus = device_cus();
+  return (wgs4 >= cus && wgs4 <= 2 * cus) ? 4 : kRowBlock;
+}
+
 namespace {
 
 // Shared body of dpia_gemv (blas = false) and dpia_gemv_blas.
@@ -293,13 +304,13 @@ dpia_status gemv_impl(const char* name, const dpia_strategy* s, dpia_dtype a_dt,
             p, with_epilogue(GemvFP8Long{static_cast<const uint8_t*>(A),
                                          static_cast<const float*>(x), row_scale,
                                          static_cast<float*>(y)}),
-            m, lda, hs, kRowBlock);
+            m, lda, hs, fp8_row_block(p, m));
       else
         e = launch_gemv<GemvFP8, 16>(
             p, with_epilogue(GemvFP8{static_cast<const uint8_t*>(A),
                                      static_cast<const float*>(x), row_scale,
                                      static_cast<float*>(y)}),
-            m, lda, hs, kRowBlock);
+            m, lda, hs, fp8_row_block(p, m));
       break;
     case DPIA_I32:
       e = launch_gemv<GemvU32, 4>(

@@ -735,3 +735,19 @@ def test_generated_low_precision_gemv_at_full_size_with_paired_rows(fmt):
     want = S.gemv(codes[rows], x, to_plan(s.with_(rows_per_wg=1)), a_format=fmt,
                   scale=None if scale is None else scale[rows])
     assert_same_bits(got[rows], want, f"generated {fmt} 16384^2 vs oracle, sampled rows")
+
+
+@pytest.mark.parametrize("kw", [dict(seq_len=4, local_size=256, order=T_),
+                                dict(seq_len=2, local_size=512, order=T_, wg_combine=SEQ)],
+                         ids=["C4-L256-tree", "C2-L512-seq"])
+def test_fp8_gemv_with_four_rows_per_team(kw):
+    # enough rows that fp8 teams take 4 rows at a time (one or two
+    # work-groups per compute unit), with a ragged last work-group
+    s = dp.Strategy(**kw)
+    teams_per_wg = 256 // (kw["local_size"] // 16)     # 16 fp8 lanes per work-item
+    m, k = 300 * teams_per_wg * 4 + 5, kw["seq_len"] * kw["local_size"]   # 301 work-groups
+    A, x = synthetic.gemv_inputs(m, k, synthetic.SEEDS["precision"])
+    codes, scale = synthetic.quantise_fp8_rows(A)
+    got = gpu_gemv(codes, x, s, a_dtype=dp.FP8_E4M3, scale=scale)
+    assert_same_bits(got, S.gemv(codes, x, to_plan(s), a_format="fp8", scale=scale),
+                     f"fp8 gemv m={m} {kw}")
