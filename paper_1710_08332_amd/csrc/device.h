@@ -343,6 +343,9 @@ __device__ __forceinline__ void lane_folds(const View& view, bool active, int t,
 // only a compiler fence keeps the accesses in that order.  Elements at or
 // past a row's end are read as zeros, which fold as the identity (see
 // lane_folds).
+#ifndef DPIA_STAGE_DEPTH
+#define DPIA_STAGE_DEPTH 1
+#endif
 constexpr int kStageVec = kStage / 4;            // 16-byte parts per row tile
 constexpr int kWave = 64;
 static_assert(kWave % kStageVec == 0, "a load instruction covers whole row tiles");
@@ -396,8 +399,7 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
     }
   }
   const int ntiles = C / kStage;
-  f32x4 regs[NOPS][kStageVec];
-  auto gload = [&](int tile) {
+  auto gload = [&](f32x4 (&regs)[NOPS][kStageVec], int tile) {
 #pragma unroll
     for (int i = 0; i < kStageVec; ++i) {
       const int e = tile * kStage + part * 4;
@@ -405,8 +407,10 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
       for (int o = 0; o < NOPS; ++o) regs[o][i] = load4_masked(rowp[o][i] + e, rowhave[i] - e);
     }
   };
-  gload(0);
-  for (int tile = 0; tile < ntiles; ++tile) {
+  // tile `regs` -> this wavefront's LDS region, then `next` (the loads of a
+  // later tile, in flight while this one is folded), then every lane folds
+  // its row's elements of the tile in increasing index
+  auto stage_fold = [&](const f32x4 (&regs)[NOPS][kStageVec], auto&& next) {
 #pragma unroll
     for (int i = 0; i < kStageVec; ++i) {
       const int r = i * kStageRowsPerLoad + lane / kStageVec;
@@ -415,7 +419,7 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
         *reinterpret_cast<f32x4*>(stage + (o * kWave + r) * kStageRow + part * 4) = regs[o][i];
     }
     wave_lds_order();
-    if (tile + 1 < ntiles) gload(tile + 1);   // in flight while this tile is folded
+    next();
     if (active) {
 #pragma unroll
       for (int j = 0; j < kStageVec; ++j) {
@@ -428,7 +432,23 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
       }
     }
     wave_lds_order();
+  };
+#if DPIA_STAGE_DEPTH >= 2
+  // two tiles in flight: tiles alternate between two register sets
+  f32x4 ra[NOPS][kStageVec], rb[NOPS][kStageVec];
+  gload(ra, 0);
+  if (ntiles > 1) gload(rb, 1);
+  for (int tile = 0; tile < ntiles; tile += 2) {
+    stage_fold(ra, [&] { if (tile + 2 < ntiles) gload(ra, tile + 2); });
+    if (tile + 1 < ntiles)
+      stage_fold(rb, [&] { if (tile + 3 < ntiles) gload(rb, tile + 3); });
   }
+#else
+  f32x4 regs[NOPS][kStageVec];
+  gload(regs, 0);
+  for (int tile = 0; tile < ntiles; ++tile)
+    stage_fold(regs, [&] { if (tile + 1 < ntiles) gload(regs, tile + 1); });
+#endif
 }
 
 // `stage`: this wavefront's LDS staging region (contiguous order, stageable
