@@ -451,6 +451,118 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
 #endif
 }
 
+// The contiguous order staged through LDS for rows of 1- or 2-byte codes
+// (gemv with bf16 / fp8 A; View::kStageableCodes): as contiguous_staged,
+// with the codes' row tiles (kStage codes, 2 or 4 16-byte parts) and x's
+// row tiles (kStage binary32, 8 parts) loaded by their own work-item
+// layouts.  Each lane decodes its kStage codes and folds them with its x
+// values in increasing index.  Parts at or past a row's end hold zero
+// codes and zero x, which fold as the identity.
+template <class E>
+__device__ __forceinline__ u32x4 load_codes_masked(const E* p, int rem) {
+  constexpr int N = 16 / static_cast<int>(sizeof(E));
+  if (rem >= N) return ld<false>(reinterpret_cast<const u32x4*>(p));
+  E c[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) c[i] = (i < rem) ? p[i] : E(0);
+  u32x4 r;
+  __builtin_memcpy(&r, c, 16);
+  return r;
+}
+
+template <class Op, class View>
+__device__ __forceinline__ void contiguous_staged_codes(const View& view, bool active, int t,
+                                                        int C, int limit, typename Op::T& acc,
+                                                        float* stage) {
+  using E = typename View::Code;
+  constexpr int ES = static_cast<int>(sizeof(E));
+  constexpr int PA = kStage * ES / 16;          // 16-byte parts of a code row tile
+  constexpr int PX = kStage / 4;                // 16-byte parts of an x row tile
+  constexpr int RA = kWave / PA, RX = kWave / PX;
+  constexpr int SA = (PA + 1) * 16, SX = (PX + 1) * 16;   // row strides: odd 16-byte units
+  static_assert(PA >= 1 && kWave % PA == 0, "whole code row tiles per load instruction");
+  unsigned char* la = reinterpret_cast<unsigned char*>(stage);
+  unsigned char* lx = la + kWave * SA;
+  acc = Op::Arith::zero();
+  const int lane = threadIdx.x & (kWave - 1);
+  int have = limit - t * C;                     // elements of this lane's row that exist
+  have = active ? (have < 0 ? 0 : (have > C ? C : have)) : 0;
+  const int pa = lane % PA, px = lane % PX;
+  const E* rowa[PA];
+  const float* rowx[PX];
+  int hava[PA], havx[PX];
+  const unsigned long long mya =
+      reinterpret_cast<unsigned long long>(view.a + static_cast<int64_t>(t) * C);
+  const unsigned long long myx =
+      reinterpret_cast<unsigned long long>(view.x + static_cast<int64_t>(t) * C);
+#pragma unroll
+  for (int i = 0; i < PA; ++i) {
+    const int r = i * RA + lane / PA;
+    hava[i] = __shfl(have, r, kWave);
+    rowa[i] = reinterpret_cast<const E*>(__shfl(mya, r, kWave));
+  }
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    const int r = i * RX + lane / PX;
+    havx[i] = __shfl(have, r, kWave);
+    rowx[i] = reinterpret_cast<const float*>(__shfl(myx, r, kWave));
+  }
+  const int ntiles = C / kStage;
+  u32x4 ca[PA];
+  f32x4 cx[PX];
+  auto gload = [&](int tile) {
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int e = tile * kStage + pa * (16 / ES);
+      ca[i] = load_codes_masked(rowa[i] + e, hava[i] - e);
+    }
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int e = tile * kStage + px * 4;
+      cx[i] = load4_masked(rowx[i] + e, havx[i] - e);
+    }
+  };
+  gload(0);
+  for (int tile = 0; tile < ntiles; ++tile) {
+#pragma unroll
+    for (int i = 0; i < PA; ++i)
+      *reinterpret_cast<u32x4*>(la + (i * RA + lane / PA) * SA + pa * 16) = ca[i];
+#pragma unroll
+    for (int i = 0; i < PX; ++i)
+      *reinterpret_cast<f32x4*>(lx + (i * RX + lane / PX) * SX + px * 16) = cx[i];
+    wave_lds_order();
+    if (tile + 1 < ntiles) gload(tile + 1);   // in flight while this tile is folded
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < PA; ++j) {
+        E c[16 / ES];
+        const u32x4 u = *reinterpret_cast<const u32x4*>(la + lane * SA + j * 16);
+        __builtin_memcpy(c, &u, 16);
+        float f[16 / ES];
+        Op::template decode<16 / ES>(c, f);
+#pragma unroll
+        for (int q = 0; q < 16 / ES / 4; ++q) {
+          const f32x4 xv =
+              *reinterpret_cast<const f32x4*>(lx + lane * SX + (j * (16 / ES / 4) + q) * 16);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc = Op::step(typename Op::Term{f[4 * q + i], xv[i]}, acc);
+        }
+      }
+    }
+    wave_lds_order();
+  }
+}
+
+template <class V, class = void>
+struct StageableCodes {
+  static constexpr bool value = false;
+};
+template <class V>
+struct StageableCodes<V, decltype(void(V::kStageableCodes))> {
+  static constexpr bool value = V::kStageableCodes;
+};
+
 // `stage`: this wavefront's LDS staging region (contiguous order, stageable
 // views) or nullptr for direct loads.  The choice is uniform per launch.
 template <class Op, int ORDER, int NV, int COMBINE, class View>
@@ -463,6 +575,11 @@ __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool act
   if constexpr (ORDER == kContiguous && View::kStageable) {
     if (stage != nullptr) {
       contiguous_staged<Op, 1>(view, active, t, C, limit, acc, stage);
+      return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
+    }
+  } else if constexpr (ORDER == kContiguous && StageableCodes<View>::value) {
+    if (stage != nullptr) {
+      contiguous_staged_codes<Op>(view, active, t, C, limit, acc[0], stage);
       return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
     }
   }

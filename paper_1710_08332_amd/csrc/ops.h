@@ -194,6 +194,9 @@ struct GemvF32Acc {
   static constexpr bool kStreamA = !kF32;
   struct View {
     static constexpr bool kStageable = std::is_same<E, float>::value;
+    // 1- and 2-byte codes: staged by contiguous_staged_codes
+    static constexpr bool kStageableCodes = !std::is_same<E, float>::value;
+    using Code = E;
     static constexpr int kOps = 2;
     const E* a;
     const float* x;

@@ -224,6 +224,11 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   q.stage = q.order == DPIA_ORDER_CONTIGUOUS && dt == DPIA_F32 && q.nv == 4 &&
             (V == 1 || V == 4) && (q.C * V) % kStage == 0 && q.wg_threads <= 256 &&
             q.wg_threads % 64 == 0;
+  // gemv rows of bf16 / fp8 codes: the codes' and x's row tiles, each row
+  // stride an odd number of 16-byte units, fit the same region
+  if (op == DPIA_OP_GEMV && (dt == DPIA_BF16 || dt == DPIA_FP8_E4M3))
+    q.stage = q.order == DPIA_ORDER_CONTIGUOUS && q.C % kStage == 0 &&
+              q.wg_threads <= 256 && q.wg_threads % 64 == 0;
   q.stage_off = 0;
   if (q.stage) {
     q.stage_off = round_up(lds, 16);

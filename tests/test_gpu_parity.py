@@ -751,3 +751,33 @@ def test_fp8_gemv_with_four_rows_per_team(kw):
     got = gpu_gemv(codes, x, s, a_dtype=dp.FP8_E4M3, scale=scale)
     assert_same_bits(got, S.gemv(codes, x, to_plan(s), a_format="fp8", scale=scale),
                      f"fp8 gemv m={m} {kw}")
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("kw", [dict(seq_len=32, local_size=64, order=C_),
+                                dict(seq_len=64, local_size=32, order=C_, wg_combine=SEQ),
+                                dict(seq_len=32, local_size=32, order=C_, row_parts=2)], ids=str)
+@pytest.mark.parametrize("k", [2048, 2047, 1001, 37])
+def test_contiguous_low_precision_gemv_staged_and_ragged(fmt, kw, k):
+    # contiguous bf16 / fp8 rows staged through LDS (C a multiple of 32),
+    # rows ending inside a 16-byte unit of codes; lda keeps rows aligned
+    import torch
+    s = dp.Strategy(**kw)
+    if k > s.seq_len * s.local_size * s.row_parts:
+        pytest.skip("row longer than the strategy")
+    m = 4 * 3 + 1
+    lda = -(-k // 16) * 16
+    A, x = synthetic.gemv_inputs(m, lda, 31)
+    if fmt == "bf16":
+        codes, scale, adt = synthetic.quantise_bf16(A), None, dp.BF16
+        At = torch.from_numpy(np.ascontiguousarray(codes.view(np.int16))).cuda()[:, :k]
+    else:
+        (codes, scale), adt = synthetic.quantise_fp8_rows(A), dp.FP8_E4M3
+        At = torch.from_numpy(np.ascontiguousarray(codes)).cuda()[:, :k]
+    xt = torch.from_numpy(np.ascontiguousarray(x[:k])).cuda()
+    st = torch.from_numpy(scale).cuda() if scale is not None else None
+    y = dp.gemv(At, xt, s, row_scale=st, a_dtype=adt)
+    torch.cuda.synchronize()
+    want = S.gemv(np.ascontiguousarray(codes[:, :k]), x[:k], to_plan(s), a_format=fmt,
+                  scale=scale)
+    assert_same_bits(y.cpu().numpy(), want, f"{fmt} contiguous gemv k={k} {kw}")
