@@ -74,6 +74,11 @@ struct DotU32 {
 struct DotF32Deep : DotF32 {
   static constexpr int kBatchElems = 2 * DPIA_BATCH_ELEMS;
 };
+// Four times the batch, for strategies with too few wavefronts to keep the
+// memory system busy otherwise (fewer than two per compute unit).
+struct DotF32Deeper : DotF32 {
+  static constexpr int kBatchElems = 4 * DPIA_BATCH_ELEMS;
+};
 
 // xs with lane operator lam x a. abs x + a.  One operand: twice the dot's
 // batch keeps the same bytes in flight (measured at 2^26, C=256 L=1024:

@@ -198,10 +198,17 @@ hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, vo
   return launch_fold<Op, FINAL>(p.values, ws, out, out_f64, stream);
 }
 
+#ifndef DPIA_DEEPER_DOT
+#define DPIA_DEEPER_DOT 1
+#endif
+
 // Plain binary32 dots whose strided lanes form teams narrower than 1024
-// lanes use the deeper load batch (DotF32Deep).
-inline bool deep_dot(const Plan& p) {
-  return p.order == DPIA_ORDER_STRIDED && p.L < 1024;
+// lanes use a deeper load batch: DotF32Deep, or DotF32Deeper when the whole
+// launch has fewer than two wavefronts per compute unit.
+inline int dot_depth(const Plan& p) {
+  if (p.order != DPIA_ORDER_STRIDED || p.L >= 1024) return 0;
+  const int64_t waves = p.items * ((p.team + 63) / 64);
+  return (DPIA_DEEPER_DOT && waves < 2 * static_cast<int64_t>(device_cus())) ? 2 : 1;
 }
 
 // Calls f(op, final-kind constant) for the operation and accumulation of a plan.
@@ -222,7 +229,11 @@ hipError_t with_reduction(const Plan& p, const void* x, const void* y, F&& f) {
     if (p.final_f64) return f(op, ic<kFinalSum2_64>{});
     return f(op, ic<kFinalSum2_32>{});
   }
-  if (deep_dot(p))
+  const int depth = dot_depth(p);
+  if (depth == 2)
+    return f(DotF32Deeper{{static_cast<const float*>(x), static_cast<const float*>(y)}},
+             ic<kFinalPlain>{});
+  if (depth == 1)
     return f(DotF32Deep{{static_cast<const float*>(x), static_cast<const float*>(y)}},
              ic<kFinalPlain>{});
   return f(DotF32{static_cast<const float*>(x), static_cast<const float*>(y)},
@@ -286,8 +297,12 @@ extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n
     if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
-    e = deep_dot(p) ? launch_reduce<DotF32Deep, kFinalPlain>(p, DotF32Deep{{xf, yf}}, out, 0, ws, hs)
-                    : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, ws, hs);
+    const int depth = dot_depth(p);
+    e = depth == 2 ? launch_reduce<DotF32Deeper, kFinalPlain>(p, DotF32Deeper{{xf, yf}}, out, 0,
+                                                               ws, hs)
+        : depth == 1 ? launch_reduce<DotF32Deep, kFinalPlain>(p, DotF32Deep{{xf, yf}}, out, 0,
+                                                              ws, hs)
+                     : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, ws, hs);
   }
   if (e != hipSuccess) return hip_fail(e, "dpia_dot launch");
   clear_detail();
