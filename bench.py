@@ -656,6 +656,37 @@ def workload_generated(args):
         g.close()
 
 
+def read_ceiling(dev, nbytes, reps=10):
+    """The measured read-stream ceiling: the best bandwidth of the plain read
+    kernel (every byte loaded once, 16-byte non-temporal loads) over a few
+    grid sizes, on a buffer as large as the dot's inputs, launched back to
+    back like the dot and timed with the same events."""
+    import torch
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    sink = torch.empty(cus * 16, dtype=torch.int32, device=dev)
+    best = None
+    for per_cu in (1, 2, 4, 8, 16):
+        grid = cus * per_cu
+        for _ in range(2):
+            dp.read_stream(buf, grid, sink=sink)
+        torch.cuda.synchronize()
+        ev = TimingEvents(reps)
+        for i in range(reps):
+            ev.record(i, 0)
+            dp.read_stream(buf, grid, sink=sink)
+            ev.record(i, 1)
+        torch.cuda.synchronize()
+        us = float(np.mean([ev.elapsed_ms(i) for i in range(reps)])) * 1e3
+        ev.close()
+        if best is None or us < best[0]:
+            best = (us, grid)
+    del buf
+    return {"kernel": "read_stream_kernel<8> (16-byte non-temporal loads, XOR of every word)",
+            "bytes_per_launch": nbytes, "gbs": round(nbytes / best[0] / 1e3, 3),
+            "avg_kernel_us": round(best[0], 3), "grid": best[1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -731,6 +762,8 @@ def main():
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
     achieved = CHUNK_KERNEL_BYTES / dot_avg_s / 1e9
+    ceiling = read_ceiling(dev, 2 * N_DOT * 4)
+    ceiling["frac"] = round(achieved / ceiling["gbs"], 4)
     rec = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -762,6 +795,7 @@ def main():
             "traffic": measured_traffic(),
             "avg_kernel_us": round(dot_avg_s * 1e6, 3),
             "timed_with": timer_kind + " around each first-pass launch",
+            "read_ceiling": ceiling,
         },
     }
     if not args.no_cpu_baseline:

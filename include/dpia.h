@@ -229,6 +229,21 @@ dpia_status dpia_scal(const dpia_strategy* s, dpia_dtype dt, int64_t n, float al
                       const void* x, void* y, dpia_stream_t stream);
 
 /*
+ * Measurement aid, not an operation of the paper: the read-bandwidth
+ * ceiling that the reductions' throughput is set against (Sec. 7.1 reports
+ * bandwidth).  Reads the `bytes` bytes at device address x once, with
+ * 16-byte non-temporal loads from `grid` work-groups of 256 threads, and
+ * stores in sink[b] (device memory, `grid` uint32_t) the XOR of the 32-bit
+ * words work-group b read: the XOR of sink[0 .. grid) is that of all of x.
+ * x 16-byte aligned and bytes a non-negative multiple of 16, grid in
+ * [1, 65536] (DPIA_ERR_SHAPE); DPIA_ERR_NULL for a NULL sink, or a NULL x
+ * with bytes > 0.  Asynchronous; nothing is launched on an error or when
+ * bytes == 0 (sink is then left as it is).
+ */
+dpia_status dpia_read_stream(const void* x, int64_t bytes, int32_t grid, uint32_t* sink,
+                             dpia_stream_t stream);
+
+/*
  * The two stages of a dot or asum strategy as separate calls.  dpia_chunks
  * evaluates the mapWorkgroup level only: chunks[g] = value of chunk g, i.e.
  * the work-group combine of its L lane folds (the OpenCL dot kernel of

@@ -177,6 +177,20 @@ def scal(alpha: float, x, s: Strategy, y=None, stream=None):
     return y
 
 
+def read_stream(x, grid: int, sink=None, stream=None):
+    """Reads every byte of the device tensor x once (the read-bandwidth
+    ceiling kernel) with ``grid`` work-groups; work-group b stores the XOR of
+    the 32-bit words it read in sink[b] (``grid`` int32 values on the
+    device).  Returns sink."""
+    if sink is None:
+        sink = _torch().empty(grid, dtype=_torch().int32, device=x.device)
+    if sink.numel() < grid:
+        raise ValueError("sink needs one int32 per work-group")
+    _lib.check(_lib.lib().dpia_read_stream(_dev(x), x.numel() * x.element_size(), int(grid),
+                                           _dev(sink), _stream(stream)), "dpia_read_stream")
+    return sink
+
+
 def num_chunks(s: Strategy, n: int) -> int:
     """G: chunks of a length-n dot / asum (the last one may be partial)."""
     w = s.seq_len * s.local_size * max(1, s.vec_width)

@@ -25,7 +25,7 @@ PLAIN, KAHAN, SUM2 = 0, 1, 2
 
 EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
            "dpia_scal", "dpia_chunks", "dpia_module_load", "dpia_module_launch",
-           "dpia_module_unload",
+           "dpia_module_unload", "dpia_read_stream",
            "dpia_fold", "dpia_batch_plan_create", "dpia_batch_workspace_bytes",
            "dpia_batch_upload", "dpia_batch_run", "dpia_batch_plan_destroy", "dpia_status_str",
            "dpia_last_error_detail", "dpia_abi_version")
@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         L.dpia_module_launch.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.POINTER(vp), ctypes.c_int32, vp]
         L.dpia_module_unload.argtypes = [vp]
+        L.dpia_read_stream.argtypes = [vp, i64, ctypes.c_int32, vp, vp]
         L.dpia_gemv_blas.argtypes = [sp, ctypes.c_int, i64, i64, i64, ctypes.c_float, vp, vp, vp,
                                      ctypes.c_float, vp, vp]
         L.dpia_chunks.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, u64, vp]
@@ -88,7 +89,7 @@ def lib() -> ctypes.CDLL:
         for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
                   "dpia_scal", "dpia_chunks", "dpia_fold", "dpia_batch_plan_create",
                   "dpia_batch_upload", "dpia_batch_run", "dpia_module_load",
-                  "dpia_module_launch", "dpia_module_unload"):
+                  "dpia_module_launch", "dpia_module_unload", "dpia_read_stream"):
             getattr(L, f).restype = ctypes.c_int
         L.dpia_status_str.argtypes = [ctypes.c_int]
         L.dpia_status_str.restype = ctypes.c_char_p

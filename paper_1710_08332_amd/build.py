@@ -24,7 +24,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdpia.so")
 
-HIP_SOURCES = ["reduce.hip", "gemv.hip", "batch.hip", "map.hip", "module.hip"]
+HIP_SOURCES = ["reduce.hip", "gemv.hip", "batch.hip", "map.hip", "module.hip", "stream.hip"]
 CPP_SOURCES = ["plan.cpp"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

@@ -250,6 +250,18 @@ def test_scal_validates_before_launching():
     assert L.dpia_scal(ctypes.byref(ks), dp.F32, 4096, 2.0, P, P2, None) == _lib.ERR_STRATEGY
 
 
+def test_read_stream_validates_before_launching():
+    L = _lib.lib()
+    assert L.dpia_read_stream(P, 4100, 8, P2, None) == _lib.ERR_SHAPE        # not 16-byte units
+    assert L.dpia_read_stream(P, -16, 8, P2, None) == _lib.ERR_SHAPE
+    assert L.dpia_read_stream(ctypes.c_void_p(0x7000_0008), 4096, 8, P2, None) == _lib.ERR_SHAPE
+    assert L.dpia_read_stream(P, 4096, 0, P2, None) == _lib.ERR_SHAPE
+    assert L.dpia_read_stream(P, 4096, 65537, P2, None) == _lib.ERR_SHAPE
+    assert L.dpia_read_stream(P, 4096, 8, None, None) == _lib.ERR_NULL
+    assert L.dpia_read_stream(None, 4096, 8, P2, None) == _lib.ERR_NULL
+    assert L.dpia_read_stream(None, 0, 8, P2, None) == _lib.OK                # nothing to read
+
+
 def test_gemv_blas_validates_before_launching():
     L = _lib.lib()
     cs = dp.Strategy(seq_len=16, local_size=16).c()
