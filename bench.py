@@ -260,9 +260,14 @@ def workload_precision(args):
         med, p10, p90 = time_us(lambda: dp.gemv(At, xvt, s, y=y, row_scale=sct, a_dtype=dt),
                                 reps=args.steps, between=evict)
         results[name] = y.cpu().numpy()
+        # the read-stream ceiling over the matrix's own bytes, timed the same way
+        ceil_us, _ = evicted_read_ceiling(At, evict)
+        a_bytes = At.numel() * At.element_size()
         _line(workload="precision", op=name, m=m, k=k, strategy=strategy_text(s, gemv=True),
               us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
               pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1), algorithmic_bytes=nbytes,
+              read_ceiling_gbs=_gbs(a_bytes, ceil_us),
+              pct_of_read_ceiling=round(100 * (nbytes / med) / (a_bytes / ceil_us), 1),
               tuned_over=[f"C={r['strategy']['seq_len']} L={r['strategy']['local_size']}: "
                           f"{r['us']:.1f} us" for r in table])
         del At
@@ -494,6 +499,12 @@ def workload_scal(args):
         At, xvt = torch.from_numpy(A).cuda(), torch.from_numpy(xv).cuda()
         y0 = torch.from_numpy(synthetic.dot_inputs(mk, synthetic.SEEDS["scale"] + 1)[0]).cuda()
         yb = torch.empty_like(y0)
+        # the read-stream ceiling on A itself, timed the same way (cache evicted)
+        ceil_us, ceil_grid = evicted_read_ceiling(At, evict)
+        a_bytes = 4 * mk * mk
+        _line(workload="scal", op="read_ceiling", bytes=a_bytes, grid=ceil_grid,
+              us=round(ceil_us, 2), gbs=_gbs(a_bytes, ceil_us),
+              pct_peak=round(100 * a_bytes / ceil_us / 1e3 / PEAK_GBPS, 1))
         for form, a_, b_, nbytes in (("y = A x", 1.0, 0.0, 4 * (mk * mk + 2 * mk)),
                                      ("y := 1.3 A x - 2.1 y", 1.3, -2.1, 4 * (mk * mk + 3 * mk))):
             def run():
@@ -506,7 +517,8 @@ def workload_scal(args):
             _line(workload="scal", op="gemv_blas" if b_ else "gemv", m=mk, k=mk, form=form,
                   strategy=strategy_text(gs, gemv=True), us=round(med, 2), p10=round(p10, 2),
                   p90=round(p90, 2), gbs=_gbs(nbytes, med),
-                  pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1))
+                  pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1),
+                  pct_of_read_ceiling=round(100 * (nbytes / med) / (a_bytes / ceil_us), 1))
             if mk == 8192:
                 yb.copy_(y0)
                 run()
@@ -685,6 +697,17 @@ def read_ceiling(dev, nbytes, reps=10):
     return {"kernel": "read_stream_kernel<8> (16-byte non-temporal loads, XOR of every word)",
             "bytes_per_launch": nbytes, "gbs": round(nbytes / best[0] / 1e3, 3),
             "avg_kernel_us": round(best[0], 3), "grid": best[1]}
+
+
+def evicted_read_ceiling(t, evict, reps=20):
+    """(median µs, grid) of the best grid of the read-stream kernel over the
+    bytes of device tensor t, with ``evict`` run before every timed call."""
+    import torch
+    from paper_1710_08332_amd.autotune import time_us
+    cus = torch.cuda.get_device_properties(t.device).multi_processor_count
+    sink = torch.empty(cus * 16, dtype=torch.int32, device=t.device)
+    return min((time_us(lambda: dp.read_stream(t, g, sink=sink), reps=reps, between=evict)[0], g)
+               for g in (cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus))
 
 
 def main():
