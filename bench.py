@@ -478,6 +478,11 @@ def workload_scal(args):
                   for C, L, o in ((16, 1024, dp.STRIDED), (64, 1024, dp.STRIDED),
                                   (256, 1024, dp.STRIDED), (16, 256, dp.CONTIGUOUS),
                                   (64, 256, dp.CONTIGUOUS))]
+    # the copy ceiling: the runtime's device-to-device copy of the same bytes
+    # (read 256 MiB, write 256 MiB), timed the same way
+    cp_us = time_us(lambda: yt.copy_(xt), reps=40, between=evict)[0]
+    _line(workload="scal", op="copy_ceiling", n=n, us=round(cp_us, 2), gbs=_gbs(8 * n, cp_us),
+          pct_peak=round(100 * 8 * n / cp_us / 1e3 / PEAK_GBPS, 1))
     for s in strategies:
         for place in ("out", "in"):
             dst = yt if place == "out" else xt
@@ -485,7 +490,8 @@ def workload_scal(args):
                                     between=evict)
             _line(workload="scal", n=n, strategy=strategy_text(s), place=place,
                   us=round(med, 2), p10=round(p10, 2), p90=round(p90, 2),
-                  gbs=_gbs(8 * n, med), pct_peak=round(100 * 8 * n / med / 1e3 / PEAK_GBPS, 1))
+                  gbs=_gbs(8 * n, med), pct_peak=round(100 * 8 * n / med / 1e3 / PEAK_GBPS, 1),
+                  pct_of_copy=round(100 * cp_us / med, 1))
     xt.copy_(torch.from_numpy(x))
     dp.scal(float(alpha), xt, strategies[0], y=yt)
     torch.cuda.synchronize()
