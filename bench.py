@@ -705,6 +705,41 @@ def read_ceiling(dev, nbytes, reps=10):
             "avg_kernel_us": round(best[0], 3), "grid": best[1]}
 
 
+def graph_replay(step, outputs, steps_per_graph=20, replays=10):
+    """The step replayed from a HIP graph: ``steps_per_graph`` steps captured
+    once, each replay timed with events (no host launch cost inside).  After
+    every replay the ``outputs`` tensors are compared bit for bit with their
+    eager values.  Returns (median µs per step, all replays equal)."""
+    import torch
+    eager = [o.clone() for o in outputs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        step()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gr, stream=side):
+            for _ in range(steps_per_graph):
+                step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ev = TimingEvents(replays)
+    same = True
+    for i in range(replays):
+        for o in outputs:
+            o.fill_(0)                  # eager work between replays
+        ev.record(i, 0)
+        gr.replay()
+        ev.record(i, 1)
+        torch.cuda.synchronize()
+        same &= all(torch.equal(o.view(torch.int32), e.view(torch.int32))
+                    for o, e in zip(outputs, eager))
+    per = sorted(ev.elapsed_ms(i) * 1e3 / steps_per_graph for i in range(replays))
+    ev.close()
+    del gr
+    return per[len(per) // 2], bool(same)
+
+
 def evicted_read_ceiling(t, evict, reps=20):
     """(median µs, grid) of the best grid of the read-stream kernel over the
     bytes of device tensor t, with ``evict`` run before every timed call."""
@@ -791,6 +826,7 @@ def main():
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
     achieved = CHUNK_KERNEL_BYTES / dot_avg_s / 1e9
+    graph_us, graph_same = graph_replay(step, [out, yg])
     ceiling = read_ceiling(dev, 2 * N_DOT * 4)
     ceiling["frac"] = round(achieved / ceiling["gbs"], 4)
     rec = {
@@ -813,6 +849,9 @@ def main():
             "percent_of_hbm_peak": round(100 * value / PEAK_GBPS, 2),
             "parallelism": "single GPU",
         },
+        "graph_replay": {"us_per_step": round(graph_us, 2),
+                         "gbs": round((DOT_BYTES + GEMV_BYTES) / graph_us / 1e3, 1),
+                         "steps_per_graph": 20, "bit_exact_vs_eager": graph_same},
         "roofline": {
             "bound": "hbm",
             "kernel": "reduce_kernel<DotF32, strided, 4, tree> (dot first pass)",
