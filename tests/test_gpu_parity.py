@@ -447,6 +447,60 @@ def test_batched_run_in_a_graph_replays_exactly():
 
 
 
+def test_single_calls_in_a_graph_replay_exactly():
+    # dot (2-pass, 1-pass with its arrival counter, Kahan to binary64), asum
+    # and gemv captured in one graph: every replay reproduces the eager bits
+    import torch
+    n = (1 << 20) + 77
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    A, xv = synthetic.gemv_inputs(96, 3000, synthetic.SEEDS["scale"])
+    xt, yt, At, xvt = cuda(x), cuda(y), cuda(A), cuda(xv)
+    calls = []
+    for s, kind in ((dp.Strategy(seq_len=256, local_size=16, order=C_, passes=2), "dot"),
+                    (dp.Strategy(seq_len=64, local_size=256, order=T_, passes=1), "dot"),
+                    (dp.Strategy(seq_len=32, local_size=128, order=T_, passes=1, accum=dp.KAHAN,
+                                 final_f64=1), "dot"),
+                    (dp.Strategy(seq_len=128, local_size=64, order=T_, passes=2), "asum"),
+                    (dp.Strategy(seq_len=64, local_size=64, order=T_, rows_per_wg=2), "gemv")):
+        if kind == "gemv":
+            out = torch.empty(96, dtype=torch.float32, device="cuda")
+            calls.append((lambda s=s, out=out: dp.gemv(At, xvt, s, y=out), out))
+            continue
+        op = dp.OP_DOT if kind == "dot" else dp.OP_ASUM
+        # compensated strategies take whole chunks only: a 2^20 prefix
+        xs, ys = (xt[:1 << 20], yt[:1 << 20]) if s.accum != dp.PLAIN else (xt, yt)
+        ws = dp.workspace(s, op, dp.F32, 0, xs.numel())
+        od = torch.float64 if s.final_f64 else torch.float32
+        out = torch.empty(1, dtype=od, device="cuda")
+        if kind == "dot":
+            calls.append((lambda s=s, out=out, ws=ws, xs=xs, ys=ys:
+                          dp.dot(xs, ys, s, out=out, ws=ws), out))
+        else:
+            calls.append((lambda s=s, out=out, ws=ws: dp.asum(xt, s, out=out, ws=ws), out))
+    for fn, _ in calls:
+        fn()
+    torch.cuda.synchronize()
+    eager = [o.clone() for _, o in calls]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for fn, _ in calls:
+                fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for _, o in calls:
+            o.fill_(float(rep) - 5.0)                 # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, ((_, o), e) in enumerate(zip(calls, eager)):
+            assert torch.equal(o.cpu().view(torch.uint8), e.cpu().view(torch.uint8)), \
+                f"replay {rep} call {i}"
+
+
 @pytest.mark.parametrize("kw", [dict(seq_len=16, local_size=256, order=T_),
                                 dict(seq_len=64, local_size=64, order=C_),     # staged, tile 64
                                 dict(seq_len=96, local_size=128, order=C_),    # staged, tile 32
