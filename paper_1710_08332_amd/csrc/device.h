@@ -371,6 +371,18 @@ __device__ __forceinline__ void wave_lds_order() {
 // lane whose row holds C vectors (C * VEC elements); element e of the row
 // belongs to component e % VEC, and each component folds its elements in
 // increasing index (kStage is a multiple of VEC).
+// Tiles a staged fold keeps in flight: Op::kStageDepth where the operation
+// declares it (launches with fewer wavefronts than compute units), else
+// DPIA_STAGE_DEPTH.
+template <class Op, class = void>
+struct StageDepth {
+  static constexpr int value = DPIA_STAGE_DEPTH;
+};
+template <class Op>
+struct StageDepth<Op, decltype(void(Op::kStageDepth))> {
+  static constexpr int value = Op::kStageDepth;
+};
+
 template <class Op, int VEC = 1, class View>
 __device__ __forceinline__ void contiguous_staged(const View& view, bool active, int t, int C,
                                                   int limit, typename Op::T (&acc)[VEC],
@@ -433,22 +445,22 @@ __device__ __forceinline__ void contiguous_staged(const View& view, bool active,
     }
     wave_lds_order();
   };
-#if DPIA_STAGE_DEPTH >= 2
-  // two tiles in flight: tiles alternate between two register sets
-  f32x4 ra[NOPS][kStageVec], rb[NOPS][kStageVec];
-  gload(ra, 0);
-  if (ntiles > 1) gload(rb, 1);
-  for (int tile = 0; tile < ntiles; tile += 2) {
-    stage_fold(ra, [&] { if (tile + 2 < ntiles) gload(ra, tile + 2); });
-    if (tile + 1 < ntiles)
-      stage_fold(rb, [&] { if (tile + 3 < ntiles) gload(rb, tile + 3); });
+  if constexpr (StageDepth<Op>::value >= 2) {
+    // two tiles in flight: tiles alternate between two register sets
+    f32x4 ra[NOPS][kStageVec], rb[NOPS][kStageVec];
+    gload(ra, 0);
+    if (ntiles > 1) gload(rb, 1);
+    for (int tile = 0; tile < ntiles; tile += 2) {
+      stage_fold(ra, [&] { if (tile + 2 < ntiles) gload(ra, tile + 2); });
+      if (tile + 1 < ntiles)
+        stage_fold(rb, [&] { if (tile + 3 < ntiles) gload(rb, tile + 3); });
+    }
+  } else {
+    f32x4 regs[NOPS][kStageVec];
+    gload(regs, 0);
+    for (int tile = 0; tile < ntiles; ++tile)
+      stage_fold(regs, [&] { if (tile + 1 < ntiles) gload(regs, tile + 1); });
   }
-#else
-  f32x4 regs[NOPS][kStageVec];
-  gload(regs, 0);
-  for (int tile = 0; tile < ntiles; ++tile)
-    stage_fold(regs, [&] { if (tile + 1 < ntiles) gload(regs, tile + 1); });
-#endif
 }
 
 // The contiguous order staged through LDS for rows of 1- or 2-byte codes

@@ -75,9 +75,11 @@ struct DotF32Deep : DotF32 {
   static constexpr int kBatchElems = 2 * DPIA_BATCH_ELEMS;
 };
 // Four times the batch, for strategies with too few wavefronts to keep the
-// memory system busy otherwise (fewer than two per compute unit).
+// memory system busy otherwise (fewer than two per compute unit); staged
+// contiguous folds keep two tiles in flight.
 struct DotF32Deeper : DotF32 {
   static constexpr int kBatchElems = 4 * DPIA_BATCH_ELEMS;
+  static constexpr int kStageDepth = 2;
 };
 
 // xs with lane operator lam x a. abs x + a.  One operand: twice the dot's
