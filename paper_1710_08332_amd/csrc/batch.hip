@@ -163,6 +163,9 @@ extern "C" dpia_status dpia_batch_plan_create(const dpia_instance* inst, int32_t
   for (int32_t i = 0; i < count; ++i) {
     const dpia_instance& d = inst[i];
     const std::string where = "instance " + std::to_string(i) + ": ";
+    if (d.op != DPIA_OP_DOT && d.op != DPIA_OP_ASUM && d.op != DPIA_OP_GEMV)
+      return bad(DPIA_ERR_STRATEGY, where + "batched instances are dot, asum or gemv");
+    if (d.reserved != 0) return bad(DPIA_ERR_STRATEGY, where + "reserved must be 0");
     if (d.strategy >= static_cast<uint32_t>(nstrat))
       return bad(DPIA_ERR_STRATEGY, where + "strategy index out of range");
     if (d.dtype != DPIA_F32) return bad(DPIA_ERR_DTYPE, where + "batched instances are F32");

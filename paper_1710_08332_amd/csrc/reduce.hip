@@ -205,12 +205,15 @@ hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, vo
 // Plain binary32 dots whose strided lanes form teams narrower than 1024
 // lanes use a deeper load batch: DotF32Deep, or DotF32Deeper when the whole
 // launch has fewer than two wavefronts per compute unit.  Contiguous dots
-// whose launch has fewer wavefronts than compute units use DotF32Deeper
-// too (two staged tiles in flight).
+// staged through LDS whose launch has fewer wavefronts than compute units
+// use DotF32Deeper too (two staged tiles in flight); unstaged contiguous
+// dots keep the default batch (a deeper one would need 128 registers of
+// loads in flight).
 inline int dot_depth(const Plan& p) {
   const int64_t waves = p.items * ((p.team + 63) / 64);
   const int64_t cus = device_cus();
-  if (p.order != DPIA_ORDER_STRIDED) return (DPIA_DEEPER_DOT && waves < cus) ? 2 : 0;
+  if (p.order != DPIA_ORDER_STRIDED)
+    return (DPIA_DEEPER_DOT && p.stage && waves < cus) ? 2 : 0;
   if (p.L >= 1024) return 0;
   return (DPIA_DEEPER_DOT && waves < 2 * cus) ? 2 : 1;
 }

@@ -186,9 +186,9 @@ def test_stage_entry_points_validate_before_launching():
     assert L.dpia_fold(ctypes.byref(cs), dp.OP_ASUM, dp.I32, n, P, P2, dp.I32, None) == _lib.ERR_DTYPE
 
 
-def _inst(op, n, strategy=0, a=P, b=P, out=P2, m=0, lda=0, dtype=dp.F32):
+def _inst(op, n, strategy=0, a=P, b=P, out=P2, m=0, lda=0, dtype=dp.F32, reserved=0):
     c = _lib.CInstance()
-    c.op, c.dtype, c.strategy, c.reserved = op, dtype, strategy, 0
+    c.op, c.dtype, c.strategy, c.reserved = op, dtype, strategy, reserved
     c.m, c.n, c.lda = m, n, lda
     c.a, c.b, c.out = a.value, (b.value if b is not None else None), out.value
     return c
@@ -225,6 +225,9 @@ def test_batch_plan_validation_is_host_only():
         ([_inst(dp.OP_GEMV, 4000, m=10, lda=4002)], [good], _lib.ERR_SHAPE),      # lda % 4
         ([_inst(dp.OP_GEMV, 5000, m=10, lda=5000)], [good], _lib.ERR_SHAPE),      # k > W
         ([_inst(dp.OP_DOT, 0)], [good], _lib.ERR_SHAPE),
+        ([_inst(dp.OP_SCAL, 1000)], [good], _lib.ERR_STRATEGY),                 # not batched
+        ([_inst(7, 1000)], [good], _lib.ERR_STRATEGY),                          # unknown op
+        ([_inst(dp.OP_DOT, 1000, reserved=1)], [good], _lib.ERR_STRATEGY),
     ]
     for insts, strats, want in bad_cases:
         st, h = _plan(insts, strats)

@@ -1,0 +1,218 @@
+"""GPU parity of kernel paths that only wide teams, large matrices or many
+instances reach: compensated accumulators merged across wavefronts through
+LDS (teams of 128 and 256 threads), the fp8 gemv that reduces 4 rows per team
+with 64-element batches, a batch of instances drawn like the benchmark's
+(lengths up to 2^20, gemv sides up to 4096), and staged contiguous folds
+with an odd number of tiles.
+
+Every comparison is bit for bit against the oracle on the same inputs.  Where
+the full problem is too large for the oracle, it is evaluated on sampled
+rows: gemv rows are the iterations of a map, so a subset of rows has the
+same values alone as inside the whole matrix."""
+
+import numpy as np
+import pytest
+
+import paper_1710_08332_amd as dp
+import synthetic
+from oracle import exact
+from oracle import strategies as S
+from tests.gpu_util import assert_same_bits, cuda, discriminating, gpu_asum, gpu_dot, to_plan
+
+pytestmark = pytest.mark.gpu
+
+C_, T_ = dp.CONTIGUOUS, dp.STRIDED
+
+
+# ------------------------------------------------ compensated, wide teams
+# (C, L, order, combine): strided L=1024 is a team of 256 threads (4
+# wavefronts, the long-vector precision strategy), L=512 one of 128; the
+# contiguous L=256 team is 4 wavefronts staged through LDS; the sequential
+# combine over 1024 lanes reads every lane pair from LDS.
+WIDE_COMP = [(256, 1024, T_, dp.TREE), (256, 512, T_, dp.TREE), (64, 256, C_, dp.TREE),
+             (16, 1024, T_, dp.SEQ)]
+
+
+@pytest.mark.parametrize("strat", WIDE_COMP, ids=lambda s: f"C{s[0]}-L{s[1]}-{s[2]}-{s[3]}")
+@pytest.mark.parametrize("final_f64", [0, 1])
+@pytest.mark.parametrize("accum", [dp.KAHAN, dp.SUM2], ids=["kahan", "sum2"])
+def test_compensated_dots_with_teams_wider_than_a_wavefront(strat, final_f64, accum):
+    import torch
+    C, L, order, comb = strat
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb, accum=accum,
+                    final_f64=final_f64)
+    n = 3 * C * L
+    print(f"compensated accum={accum} f64={final_f64} C={C} L={L} n={n}", flush=True)
+    x, y = synthetic.kahan_dot_inputs(n, synthetic.SEEDS["precision"])
+    want = S.dot(x, y, to_plan(s))
+    for passes in (1, 2):
+        assert_same_bits(gpu_dot(x, y, s.with_(passes=passes)), want, f"passes={passes}")
+    if final_f64:
+        assert_same_bits(gpu_dot(x, y, s, out_dtype=torch.float32), np.float32(want),
+                         "binary64 fold rounded to binary32")
+    # cancelling products: the result is rounding error alone
+    xd, yd = discriminating(61, n)
+    assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, to_plan(s)), "cancelling")
+    err = abs(float(want) - exact.dot_exact(x, y)) / exact.dot_abs_terms(x, y)
+    assert err < 1e-6
+
+
+# ------------------------------------------------ fp8 gemv, rows per team
+def _fp8_rows_per_team(s, m, cus=256):
+    """The rows one team reduces at once for an fp8 matrix (the library's
+    rule, restated): 4 when that gives 1..2 work-groups per compute unit."""
+    team = s.local_size // 16
+    lg = max(1, 256 // (team * s.rows_per_wg))
+    per_wg4 = lg * s.rows_per_wg * 4
+    wgs4 = -(-m // per_wg4)
+    return 4 if cus <= wgs4 <= 2 * cus else 2
+
+
+@pytest.mark.parametrize("C,L", [(64, 256), (128, 128), (32, 512)])
+def test_fp8_gemv_rows_per_team_at_full_size(C, L):
+    # 16384 x 16384 fp8 rows with per-row scales; C >= 64 takes the
+    # 64-element batches, and (C=64, L=256) and (C=32, L=512) reduce 4 rows
+    # per team on a 256-CU device, (C=128, L=128) 2.
+    import torch
+    m = k = 16384
+    s = dp.Strategy(seq_len=C, local_size=L, order=T_, wg_combine=dp.TREE)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    print(f"fp8 gemv C={C} L={L} rows per team {_fp8_rows_per_team(s, m, cus)}", flush=True)
+    g = synthetic.rng(synthetic.SEEDS["precision"] + C)
+    A = synthetic.normal(g, (m, k))
+    x = synthetic.uniform_pm1(g, k)
+    codes, scale = synthetic.quantise_fp8_rows(A)
+    del A
+    y = dp.gemv(cuda(codes), cuda(x), s, row_scale=cuda(scale), a_dtype=dp.FP8_E4M3)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    # every row of the first and last team blocks, and a seeded sample
+    rows = np.unique(np.concatenate([np.arange(0, 128), np.arange(m - 128, m),
+                                     np.sort(g.choice(m, 256, replace=False))]))
+    want = S.gemv(codes[rows], x, to_plan(s), a_format="fp8", scale=scale[rows])
+    assert_same_bits(got[rows], want, f"fp8 C={C} L={L}")
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_row_blocked_gemv_with_a_ragged_last_block(fmt):
+    # m not a multiple of the rows a work-group takes at once: the last
+    # block's missing rows are skipped, the others exact
+    s = dp.Strategy(seq_len=64, local_size=256, order=T_, wg_combine=dp.TREE)
+    m, k = 16384 + 40, 16384 - 100
+    g = synthetic.rng(77)
+    A = synthetic.normal(g, (m, k))
+    x = synthetic.uniform_pm1(g, k)
+    import torch
+    lda = k + (-k) % 16
+    if fmt == "bf16":
+        codes, scale, adt = synthetic.quantise_bf16(A), None, dp.BF16
+    else:
+        (codes, scale), adt = synthetic.quantise_fp8_rows(A), dp.FP8_E4M3
+    del A
+    pad = np.zeros((m, lda), codes.dtype)
+    pad[:, :k] = codes
+    At = cuda(pad.view(np.int16) if pad.dtype == np.uint16 else pad)[:, :k]
+    y = dp.gemv(At, cuda(x), s, row_scale=cuda(scale) if scale is not None else None,
+                a_dtype=adt)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    rows = np.unique(np.concatenate([np.arange(m - 200, m), g.choice(m, 128, replace=False)]))
+    want = S.gemv(np.ascontiguousarray(codes[rows]), x, to_plan(s), a_format=fmt,
+                  scale=scale[rows] if scale is not None else None)
+    assert_same_bits(got[rows], want, f"{fmt} ragged block")
+
+
+# ------------------------------------------------ staged folds, odd tiles
+# Contiguous binary32 folds staged through LDS in 32-element tiles: C*V/32
+# tiles per lane row.  With few chunks (fewer wavefronts than compute units)
+# the dot keeps two tiles in flight; odd tile counts (1, 3, 5) end on the
+# first register set, and a single tile has no second one at all.
+ODD_TILES = [dict(seq_len=32, local_size=64, order=C_),
+             dict(seq_len=96, local_size=64, order=C_),
+             dict(seq_len=160, local_size=128, order=C_, wg_combine=dp.SEQ),
+             dict(seq_len=8, local_size=64, order=C_, vec_width=4),
+             dict(seq_len=24, local_size=64, order=C_, vec_width=4, wg_combine=dp.NONE),
+             dict(seq_len=40, local_size=256, order=C_)]
+
+
+@pytest.mark.parametrize("kw", ODD_TILES, ids=str)
+@pytest.mark.parametrize("chunks", [1, 7, 100])
+def test_staged_contiguous_folds_with_odd_tile_counts(kw, chunks):
+    import torch
+    s = dp.Strategy(**kw)
+    W = s.seq_len * s.local_size * max(1, s.vec_width)
+    n = W * chunks - (W // 3 if chunks > 1 else 0)          # a ragged last chunk too
+    print(f"odd tiles {kw} chunks={chunks} n={n}", flush=True)
+    x, y = discriminating(83 + chunks, n)
+    plan = to_plan(s)
+    assert_same_bits(gpu_dot(x, y, s), S.dot(x, y, plan), "dot")
+    assert_same_bits(gpu_asum(x, s), S.asum(x, plan), "asum")
+    xt, yt = cuda(x), cuda(y)
+    c = dp.chunks(dp.OP_DOT, s, xt, yt)
+    torch.cuda.synchronize()
+    vals = c.cpu().numpy().view(np.float32)[:dp.num_chunks(s, n) * dp.values_per_chunk(s)]
+    assert_same_bits(vals, S.dot_chunks(x, y, plan), "chunk values")
+
+
+# ------------------------------------------------ batches at benchmark sizes
+def _bench_like_instances(seed, n_red, n_gemv):
+    """Instances drawn as the benchmark draws them (op by a seeded coin,
+    n = floor(2^U(8, 20)); gemv m, k uniform in 64..4096), each with a
+    batch-eligible strategy of its size class picked by a seeded draw."""
+    import torch
+    from paper_1710_08332_amd import autotune as T
+    g = synthetic.rng(seed)
+    strategies, insts, host = [], [], []
+
+    def pick(cls):
+        cands = T.batch_candidates(cls)
+        s = cands[int(g.integers(0, len(cands)))]
+        if s not in strategies:
+            strategies.append(s)
+        return strategies.index(s)
+
+    for _ in range(n_red):
+        op = dp.OP_DOT if g.random() < 0.5 else dp.OP_ASUM
+        n = int(2 ** g.uniform(8, 20))
+        x = synthetic.uniform_pm1(g, n)
+        y = synthetic.uniform_pm1(g, n)
+        d = {"op": op, "x": torch.from_numpy(x).cuda(), "out": torch.empty(1, device="cuda")}
+        if op == dp.OP_DOT:
+            d["y"] = torch.from_numpy(y).cuda()
+        d["strategy"] = pick(T.size_class(d))
+        insts.append(d)
+        host.append((op, x, y))
+    for _ in range(n_gemv):
+        m, k = int(g.integers(64, 4097)), int(g.integers(64, 4097))
+        lda = -(-k // 4) * 4
+        A = np.zeros((m, lda), np.float32)
+        A[:, :k] = synthetic.uniform_pm1(g, (m, k))
+        x = synthetic.uniform_pm1(g, k)
+        d = {"op": dp.OP_GEMV, "A": torch.from_numpy(A).cuda()[:, :k],
+             "x": torch.from_numpy(x).cuda(), "out": torch.empty(m, device="cuda")}
+        d["strategy"] = pick(T.size_class(d))
+        insts.append(d)
+        host.append((dp.OP_GEMV, np.ascontiguousarray(A[:, :k]), x))
+    return insts, host, strategies
+
+
+def test_batch_at_benchmark_sizes_equals_the_oracle():
+    import torch
+    insts, host, strategies = _bench_like_instances(synthetic.SEEDS["batch"] + 1, 120, 8)
+    print(f"batch {len(insts)} instances, {len(strategies)} strategies", flush=True)
+    plan = dp.BatchPlan(insts, strategies)
+    ws = plan.workspace()
+    plan.upload(ws)
+    plan.run(ws)
+    torch.cuda.synchronize()
+    for i, (d, (op, a, b)) in enumerate(zip(insts, host)):
+        p = to_plan(strategies[d["strategy"]])
+        got = d["out"].cpu().numpy()
+        if op == dp.OP_GEMV:
+            want = S.gemv(a, b, p)
+        elif op == dp.OP_DOT:
+            want = np.atleast_1d(S.dot(a, b, p))
+        else:
+            want = np.atleast_1d(S.asum(a, p))
+        assert_same_bits(got, want, f"instance {i} op={op}")
+    plan.close()

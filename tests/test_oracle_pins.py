@@ -556,6 +556,92 @@ def test_kahan_expression_follows_the_stated_steps():
     assert same_bits(eval_scalar.evaluate(e, {"xs": x, "ys": y}), r)
 
 
+def _r64(q):
+    # Fraction -> nearest binary64 (CPython divides the integers correctly rounded)
+    return Fraction(float(q))
+
+
+@pytest.mark.parametrize("ev", EVALS)
+def test_kahan_binary64_final_fold_closed_forms(ev):
+    # The binary64 fold of the chunk values: acc = (f64 s - f64 c) + acc, from
+    # +0, in chunk order (a Kahan pair's value is s - c).
+    # (a) one lane folding 1 then 2^-30: the sum 1 + 2^-30 rounds to 1 in
+    #     binary32 and Kahan keeps the lost part as c = -2^-30, so the pair is
+    #     (1, -2^-30) and the binary64 value is exactly 1 + 2^-30.  A sign
+    #     flip (s + c) gives 1 - 2^-30; dropping c, or subtracting in binary32
+    #     before widening, gives 1.
+    p = S.Plan(seq=2, lanes=1, accum="kahan", final_f64=True)
+    xs = np.array([1.0, 2.0 ** -30], np.float32)
+    ys = np.ones(2, np.float32)
+    r = ev(S.dot_expr(2, p), {"xs": xs, "ys": ys})
+    assert np.asarray(r).dtype == np.float64
+    assert float(r) == 1.0 + 2.0 ** -30
+    # two such chunks: 2 + 2^-29, exact in binary64
+    r2 = ev(S.dot_expr(4, p), {"xs": np.tile(xs, 2), "ys": np.ones(4, np.float32)})
+    assert float(r2) == 2.0 + 2.0 ** -29
+    # (b) the fold runs in chunk order: chunk values 1, 2^53, -2^53.  In order,
+    #     2^53 + 1 is a tie that rounds to 2^53 (even), so the result is +0.
+    #     Folded from the last chunk (or as 1 + (2^53 - 2^53)) it would be 1.
+    q = S.Plan(seq=1, lanes=1, accum="kahan", final_f64=True)
+    xs = np.array([1.0, 2.0 ** 53, -2.0 ** 53], np.float32)
+    r3 = ev(S.dot_expr(3, q), {"xs": xs, "ys": np.ones(3, np.float32)})
+    assert np.asarray(r3).view(np.uint64) == 0
+    r4 = ev(S.dot_expr(3, q), {"xs": xs[::-1].copy(), "ys": np.ones(3, np.float32)})
+    assert float(r4) == 1.0
+    # (c) a chunk's c meets the next chunk in binary64: (1, -2^-30) then a
+    #     chunk (-1, 0) gives exactly 2^-30 (dropping c would give 0)
+    xs = np.array([1.0, 2.0 ** -30, -1.0, 0.0], np.float32)
+    r5 = ev(S.dot_expr(4, p), {"xs": xs, "ys": np.ones(4, np.float32)})
+    assert float(r5) == 2.0 ** -30
+
+
+def _kahan_chunk_pairs(x, y, C, L):
+    """Each chunk's merged Kahan pair (lane folds, tree combine, then merged
+    into the zero pair as the first step of the outer fold), in Fractions."""
+    W = C * L
+    zero = (Fraction(0), Fraction(0))
+    return [_kahan_reference_merge(zero, _kahan_reference(x[g * W:(g + 1) * W],
+                                                          y[g * W:(g + 1) * W], C, L))
+            for g in range(len(x) // W)]
+
+
+def test_kahan_final_folds_over_many_chunks_follow_the_stated_steps():
+    # Random chunk pairs with nonzero c: the binary32 TwoSum fold then s - c,
+    # and the binary64 fold of s - c, restated over Fractions with each
+    # rounding explicit, agree bit for bit with the oracle.
+    g = np.random.default_rng(35)
+    C, L, G = 8, 4, 9
+    n = C * L * G
+    x = (np.where(g.random(n) < 0.5, -1, 1) * 10.0 ** g.uniform(-4, 4, n)).astype(np.float32)
+    y = (np.where(g.random(n) < 0.5, -1, 1) * 10.0 ** g.uniform(-4, 4, n)).astype(np.float32)
+    pairs = _kahan_chunk_pairs(x, y, C, L)
+    assert sum(c != 0 for _, c in pairs) >= G // 2          # the c parts matter here
+    # binary32: TwoSum-merge the chunk pairs in order from the zero pair
+    # (the first merge into the zero pair is the identity on these pairs)
+    acc = pairs[0]
+    for pr in pairs[1:]:
+        acc = _kahan_reference_merge(acc, pr)
+    want32 = np.float32(float(acc[0])) - np.float32(float(acc[1]))
+    got32 = S.dot(x, y, S.Plan(seq=C, lanes=L, accum="kahan"))
+    assert same_bits(got32, want32)
+    # binary64: acc = (s - c) + acc, each operation rounded to binary64
+    a64 = Fraction(0)
+    for s, c in pairs:
+        a64 = _r64(_r64(s - c) + a64)
+    got64 = S.dot(x, y, S.Plan(seq=C, lanes=L, accum="kahan", final_f64=True))
+    assert np.asarray(got64).dtype == np.float64
+    assert float(got64) == float(a64)
+    # and the order matters on these data: folding from the last chunk differs
+    b64 = Fraction(0)
+    for s, c in reversed(pairs):
+        b64 = _r64(_r64(s - c) + b64)
+    c64 = Fraction(0)
+    for s, c in pairs:
+        c64 = _r64(_r64(s + c) + c64)
+    assert float(b64) != float(a64) or float(c64) != float(a64)
+    assert float(c64) != float(a64)
+
+
 def _kahan_reference_merge(left, right):
     def r32(q):
         return Fraction(struct.unpack("<f", struct.pack("<f", float(q)))[0])
