@@ -178,6 +178,24 @@ dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const voi
                      dpia_stream_t stream);
 
 /*
+ * dpia_dot without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and bits as dpia_dot with
+ * the same strategy; no call allocates or frees memory.  The chunk values
+ * and the 1-pass arrival counter live in a 1 MiB array inside the library,
+ * one per GPU, held until the process ends: strategies whose chunk values
+ * need more than 1 MiB - 256 bytes (G values of 4 bytes, 8 for compensated
+ * pairs) are rejected with DPIA_ERR_WORKSPACE before anything is launched.
+ * The first call on a device looks the array up and launches one small
+ * kernel on `stream` that clears the counter.  All calls on one GPU share
+ * its array: calls that may overlap (different streams without ordering,
+ * concurrent host threads on unordered streams) race and give undefined
+ * results; calls ordered on one stream are safe.
+ */
+dpia_status dpia_dot_noalloc(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                             const void* y, void* out, dpia_dtype out_dt, dpia_stream_t stream);
+
+/*
  * out[0] = sum |x[i]| under strategy s, with the per-lane operator
  * lam x a. abs x + a (the paper benchmarks asum, Sec. 7.1; abs is the one
  * scalar primitive added to Fig. 5a).  dt = out_dt = DPIA_F32, plain only.

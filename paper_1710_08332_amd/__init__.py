@@ -117,6 +117,19 @@ def dot(x, y, s: Strategy, out=None, ws=None, out_dtype=None, stream=None):
     return out
 
 
+def dot_noalloc(x, y, s: Strategy, out, stream=None):
+    """dpia_dot_noalloc: the dot with the library's own per-device scratch in
+    place of a workspace (no allocation in the call; ``out`` is required)."""
+    dt = _dtype_code(x)
+    if _dtype_code(y) != dt:
+        raise TypeError("x and y must have the same dtype")
+    cs = s.c()
+    _lib.check(_lib.lib().dpia_dot_noalloc(ctypes.byref(cs), dt, x.numel(), _dev(x), _dev(y),
+                                           _dev(out), _dtype_code(out), _stream(stream)),
+               "dpia_dot_noalloc")
+    return out
+
+
 def asum(x, s: Strategy, out=None, ws=None, stream=None):
     torch = _torch()
     n = x.numel()

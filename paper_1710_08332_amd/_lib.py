@@ -23,8 +23,8 @@ CONTIGUOUS, STRIDED = 0, 1
 TREE, SEQ, NONE = 0, 1, 2
 PLAIN, KAHAN, SUM2 = 0, 1, 2
 
-EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
-           "dpia_scal", "dpia_chunks", "dpia_module_load", "dpia_module_launch",
+EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_dot_noalloc", "dpia_asum", "dpia_gemv",
+           "dpia_gemv_blas", "dpia_scal", "dpia_chunks", "dpia_module_load", "dpia_module_launch",
            "dpia_module_unload", "dpia_read_stream",
            "dpia_fold", "dpia_batch_plan_create", "dpia_batch_workspace_bytes",
            "dpia_batch_upload", "dpia_batch_run", "dpia_batch_plan_destroy", "dpia_status_str",
@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
         L.dpia_strategy_check.argtypes = [sp, ctypes.c_int, ctypes.c_int, i64, i64,
                                           ctypes.POINTER(u64)]
         L.dpia_dot.argtypes = [sp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int, vp, u64, vp]
+        L.dpia_dot_noalloc.argtypes = [sp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int, vp]
         L.dpia_asum.argtypes = [sp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp, u64, vp]
         L.dpia_gemv.argtypes = [sp, ctypes.c_int, i64, i64, i64, vp, vp, vp, vp, vp, u64, vp]
         L.dpia_scal.argtypes = [sp, ctypes.c_int, i64, ctypes.c_float, vp, vp, vp]
@@ -86,8 +87,8 @@ def lib() -> ctypes.CDLL:
         L.dpia_batch_run.argtypes = [vp, vp, u64, vp]
         L.dpia_batch_plan_destroy.argtypes = [vp]
         L.dpia_batch_plan_destroy.restype = None
-        for f in ("dpia_strategy_check", "dpia_dot", "dpia_asum", "dpia_gemv", "dpia_gemv_blas",
-                  "dpia_scal", "dpia_chunks", "dpia_fold", "dpia_batch_plan_create",
+        for f in ("dpia_strategy_check", "dpia_dot", "dpia_dot_noalloc", "dpia_asum",
+                  "dpia_gemv", "dpia_gemv_blas", "dpia_scal", "dpia_chunks", "dpia_fold", "dpia_batch_plan_create",
                   "dpia_batch_upload", "dpia_batch_run", "dpia_module_load",
                   "dpia_module_launch", "dpia_module_unload", "dpia_read_stream"):
             getattr(L, f).restype = ctypes.c_int

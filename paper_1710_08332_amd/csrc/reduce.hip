@@ -9,6 +9,8 @@
 // second kernel (2 passes) or in the last work-group to finish (1 pass:
 // release fence, integer arrival counter, acquire fence).  Both evaluate the
 // same expression and give the same bits.
+#include <mutex>
+
 #include "device.h"
 #include "fold.h"
 #include "ops.h"
@@ -187,15 +189,17 @@ hipError_t launch_fold(int64_t G, const void* partials, void* out, int out_f64,
                          kFoldBlock * sizeof(T), stream);
 }
 
+// Both passes of a reduction: chunk values into `partials`, then the outer
+// fold (1 pass: in the last work-group, which needs `counter` at zero and
+// leaves it at zero; 2 passes: a second kernel).
 template <class Op, int FINAL>
-hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* ws,
-                         hipStream_t stream) {
+hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* partials,
+                         void* counter, hipStream_t stream) {
   const bool two_pass = p.passes == 2 || p.items == 0;
-  ReduceArgs a = reduce_args<Op>(p, ws, static_cast<char*>(ws) + p.partial_bytes, out, out_f64,
-                                 !two_pass);
+  ReduceArgs a = reduce_args<Op>(p, partials, counter, out, out_f64, !two_pass);
   hipError_t e = launch_chunks<Op, FINAL>(p, op, a, stream);
   if (e != hipSuccess || !two_pass) return e;
-  return launch_fold<Op, FINAL>(p.values, ws, out, out_f64, stream);
+  return launch_fold<Op, FINAL>(p.values, partials, out, out_f64, stream);
 }
 
 #ifndef DPIA_DEEPER_DOT
@@ -266,54 +270,151 @@ dpia_status check_ws(const Plan& p, void* ws, size_t ws_bytes) {
 
 using namespace dpia;
 
-extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
-                                const void* y, void* out, dpia_dtype out_dt, void* ws,
-                                size_t ws_bytes, dpia_stream_t stream) {
-  Plan p;
-  std::string detail;
-  dpia_status st = make_plan(s, DPIA_OP_DOT, dt, 0, n, &p, &detail);
-  if (st != DPIA_OK) return bad(st, detail);
-  if (!out || (n > 0 && (!x || !y))) return bad(DPIA_ERR_NULL, "x, y and out must be non-NULL");
-  if (n > 0 && (!aligned16(x) || !aligned16(y)))
-    return bad(DPIA_ERR_SHAPE, "x and y must be 16-byte aligned");
-  st = check_ws(p, ws, ws_bytes);
-  if (st != DPIA_OK) return st;
-  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+namespace {
+
+// Shared body of dpia_dot and dpia_dot_noalloc after validation: the launches
+// of a dot with its chunk values in `partials` and the 1-pass arrival
+// counter at `counter`.
+dpia_status dot_launch(const Plan& p, dpia_dtype dt, const void* x, const void* y, void* out,
+                       dpia_dtype out_dt, void* partials, void* counter, hipStream_t hs,
+                       const char* name) {
   hipError_t e;
   if (dt == DPIA_I32) {
-    if (out_dt != DPIA_I32) return bad(DPIA_ERR_DTYPE, "an I32 dot writes an I32 result");
     e = launch_reduce<DotU32, kFinalPlain>(
-        p, DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)}, out, 0, ws,
-        hs);
+        p, DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)}, out, 0,
+        partials, counter, hs);
   } else if (p.accum == DPIA_ACCUM_KAHAN || p.accum == DPIA_ACCUM_SUM2) {
-    if (out_dt != DPIA_F32 && !(out_dt == DPIA_F64 && p.final_f64))
-      return bad(DPIA_ERR_DTYPE, "a compensated dot writes F32, or F64 with final_f64");
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     const int f64 = out_dt == DPIA_F64;
     if (p.accum == DPIA_ACCUM_KAHAN) {
       KahanDotF32 op{xf, yf};
-      e = p.final_f64 ? launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, f64, ws, hs)
-                      : launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, ws, hs);
+      e = p.final_f64
+              ? launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, f64, partials, counter, hs)
+              : launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, partials, counter, hs);
     } else {
       Sum2DotF32 op{xf, yf};
-      e = p.final_f64 ? launch_reduce<Sum2DotF32, kFinalSum2_64>(p, op, out, f64, ws, hs)
-                      : launch_reduce<Sum2DotF32, kFinalSum2_32>(p, op, out, 0, ws, hs);
+      e = p.final_f64
+              ? launch_reduce<Sum2DotF32, kFinalSum2_64>(p, op, out, f64, partials, counter, hs)
+              : launch_reduce<Sum2DotF32, kFinalSum2_32>(p, op, out, 0, partials, counter, hs);
     }
   } else {
-    if (out_dt != DPIA_F32) return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     const int depth = dot_depth(p);
     e = depth == 2 ? launch_reduce<DotF32Deeper, kFinalPlain>(p, DotF32Deeper{{xf, yf}}, out, 0,
-                                                               ws, hs)
+                                                               partials, counter, hs)
         : depth == 1 ? launch_reduce<DotF32Deep, kFinalPlain>(p, DotF32Deep{{xf, yf}}, out, 0,
-                                                              ws, hs)
-                     : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, ws, hs);
+                                                              partials, counter, hs)
+                     : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, partials,
+                                                          counter, hs);
   }
-  if (e != hipSuccess) return hip_fail(e, "dpia_dot launch");
+  if (e != hipSuccess) return hip_fail(e, name);
   clear_detail();
   return DPIA_OK;
+}
+
+// Everything dpia_dot checks apart from the workspace.
+dpia_status dot_validate(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                         const void* y, const void* out, dpia_dtype out_dt, Plan* p) {
+  std::string detail;
+  dpia_status st = make_plan(s, DPIA_OP_DOT, dt, 0, n, p, &detail);
+  if (st != DPIA_OK) return bad(st, detail);
+  if (!out || (n > 0 && (!x || !y))) return bad(DPIA_ERR_NULL, "x, y and out must be non-NULL");
+  if (n > 0 && (!aligned16(x) || !aligned16(y)))
+    return bad(DPIA_ERR_SHAPE, "x and y must be 16-byte aligned");
+  if (dt == DPIA_I32) {
+    if (out_dt != DPIA_I32) return bad(DPIA_ERR_DTYPE, "an I32 dot writes an I32 result");
+  } else if (p->accum == DPIA_ACCUM_KAHAN || p->accum == DPIA_ACCUM_SUM2) {
+    if (out_dt != DPIA_F32 && !(out_dt == DPIA_F64 && p->final_f64))
+      return bad(DPIA_ERR_DTYPE, "a compensated dot writes F32, or F64 with final_f64");
+  } else if (out_dt != DPIA_F32) {
+    return bad(DPIA_ERR_DTYPE, "an F32 dot writes an F32 result");
+  }
+  return DPIA_OK;
+}
+
+}  // namespace
+
+extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
+                                const void* y, void* out, dpia_dtype out_dt, void* ws,
+                                size_t ws_bytes, dpia_stream_t stream) {
+  Plan p;
+  dpia_status st = dot_validate(s, dt, n, x, y, out, out_dt, &p);
+  if (st != DPIA_OK) return st;
+  st = check_ws(p, ws, ws_bytes);
+  if (st != DPIA_OK) return st;
+  return dot_launch(p, dt, x, y, out, out_dt, ws, static_cast<char*>(ws) + p.partial_bytes,
+                    reinterpret_cast<hipStream_t>(stream), "dpia_dot launch");
+}
+
+// ------------------------------------------------------------ no-alloc dot
+// dpia_dot_noalloc keeps the chunk values and the arrival counter of a call
+// in this file-scope device array instead of a caller workspace: bytes
+// [0, kWsAlign) hold the counter (at a fixed place, so that 1-pass calls of
+// any size find it at zero), the chunk values start at kWsAlign.  Every GPU
+// the library runs on has its own copy, at its own address.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+__global__ void scratch_clear_kernel(unsigned int* counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// The current device's copy of `scratch` (set up on the first call on that
+// device: its address, and the counter cleared by a kernel on `hs`).
+dpia_status scratch_for_current_device(hipStream_t hs, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "dpia_dot_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return bad(DPIA_ERR_HIP, "dpia_dot_noalloc: device id beyond the supported 64");
+  ScratchSlot& slot = g_scratch[dev];
+  std::call_once(slot.once, [&] {
+    void* ptr = nullptr;
+    slot.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (slot.err != hipSuccess) return;
+    unsigned int* counter = static_cast<unsigned int*>(ptr);
+    void* args[] = {&counter};
+    slot.err = hipLaunchKernel(reinterpret_cast<const void*>(scratch_clear_kernel), dim3(1),
+                               dim3(64), args, 0, hs);
+    if (slot.err == hipSuccess) slot.ptr = ptr;
+  });
+  if (slot.err != hipSuccess) return hip_fail(slot.err, "dpia_dot_noalloc: scratch set-up");
+  *out = slot.ptr;
+  return DPIA_OK;
+}
+
+}  // namespace
+
+extern "C" dpia_status dpia_dot_noalloc(const dpia_strategy* s, dpia_dtype dt, int64_t n,
+                                        const void* x, const void* y, void* out,
+                                        dpia_dtype out_dt, dpia_stream_t stream) {
+  Plan p;
+  dpia_status st = dot_validate(s, dt, n, x, y, out, out_dt, &p);
+  if (st != DPIA_OK) return st;
+  if (p.partial_bytes > kScratchBytes - kWsAlign)
+    return bad(DPIA_ERR_WORKSPACE,
+               "the strategy's " + std::to_string(p.partial_bytes) +
+                   " bytes of chunk values exceed the no-alloc scratch of " +
+                   std::to_string(kScratchBytes - kWsAlign) + " bytes");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  void* base = nullptr;
+  st = scratch_for_current_device(hs, &base);
+  if (st != DPIA_OK) return st;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  return dot_launch(p, dt, x, y, out, out_dt, b + kWsAlign, b, hs, "dpia_dot_noalloc launch");
 }
 
 extern "C" dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,
@@ -330,6 +431,7 @@ extern "C" dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t 
   if (st != DPIA_OK) return st;
   hipError_t e = launch_reduce<AsumF32, kFinalPlain>(p, AsumF32{static_cast<const float*>(x)},
                                                      out, 0, ws,
+                                                     static_cast<char*>(ws) + p.partial_bytes,
                                                      reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "dpia_asum launch");
   clear_detail();

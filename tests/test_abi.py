@@ -165,6 +165,28 @@ def test_entry_points_validate_before_launching():
                        None) == _lib.OK
 
 
+def _dot_noalloc(s, n, x=P, y=P, out=P2, out_dt=dp.F32, dt=dp.F32):
+    cs = s.c()
+    return _lib.lib().dpia_dot_noalloc(ctypes.byref(cs), dt, n, x, y, out, out_dt, None)
+
+
+def test_noalloc_dot_validates_before_any_hip_call():
+    n = 1 << 20
+    assert _dot_noalloc(BASE.with_(accum=dp.KAHAN), n + 1) == _lib.ERR_SHAPE
+    assert _dot_noalloc(BASE, n, out=ctypes.c_void_p(0)) == _lib.ERR_NULL
+    assert _dot_noalloc(BASE, n, y=ctypes.c_void_p(0)) == _lib.ERR_NULL
+    assert _dot_noalloc(BASE, n, y=ctypes.c_void_p(0x7000_0008)) == _lib.ERR_SHAPE
+    assert _dot_noalloc(BASE, n, out_dt=dp.F64) == _lib.ERR_DTYPE
+    assert _dot_noalloc(BASE, n, dt=dp.BF16) == _lib.ERR_DTYPE
+    # chunk values beyond the 1 MiB scratch (less its 256-byte counter
+    # section): 2^18 - 64 binary32 values fit, 2^18 do not
+    one = dp.Strategy(seq_len=1, local_size=1, wg_combine=dp.NONE)
+    assert _dot_noalloc(one, 1 << 18) == _lib.ERR_WORKSPACE
+    assert "scratch" in _lib.last_error_detail()
+    kahan = dp.Strategy(seq_len=1, local_size=1, accum=dp.KAHAN)
+    assert _dot_noalloc(kahan, 1 << 17) == _lib.ERR_WORKSPACE   # 8-byte pairs
+
+
 def test_python_strategy_check_raises_with_detail():
     with pytest.raises(dp.DpiaError) as ei:
         dp.strategy_check(BASE.with_(accum=dp.KAHAN), dp.OP_DOT, dp.F32, 0, 1000)
