@@ -74,26 +74,108 @@ __device__ __forceinline__ void vload(const E* __restrict__ p, E (&out)[NV]) {
   }
 }
 
+// Device-coherent accesses to chunk values that another work-group (on
+// another XCD, whose L2 is not kept coherent with this one's) wrote or will
+// read within the same launch: a relaxed agent-scope atomic store goes
+// through to memory (global_store ... sc1) and a relaxed agent-scope atomic
+// load is served coherently (global_load ... sc1).  A writer makes its stores
+// complete (s_waitcnt) before it raises an arrival counter, so no L2
+// write-back (an agent-scope release) is needed per work-group.
+template <class T>
+__device__ __forceinline__ void store_coherent(T* p, const T& v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  if constexpr (sizeof(T) == 4) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  T v;
+  if constexpr (sizeof(T) == 4) {
+    const uint32_t u = __hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_memcpy(&v, &u, 4);
+  } else {
+    const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_memcpy(&v, &u, 8);
+  }
+  return v;
+}
+
+// Waits until every memory access this thread issued has completed (its
+// coherent stores included).
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
+// ------------------------------------------------------------ lane exchange
+// The 32-bit value of the butterfly partner at distance D (1, 2, ..., 32)
+// within the wavefront, for the levels of the tree combine, without the LDS
+// crossbar: DPP quad permutations swap neighbours (D = 1) and pairs (D = 2);
+// from D = 4 on, every aligned group of D lanes already holds one value (the
+// node of the levels below), so the half-row and row mirrors (lane i reads
+// lane 7 - i, or 15 - i, within its 8 or 16 lanes) fetch the partner group's
+// value as an exchange with lane i ^ D would; gfx950's permlane swaps
+// exchange the 16-lane rows (D = 16) and the 32-lane halves (D = 32).  Every
+// lane of the wavefront must execute it.
+template <int D>
+__device__ __forceinline__ uint32_t butterfly_partner(uint32_t v) {
+  const int x = static_cast<int>(v);
+  if constexpr (D == 1) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+  } else if constexpr (D == 2) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+  } else if constexpr (D == 4) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));
+  } else if constexpr (D == 8) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));
+  } else if constexpr (D == 16) {
+    // {old vdst, old vsrc} = {v, v}: vdst then holds rows 0,0,2,2 of v and
+    // vsrc rows 1,1,3,3
+    const auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? s[0] : s[1];
+  } else {
+    static_assert(D == 32, "butterfly distances are powers of two up to 32");
+    // vdst then holds halves 0,0 of v and vsrc halves 1,1
+    const auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? s[0] : s[1];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float butterfly_partner(float v) {
+  return __uint_as_float(butterfly_partner<D>(__float_as_uint(v)));
+}
+
 // ------------------------------------------------------------ accumulators
 // Each accumulator type provides zero() (the literal 0 of the expression,
 // +0 for binary32) and add(e, acc) = the reduceSeq operator (+) applied to an
 // element e and the accumulator acc (element first, as in the paper's
-// reduce), plus warp shuffles for the tree.
+// reduce), plus the butterfly exchange for the tree.
 
 struct PlainF32 {
   using T = float;
   __device__ static T zero() { return 0.0f; }
   __device__ static T add(T e, T acc) { return e + acc; }
-  __device__ static T shfl_xor(T v, int d) { return __shfl_xor(v, d, 64); }
+  template <int D>
+  __device__ static T partner(T v) { return butterfly_partner<D>(v); }
 };
 
 struct PlainU32 {
   using T = uint32_t;
   __device__ static T zero() { return 0u; }
   __device__ static T add(T e, T acc) { return e + acc; }
-  __device__ static T shfl_xor(T v, int d) {
-    return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), d, 64));
-  }
+  template <int D>
+  __device__ static T partner(T v) { return butterfly_partner<D>(v); }
 };
 
 // Compensated pair (s, c), value s - c.  add(r, l) merges a later pair r
@@ -113,8 +195,9 @@ struct KahanF32 {
     const float e = (l.s - (s - bp)) + (r.s - bp);
     return KPair{s, (l.c + r.c) - e};
   }
-  __device__ static T shfl_xor(T v, int d) {
-    return KPair{__shfl_xor(v.s, d, 64), __shfl_xor(v.c, d, 64)};
+  template <int D>
+  __device__ static T partner(T v) {
+    return KPair{butterfly_partner<D>(v.s), butterfly_partner<D>(v.c)};
   }
 };
 
@@ -132,8 +215,9 @@ struct Sum2F32 {
     const float e = (l.s - (s - bp)) + (r.s - bp);
     return KPair{s, (l.c + r.c) + e};
   }
-  __device__ static T shfl_xor(T v, int d) {
-    return KPair{__shfl_xor(v.s, d, 64), __shfl_xor(v.c, d, 64)};
+  template <int D>
+  __device__ static T partner(T v) {
+    return KPair{butterfly_partner<D>(v.s), butterfly_partner<D>(v.c)};
   }
 };
 
@@ -144,6 +228,28 @@ __device__ __forceinline__ typename A::T tree_node(typename A::T left, typename 
 }
 
 // ------------------------------------------------------------ team combine
+// The tree levels over `width` adjacent threads (a power of two up to 64,
+// uniform across the wavefront): level d pairs thread t with t ^ d, and both
+// compute the node (0 + left) + right with the lower thread's value on the
+// left.  Every thread of the wavefront takes part.
+template <class A, int D>
+__device__ __forceinline__ void butterfly_level(typename A::T& v, int t, int width) {
+  if (width > D) {
+    const typename A::T other = A::template partner<D>(v);
+    v = (t & D) ? tree_node<A>(other, v) : tree_node<A>(v, other);
+  }
+}
+
+template <class A>
+__device__ __forceinline__ void butterfly_levels(typename A::T& v, int t, int width) {
+  butterfly_level<A, 1>(v, t, width);
+  butterfly_level<A, 2>(v, t, width);
+  butterfly_level<A, 4>(v, t, width);
+  butterfly_level<A, 8>(v, t, width);
+  butterfly_level<A, 16>(v, t, width);
+  butterfly_level<A, 32>(v, t, width);
+}
+
 // Combine the lane values of one chunk.  `acc` holds the NL lane values of
 // this thread (NL = lanes per thread: NV for the strided order, 1 for the
 // contiguous order), lanes t*NL .. t*NL + NL-1 of the team.  Returns the
@@ -174,10 +280,7 @@ __device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL],
     // levels across the threads of one wavefront: butterfly over ascending
     // distances pairs thread t with t^d, the lower one holding the left node
     const int in_wave = team < 64 ? team : 64;
-    for (int d = 1; d < in_wave; d <<= 1) {
-      T other = A::shfl_xor(v, d);
-      v = (t & d) ? tree_node<A>(other, v) : tree_node<A>(v, other);
-    }
+    butterfly_levels<A>(v, t, in_wave);
     if (team > 64) {
       // levels across wavefronts, through LDS
       const int waves = team / 64;
@@ -185,10 +288,7 @@ __device__ __forceinline__ typename A::T combine_lanes(typename A::T (&acc)[NL],
       __syncthreads();
       if (t < 64) {
         v = (t < waves) ? scratch[t] : A::zero();
-        for (int d = 1; d < waves; d <<= 1) {
-          T other = A::shfl_xor(v, d);
-          v = (t & d) ? tree_node<A>(other, v) : tree_node<A>(v, other);
-        }
+        butterfly_levels<A>(v, t, waves);
       }
       __syncthreads();
     }
@@ -618,7 +718,7 @@ struct ShiftedView {
 // VEC consecutive elements, asVector VEC) and of uncombined ones (COMBINE ==
 // kNone: every lane's value is a chunk value).  Writes the chunk's values to
 // out[g * cv ...], cv = VEC, or L * VEC uncombined, in lane then component
-// order (asScalar VEC of the join).  All threads of the work-group call this
+// order (asScalar VEC of the join), with device-coherent stores.  All threads of the work-group call this
 // together (the combine has barriers).
 // `stage`: as for chunk_value (the contiguous order, staged per wavefront).
 template <class Op, int ORDER, int NV, int COMBINE, int VEC, class View>
@@ -643,7 +743,7 @@ __device__ __forceinline__ void chunk_values_wide(const View& view, bool active,
     if (active) {
       const int64_t lane0 = g * L + (ORDER == kStrided ? t * NV : t);
 #pragma unroll
-      for (int v = 0; v < NL; ++v) out[lane0 + v] = acc[v];
+      for (int v = 0; v < NL; ++v) store_coherent(out + lane0 + v, acc[v]);
     }
   } else {
     static_assert(NV == VEC, "a thread is one vector lane");
@@ -674,7 +774,7 @@ __device__ __forceinline__ void chunk_values_wide(const View& view, bool active,
     if constexpr (COMBINE == kNone) {
       if (active) {
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) out[(g * L + t) * VEC + j] = acc[j];
+        for (int j = 0; j < VEC; ++j) store_coherent(out + (g * L + t) * VEC + j, acc[j]);
       }
     } else {
       // the combine acts on each component
@@ -682,7 +782,7 @@ __device__ __forceinline__ void chunk_values_wide(const View& view, bool active,
       for (int j = 0; j < VEC; ++j) {
         T one[1] = {acc[j]};
         const T c = combine_lanes<typename Op::Arith, 1, COMBINE>(one, t, team, L, scratch);
-        if (active && t == 0) out[g * VEC + j] = c;
+        if (active && t == 0) store_coherent(out + g * VEC + j, c);
       }
     }
   }

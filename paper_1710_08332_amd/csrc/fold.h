@@ -21,7 +21,9 @@ enum : int {
 // order, by one thread.  The work-group stages blocks of chunk values in LDS
 // (coalesced), then thread 0 reads them back 32 at a time into registers
 // and folds them in order.
-template <class A, int FINAL>
+// COHERENT: the chunk values are read with device-coherent loads (values
+// written by other work-groups of the same launch with store_coherent).
+template <class A, int FINAL, bool COHERENT = false>
 __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
                            typename A::T* buf) {
   using T = typename A::T;
@@ -38,7 +40,8 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
   };
   for (int64_t b = 0; b < G; b += kFoldBlock) {
     const int cnt = static_cast<int>(G - b < kFoldBlock ? G - b : kFoldBlock);
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[i] = partials[b + i];
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+      buf[i] = COHERENT ? load_coherent(partials + b + i) : partials[b + i];
     __syncthreads();
     if (threadIdx.x == 0) {
       int i = 0;

@@ -7,8 +7,9 @@
 // temporary of Sec. 6.3: one slot per parforWorkgroup iteration).  The outer
 // reduceSeq over partial[0..G) from +0 in chunk order then runs either in a
 // second kernel (2 passes) or in the last work-group to finish (1 pass:
-// release fence, integer arrival counter, acquire fence).  Both evaluate the
-// same expression and give the same bits.
+// device-coherent chunk-value stores, an integer arrival counter, coherent
+// loads in the last work-group).  Both evaluate the same expression and give
+// the same bits.
 #include <mutex>
 
 #include "device.h"
@@ -62,28 +63,28 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
     if constexpr (VEC == 1 && COMBINE != kNone) {
       const T v = chunk_value<Op, ORDER, NV, COMBINE>(view, active, t, a.team, a.L, a.C, limit,
                                                       scratch, stage);
-      if (active && t == 0) partials[g] = v;
+      if (active && t == 0) store_coherent(partials + g, v);
     } else {
       chunk_values_wide<Op, ORDER, NV, COMBINE, VEC>(view, active, t, a.team, a.L, a.C, limit,
                                                      scratch, partials, g, stage);
     }
   }
   if (a.one_pass) {
-    // The barrier makes this work-group's partial stores happen before
-    // thread 0's agent-scope release; the arrival counter then orders them
-    // before the last work-group's acquire, which the barrier hands on to
-    // every thread of that work-group.  One fence per work-group.
+    // Chunk values were written with device-coherent stores; each thread
+    // waits for its own to complete, the barrier then puts all of this
+    // work-group's before the arrival counter, and the last work-group to
+    // arrive reads them back with device-coherent loads.  No L2 write-back
+    // per work-group.
+    wait_memory();
     __syncthreads();
     if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned prev =
           __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       is_last = (prev == gridDim.x - 1);
-      if (is_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (is_last) {
-      final_fold<typename Op::Arith, FINAL>(partials, a.values, a.out, a.out_f64, lds);
+      final_fold<typename Op::Arith, FINAL, true>(partials, a.values, a.out, a.out_f64, lds);
       if (threadIdx.x == 0)   // leave the counter at zero for the next call
         __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -153,15 +154,7 @@ hipError_t with_reduce_shape(const Plan& p, F&& f) {
 template <class Op, int FINAL>
 hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
   if (p.items == 0) return hipSuccess;
-  int64_t grid = grid_size(p);
-  if (a.one_pass && p.max_grid == 0) {
-    // 1 pass: every work-group ends with an agent-scope release (an L2
-    // write-back); one work-group per compute unit, each taking many chunks
-    // by the grid-stride loop, pays it fewest times (measured at 2^26, L=256:
-    // strided C=64 45% -> 58% of peak, contiguous C=256 52% -> 68%)
-    const int64_t cus = device_cus();
-    if (grid > cus) grid = cus;
-  }
+  const int64_t grid = grid_size(p);
   return with_reduce_shape<FINAL == kFinalPlain>(p, [&](auto ord, auto comb, auto nvc, auto vec) {
     constexpr int ORDER = decltype(ord)::value;
     constexpr int COMBINE = decltype(comb)::value;
