@@ -311,13 +311,20 @@ dpia_status dpia_module_unload(dpia_module* m);
 
 /*
  * Batched execution: many independent dot / asum / gemv instances, each with
- * its own strategy, in two launches (a persistent kernel over a table of
- * tiles, then one work-group per reduction instance folding its chunk values
- * in order).  Each instance's result has exactly the bits of the single call
- * (dpia_dot / dpia_asum / dpia_gemv) with the same strategy.  This is the
- * strategy-per-size-class execution that the paper's strategy search
+ * its own strategy.  A tile is a group of chunks (or gemv rows) of one
+ * instance; the work-groups take the tiles, largest first, by a grid-stride
+ * loop (the parforWorkgroup of Sec. 6.2).  Tiles only place work on
+ * work-groups, so each instance's result has exactly the bits of the single
+ * call (dpia_dot / dpia_asum / dpia_gemv) with the same strategy.  This is
+ * the strategy-per-size-class execution that the paper's strategy search
  * (Sec. 1, building on Steuwer et al. 2015) produces, for workloads of many
- * small problems.
+ * small problems.  Two engines run a plan:
+ *  - dpia_batch_run: two launches, the tiles, then one work-group per
+ *    reduction instance folding its chunk values in chunk order;
+ *  - dpia_batch_run_one_launch: one persistent launch; an arrival counter
+ *    per instance counts the tiles whose chunk values are complete, and the
+ *    work-group that completes the count folds that instance's values.
+ * Both give the same bits.
  *
  * Restrictions: F32 data, plain accumulation, strategies whose vector width
  * is 16 bytes (strided: local_size, contiguous: seq_len a multiple of 4) and
@@ -351,18 +358,29 @@ dpia_status dpia_batch_plan_create(const dpia_instance* inst, int32_t count,
                                    const dpia_strategy* strategies, int32_t nstrat,
                                    dpia_batch_plan** out);
 
-/* Device workspace bytes a run needs (tables + chunk values). */
+/* Device workspace bytes a run needs (tables, counters, chunk values). */
 size_t dpia_batch_workspace_bytes(const dpia_batch_plan* plan);
 
-/* Copies the plan's tables into `ws` (256-byte aligned) and waits for the
- * copy; call once per workspace before the first run. */
+/* Enqueues on `stream` a copy of the plan's tables, with every counter
+ * zeroed, into `ws` (256-byte aligned); call once per workspace before the
+ * first run.  Does not wait: the plan must not be destroyed before the copy
+ * has completed (e.g. before the stream reaches a later run). */
 dpia_status dpia_batch_upload(const dpia_batch_plan* plan, void* ws, size_t ws_bytes,
                               dpia_stream_t stream);
 
 /* Runs every instance: two kernel launches on `stream`, no allocation, no
- * memset, no synchronisation (may be captured in a graph and replayed). */
+ * memset, no synchronisation (may be captured in a graph and replayed).
+ * Runs sharing a workspace must be ordered (same stream). */
 dpia_status dpia_batch_run(const dpia_batch_plan* plan, void* ws, size_t ws_bytes,
                            dpia_stream_t stream);
+
+/* Runs every instance in one kernel launch on `stream`: no allocation, no
+ * memset, no synchronisation.  The launch leaves every arrival counter in
+ * `ws` at zero again, so it may be captured in a graph and replayed, and
+ * runs of either engine may follow each other on one workspace.  Runs
+ * sharing a workspace must be ordered (same stream). */
+dpia_status dpia_batch_run_one_launch(const dpia_batch_plan* plan, void* ws, size_t ws_bytes,
+                                      dpia_stream_t stream);
 
 void dpia_batch_plan_destroy(dpia_batch_plan* plan);
 

@@ -251,8 +251,8 @@ def fold(op: int, s: Strategy, chunk_values, n: int, dtype: int, out=None, out_d
 # ------------------------------------------------------------ batched
 
 class BatchPlan:
-    """Many dot / asum / gemv instances, each with its own strategy, run as
-    two kernel launches (see dpia_batch_* in include/dpia.h).
+    """Many dot / asum / gemv instances, each with its own strategy, run by
+    one of two engines (see dpia_batch_* in include/dpia.h).
 
     ``instances``: list of dicts with keys ``op`` (OP_DOT / OP_ASUM /
     OP_GEMV), ``strategy`` (index into ``strategies``), and tensors ``x``,
@@ -284,6 +284,7 @@ class BatchPlan:
         _lib.check(L.dpia_batch_plan_create(arr, n, cs, len(strategies), ctypes.byref(h)),
                    "dpia_batch_plan_create")
         self._h = h
+        self._uploaded = False
         self.workspace_bytes = L.dpia_batch_workspace_bytes(h)
 
     def workspace(self, device="cuda"):
@@ -292,13 +293,20 @@ class BatchPlan:
     def upload(self, ws, stream=None):
         _lib.check(_lib.lib().dpia_batch_upload(self._h, _dev(ws), ws.numel(), _stream(stream)),
                    "dpia_batch_upload")
+        self._uploaded = True
 
-    def run(self, ws, stream=None):
-        _lib.check(_lib.lib().dpia_batch_run(self._h, _dev(ws), ws.numel(), _stream(stream)),
-                   "dpia_batch_run")
+    def run(self, ws, stream=None, one_launch=False):
+        """Runs every instance: two launches (dpia_batch_run), or one
+        persistent launch with per-instance arrival counters
+        (dpia_batch_run_one_launch); the same bits either way."""
+        f = _lib.lib().dpia_batch_run_one_launch if one_launch else _lib.lib().dpia_batch_run
+        _lib.check(f(self._h, _dev(ws), ws.numel(), _stream(stream)),
+                   "dpia_batch_run_one_launch" if one_launch else "dpia_batch_run")
 
     def close(self):
         if self._h:
+            if self._uploaded:
+                _torch().cuda.synchronize()   # the upload copies from the plan's tables
             _lib.lib().dpia_batch_plan_destroy(self._h)
             self._h = None
 

@@ -27,7 +27,8 @@ EXPORTS = ("dpia_strategy_check", "dpia_dot", "dpia_dot_noalloc", "dpia_asum", "
            "dpia_gemv_blas", "dpia_scal", "dpia_chunks", "dpia_module_load", "dpia_module_launch",
            "dpia_module_unload", "dpia_read_stream",
            "dpia_fold", "dpia_batch_plan_create", "dpia_batch_workspace_bytes",
-           "dpia_batch_upload", "dpia_batch_run", "dpia_batch_plan_destroy", "dpia_status_str",
+           "dpia_batch_upload", "dpia_batch_run", "dpia_batch_run_one_launch",
+           "dpia_batch_plan_destroy", "dpia_status_str",
            "dpia_last_error_detail", "dpia_abi_version")
 
 
@@ -85,11 +86,13 @@ def lib() -> ctypes.CDLL:
         L.dpia_batch_workspace_bytes.restype = u64
         L.dpia_batch_upload.argtypes = [vp, vp, u64, vp]
         L.dpia_batch_run.argtypes = [vp, vp, u64, vp]
+        L.dpia_batch_run_one_launch.argtypes = [vp, vp, u64, vp]
         L.dpia_batch_plan_destroy.argtypes = [vp]
         L.dpia_batch_plan_destroy.restype = None
         for f in ("dpia_strategy_check", "dpia_dot", "dpia_dot_noalloc", "dpia_asum",
                   "dpia_gemv", "dpia_gemv_blas", "dpia_scal", "dpia_chunks", "dpia_fold", "dpia_batch_plan_create",
-                  "dpia_batch_upload", "dpia_batch_run", "dpia_module_load",
+                  "dpia_batch_upload", "dpia_batch_run", "dpia_batch_run_one_launch",
+                  "dpia_module_load",
                   "dpia_module_launch", "dpia_module_unload", "dpia_read_stream"):
             getattr(L, f).restype = ctypes.c_int
         L.dpia_status_str.argtypes = [ctypes.c_int]

@@ -23,11 +23,12 @@ enum : int {
 // and folds them in order.
 // COHERENT: the chunk values are read with device-coherent loads (values
 // written by other work-groups of the same launch with store_coherent).
-template <class A, int FINAL, bool COHERENT = false>
+// R: values thread 0 reads from LDS into registers at a time (fewer
+// registers where the fold shares a kernel with other work).
+template <class A, int FINAL, bool COHERENT = false, int R = 32>
 __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
                            typename A::T* buf) {
   using T = typename A::T;
-  constexpr int R = 32;
   T acc = A::zero();
   double acc64 = 0.0;
   auto fold1 = [&](const T& e) {

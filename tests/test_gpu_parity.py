@@ -394,13 +394,14 @@ def _batch_instances(seed, count_red, count_gemv, max_log_n=14, max_mk=300):
     return insts, host, strategies
 
 
-def test_batched_instances_equal_single_calls_and_the_oracle():
+@pytest.mark.parametrize("one_launch", [False, True], ids=["two_launches", "one_launch"])
+def test_batched_instances_equal_single_calls_and_the_oracle(one_launch):
     import torch
     insts, host, strategies = _batch_instances(31, 150, 40)
     plan = dp.BatchPlan(insts, strategies)
     ws = plan.workspace()
     plan.upload(ws)
-    plan.run(ws)
+    plan.run(ws, one_launch=one_launch)
     torch.cuda.synchronize()
     for d, (op, si, a, b) in zip(insts, host):
         s = strategies[si]
@@ -418,13 +419,14 @@ def test_batched_instances_equal_single_calls_and_the_oracle():
         assert_same_bits(got, want, f"batched vs oracle op={op} s={si}")
 
 
-def test_batched_run_in_a_graph_replays_exactly():
+@pytest.mark.parametrize("one_launch", [False, True], ids=["two_launches", "one_launch"])
+def test_batched_run_in_a_graph_replays_exactly(one_launch):
     import torch
     insts, host, strategies = _batch_instances(37, 60, 20)
     plan = dp.BatchPlan(insts, strategies)
     ws = plan.workspace()
     plan.upload(ws)
-    plan.run(ws)
+    plan.run(ws, one_launch=one_launch)
     torch.cuda.synchronize()
     eager = [d["out"].clone() for d in insts]
     side = torch.cuda.Stream()
@@ -434,7 +436,7 @@ def test_batched_run_in_a_graph_replays_exactly():
         for d in insts:
             d["out"].fill_(-1.0)
         with torch.cuda.graph(graph, stream=side):
-            plan.run(ws)
+            plan.run(ws, one_launch=one_launch)
     torch.cuda.current_stream().wait_stream(side)
     for rep in range(3):
         for d in insts:

@@ -196,14 +196,16 @@ def _bench_like_instances(seed, n_red, n_gemv):
     return insts, host, strategies
 
 
-def test_batch_at_benchmark_sizes_equals_the_oracle():
+@pytest.mark.parametrize("one_launch", [False, True], ids=["two_launches", "one_launch"])
+def test_batch_at_benchmark_sizes_equals_the_oracle(one_launch):
     import torch
     insts, host, strategies = _bench_like_instances(synthetic.SEEDS["batch"] + 1, 120, 8)
-    print(f"batch {len(insts)} instances, {len(strategies)} strategies", flush=True)
+    print(f"batch {len(insts)} instances, {len(strategies)} strategies, "
+          f"one_launch={one_launch}", flush=True)
     plan = dp.BatchPlan(insts, strategies)
     ws = plan.workspace()
     plan.upload(ws)
-    plan.run(ws)
+    plan.run(ws, one_launch=one_launch)
     torch.cuda.synchronize()
     for i, (d, (op, a, b)) in enumerate(zip(insts, host)):
         p = to_plan(strategies[d["strategy"]])
@@ -215,4 +217,59 @@ def test_batch_at_benchmark_sizes_equals_the_oracle():
         else:
             want = np.atleast_1d(S.asum(a, p))
         assert_same_bits(got, want, f"instance {i} op={op}")
+    plan.close()
+
+
+def test_batch_runs_back_to_back_clear_their_counters():
+    # Reductions of many tiles each (W = 256, 16 chunks per tile: up to 64
+    # arrivals per instance) mixed with one-tile ones and gemvs, run six
+    # times in a row on one stream, on two workspaces, by both engines in
+    # turn: every one-launch run starts from the counters the previous run
+    # left at zero, and every run gives the single calls' bits.
+    import torch
+    g = synthetic.rng(91)
+    strategies = [dp.Strategy(seq_len=4, local_size=64, order=T_),
+                  dp.Strategy(seq_len=16, local_size=256, order=C_, wg_combine=dp.SEQ),
+                  dp.Strategy(seq_len=8, local_size=64, order=T_)]
+    insts = []
+    for i in range(48):
+        op = (dp.OP_DOT, dp.OP_ASUM, dp.OP_GEMV)[i % 3]
+        si = i % 2 if op != dp.OP_GEMV else 2
+        if op == dp.OP_GEMV:
+            m, k = int(g.integers(1, 700)), int(g.integers(1, 513))
+            lda = -(-k // 4) * 4
+            A = torch.zeros((m, lda), device="cuda")
+            A[:, :k] = torch.from_numpy(synthetic.normal(g, (m, k))).cuda()
+            insts.append({"op": op, "strategy": si, "A": A[:, :k],
+                          "x": torch.from_numpy(synthetic.uniform_pm1(g, k)).cuda(),
+                          "out": torch.empty(m, device="cuda")})
+            continue
+        n = int(2 ** g.uniform(8, 18)) if i % 4 else (1 << 18) - int(g.integers(0, 200))
+        d = {"op": op, "strategy": si, "out": torch.empty(1, device="cuda"),
+             "x": torch.from_numpy(synthetic.log_uniform_signed(g, n)).cuda()}
+        if op == dp.OP_DOT:
+            d["y"] = torch.from_numpy(synthetic.uniform_pm1(g, n)).cuda()
+        insts.append(d)
+    single = []
+    for d in insts:
+        s = strategies[d["strategy"]]
+        if d["op"] == dp.OP_GEMV:
+            single.append(dp.gemv(d["A"], d["x"], s).cpu().numpy())
+        elif d["op"] == dp.OP_DOT:
+            single.append(dp.dot(d["x"], d["y"], s).cpu().numpy())
+        else:
+            single.append(dp.asum(d["x"], s).cpu().numpy())
+    plan = dp.BatchPlan(insts, strategies)
+    ws_a, ws_b = plan.workspace(), plan.workspace()
+    plan.upload(ws_a)
+    plan.upload(ws_b)
+    runs = ((ws_a, True), (ws_a, True), (ws_b, True), (ws_a, False), (ws_a, True), (ws_b, False))
+    for run, (ws, one) in enumerate(runs):
+        print(f"batch back-to-back run {run} one_launch={one}", flush=True)
+        for d in insts:
+            d["out"].fill_(float("nan"))
+        plan.run(ws, one_launch=one)
+        torch.cuda.synchronize()
+        for i, (d, want) in enumerate(zip(insts, single)):
+            assert_same_bits(d["out"].cpu().numpy(), want, f"run {run} instance {i}")
     plan.close()
