@@ -27,7 +27,7 @@ Other workloads (one JSON line per measured item, not the headline):
                           [2^8, 2^20]) and 512 gemvs (m, k in [64, 4096]),
                           strategies tuned per size class: per-instance
                           launches (eager, graph) against one batched run
-                          (eager, graph)
+                          by each engine, two launches or one (eager, graph)
     --workload scal       scal y = alpha x, N = 2^26, under strided and
                           contiguous strategies, out of place and in place;
                           and the BLAS gemv y := alpha A x + beta y beside
@@ -77,6 +77,7 @@ DOT_BYTES = 2 * 4 * N_DOT + 4                    # x, y read; one result written
 G_DOT = N_DOT // (DOT_STRATEGY.seq_len * DOT_STRATEGY.local_size)
 CHUNK_KERNEL_BYTES = 2 * 4 * N_DOT + 4 * G_DOT   # first pass: x, y read; G values written
 GEMV_BYTES = 4 * M_GEMV * K_GEMV + 4 * K_GEMV + 4 * M_GEMV
+A_COPIES = 3
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -109,29 +110,49 @@ def strategy_text(s: dp.Strategy, gemv: bool = False) -> str:
             + (f" R={s.rows_per_wg}" if gemv else f" passes={s.passes}"))
 
 
-def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=12.0):
-    """The oracle (numpy, one thread) on the same step, repeated until about
-    ``budget_s`` seconds have passed; also confirms bit parity of the
-    measured GPU results."""
+def cpu_baseline(x, y, A, xv, gpu_dot_val, gpu_y, budget_s=10.0):
+    """The oracle on the same step, timed twice on this host: serially on
+    one core, and with its outermost maps (the dot's chunks, the gemv's rows)
+    evaluated by worker processes on every core this process may use; each
+    repeated until about ``budget_s`` seconds have passed.  Also confirms bit
+    parity of the measured GPU results with both."""
+    from oracle import parallel as P
     from oracle import strategies as S
     from tests.gpu_util import to_plan
     dplan, gplan = to_plan(DOT_STRATEGY), to_plan(GEMV_STRATEGY)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        d = S.dot(x, y, dplan)
-        g = S.gemv(A, xv, gplan)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 1000:
-            break
-    parity = {
-        "dot_bit_exact": bool(np.asarray(d).view(np.uint32) == np.float32(gpu_dot_val).view(np.uint32)),
-        "gemv_bit_exact": bool(np.array_equal(np.asarray(g).view(np.uint32), gpu_y.view(np.uint32))),
-    }
-    value = (DOT_BYTES + GEMV_BYTES) * reps / el / 1e9
-    return {"value": round(value, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full step (dot 2^26 + gemv 8192^2, same strategies) x {reps} "
-                      f"repetitions, {el:.1f} s, numpy single thread"}, parity
+    step_bytes = DOT_BYTES + GEMV_BYTES
+
+    def timed(run):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            d, g = run()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or reps >= 1000:
+                return d, g, reps, el
+
+    d1, g1, reps1, el1 = timed(lambda: (S.dot(x, y, dplan), S.gemv(A, xv, gplan)))
+    t0 = time.perf_counter()
+    with P.Evaluator({"xs": x, "ys": y, "A": A, "x": xv}) as ev:
+        setup = time.perf_counter() - t0
+        dn, gn, repsn, eln = timed(lambda: (ev.dot(dplan), ev.gemv(gplan)))
+        workers = ev.workers
+
+    def same(a, b):
+        return bool(np.array_equal(np.asarray(a, np.float32).view(np.uint32),
+                                   np.asarray(b, np.float32).view(np.uint32)))
+    parity = {"dot_bit_exact": same(d1, gpu_dot_val) and same(dn, gpu_dot_val),
+              "gemv_bit_exact": same(g1, gpu_y) and same(gn, gpu_y)}
+    one = step_bytes * reps1 / el1 / 1e9
+    many = step_bytes * repsn / eln / 1e9
+    return {"value": round(many, 3), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "cpu_model": P.cpu_model(), "host_cores_available": P.host_cores(cap=1 << 16),
+            "sample": f"the full step (dot 2^26 + gemv 8192^2, same strategies) x {repsn} "
+                      f"repetitions in {eln:.1f} s, the dot's chunks and the gemv's rows split "
+                      f"over {workers} worker processes (pool set-up {setup:.1f} s, untimed)",
+            "single_core": {"value": round(one, 3), "cores": 1,
+                            "sample": f"the full step x {reps1} repetitions in {el1:.1f} s, "
+                                      "serial"}}, parity
 
 
 def _line(**kw):
@@ -422,13 +443,21 @@ def workload_batch(args):
     rows["per_instance_eager"] = per_us
     g1 = graphed(per_instance)
     rows["per_instance_graph"] = time_us(g1.replay, reps=reps, warmup=1)[0]
-    rows["batched_eager"] = time_us(lambda: plan.run(ws), reps=reps, warmup=1)[0]
-    g2 = graphed(lambda: plan.run(ws))
-    rows["batched_graph"] = time_us(g2.replay, reps=reps, warmup=1)[0]
-    plan.run(ws)
-    torch.cuda.synchronize()
-    same = all(np.array_equal(d["out"].cpu().numpy().view(np.uint32), p.cpu().numpy().view(np.uint32))
-               for d, p in zip(insts, per_out))
+    same = True
+    for one in (False, True):
+        name = "one_launch" if one else "two_launches"
+        rows[f"batched_{name}_eager"] = time_us(lambda: plan.run(ws, one_launch=one), reps=reps,
+                                                warmup=1)[0]
+        g2 = graphed(lambda: plan.run(ws, one_launch=one))
+        rows[f"batched_{name}_graph"] = time_us(g2.replay, reps=reps, warmup=1)[0]
+        del g2
+        for d in insts:
+            d["out"].fill_(float("nan"))
+        plan.run(ws, one_launch=one)
+        torch.cuda.synchronize()
+        same = same and all(np.array_equal(d["out"].cpu().numpy().view(np.uint32),
+                                           p.cpu().numpy().view(np.uint32))
+                            for d, p in zip(insts, per_out))
     for name, us in rows.items():
         _line(workload="batch", mode=name, instances=len(insts), us=round(us, 1),
               gbs=_gbs(nbytes, us), pct_peak=round(100 * nbytes / us / 1e3 / PEAK_GBPS, 1),
@@ -437,8 +466,9 @@ def workload_batch(args):
           strategies=[strategy_text(s) for s in strategies],
           size_classes=len({row["class"] for row in table}), tuning_runs=len(table),
           tune_seconds=round(tune_s, 1), generate_seconds=round(gen_s, 1),
-          note="one batched run = 2 launches; per-instance = one call per instance (2 kernels "
-               "per reduction), the same strategies")
+          note="batched: two launches (tiles, then folds) or one persistent launch (per-instance "
+               "arrival counters, the last tile folds); per-instance = one call per instance "
+               "(2 kernels per reduction); the same strategies throughout")
     if not args.no_cpu_baseline:
         from oracle import strategies as S
         from tests.gpu_util import to_plan
@@ -707,7 +737,8 @@ def read_ceiling(dev, nbytes, reps=10):
 
 def graph_replay(step, outputs, steps_per_graph=20, replays=10):
     """The step replayed from a HIP graph: ``steps_per_graph`` steps captured
-    once, each replay timed with events (no host launch cost inside).  After
+    once (``step(j)`` for step j of the graph), each replay timed with events
+    (no host launch cost inside).  After
     every replay the ``outputs`` tensors are compared bit for bit with their
     eager values.  Returns (median µs per step, all replays equal)."""
     import torch
@@ -716,11 +747,11 @@ def graph_replay(step, outputs, steps_per_graph=20, replays=10):
     side.wait_stream(torch.cuda.current_stream())
     gr = torch.cuda.CUDAGraph()
     with torch.cuda.stream(side):
-        step()
+        step(0)
         torch.cuda.synchronize()
         with torch.cuda.graph(gr, stream=side):
-            for _ in range(steps_per_graph):
-                step()
+            for j in range(steps_per_graph):
+                step(j)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     ev = TimingEvents(replays)
@@ -780,25 +811,38 @@ def main():
          "batch": workload_batch, "scal": workload_scal,
          "vector": workload_vector, "generated": workload_generated}[args.workload](args)
         return
+    from paper_1710_08332_amd.autotune import cache_evictor, time_us
     dev = torch.device("cuda:0")
     x, y = synthetic.dot_inputs(N_DOT, SEED)
     A, xv = synthetic.gemv_inputs(M_GEMV, K_GEMV, SEED)
     xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
-    At, xvt = torch.from_numpy(A).to(dev), torch.from_numpy(xv).to(dev)
+    # A_COPIES copies of A, read in turn: between two reads of one copy the
+    # step streams the dot's 512 MiB and the other copies' 512 MiB, so the
+    # gemv never finds its matrix in the 256 MB last-level cache
+    Ats = [torch.from_numpy(A).to(dev) for _ in range(A_COPIES)]
+    xvt = torch.from_numpy(xv).to(dev)
     out = torch.empty(1, dtype=torch.float32, device=dev)
     yg = torch.empty(M_GEMV, dtype=torch.float32, device=dev)
     chunk_vals = torch.empty(G_DOT * 4, dtype=torch.uint8, device=dev)
 
     # one step: the dot's two passes (chunk values, then their ordered fold)
-    # and the gemv, all on torch's current stream
-    def step(i=None):
-        if i is not None:
-            timer.record(i, 0)
+    # and the gemv, all on torch's current stream; `marks` optionally times
+    # the first pass alone (roofline), or each part of the step
+    def step(i, first=None, parts=None):
+        if first is not None:
+            first.record(i, 0)
+        if parts is not None:
+            parts[0].record(i, 0)
         dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals)
-        if i is not None:
-            timer.record(i, 1)
+        if first is not None:
+            first.record(i, 1)
         dp.fold(dp.OP_DOT, DOT_STRATEGY, chunk_vals, N_DOT, dp.F32, out=out)
-        dp.gemv(At, xvt, GEMV_STRATEGY, y=yg)
+        if parts is not None:
+            parts[0].record(i, 1)
+            parts[1].record(i, 0)
+        dp.gemv(Ats[i % A_COPIES], xvt, GEMV_STRATEGY, y=yg)
+        if parts is not None:
+            parts[1].record(i, 1)
 
     if args.profile_copy:
         src = torch.empty(1 << 26, dtype=torch.float32, device=dev).fill_(1.0)
@@ -808,20 +852,37 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
 
+    # the headline: K steps back to back, only the first pass bracketed
     timer = TimingEvents(args.steps)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(i)
+        step(i, first=timer)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     dot_ms = [timer.elapsed_ms(i) for i in range(args.steps)]
     dot_avg_s = float(np.mean(dot_ms)) / 1e3
     timer_kind = timer.kind
     timer.close()
+
+    # the same steps again, each part of the step bracketed (not the headline:
+    # the extra events add their own small gaps)
+    parts = (TimingEvents(args.steps), TimingEvents(args.steps))
+    for i in range(args.steps):
+        step(i, parts=parts)
+    torch.cuda.synchronize()
+    dot_e2e_us = float(np.median([parts[0].elapsed_ms(i) for i in range(args.steps)])) * 1e3
+    gemv_step_us = float(np.median([parts[1].elapsed_ms(i) for i in range(args.steps)])) * 1e3
+    for t in parts:
+        t.close()
+    # the gemv alone with the last-level cache evicted before every call
+    evict = cache_evictor()
+    gemv_cold_us = time_us(lambda: dp.gemv(Ats[0], xvt, GEMV_STRATEGY, y=yg), reps=20,
+                           between=evict)[0]
+    del evict
 
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
@@ -843,11 +904,26 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "FP32 dot N=2^26 + FP32 gemv 8192x8192 (one step = one of each)",
+            "workload": "FP32 dot N=2^26 + FP32 gemv 8192x8192 (one step = one of each; the "
+                        f"gemv reads {A_COPIES} copies of A in turn, none cache-resident)",
             "dot_strategy": strategy_text(DOT_STRATEGY),
             "gemv_strategy": strategy_text(GEMV_STRATEGY, gemv=True),
             "percent_of_hbm_peak": round(100 * value / PEAK_GBPS, 2),
             "parallelism": "single GPU",
+        },
+        "step_parts": {
+            "dot_end_to_end": {"us": round(dot_e2e_us, 2), "bytes": DOT_BYTES,
+                               "gbs": _gbs(DOT_BYTES, dot_e2e_us),
+                               "frac": round(DOT_BYTES / dot_e2e_us / 1e3 / PEAK_GBPS, 4),
+                               "what": "both passes: chunk values, then their ordered fold"},
+            "gemv_in_step": {"us": round(gemv_step_us, 2), "bytes": GEMV_BYTES,
+                             "gbs": _gbs(GEMV_BYTES, gemv_step_us),
+                             "frac": round(GEMV_BYTES / gemv_step_us / 1e3 / PEAK_GBPS, 4)},
+            "gemv_cache_evicted": {"us": round(gemv_cold_us, 2), "bytes": GEMV_BYTES,
+                                   "gbs": _gbs(GEMV_BYTES, gemv_cold_us),
+                                   "frac": round(GEMV_BYTES / gemv_cold_us / 1e3 / PEAK_GBPS, 4),
+                                   "what": "the gemv alone, 512 MiB written before every call"},
+            "timed_with": timer_kind + " (medians)",
         },
         "graph_replay": {"us_per_step": round(graph_us, 2),
                          "gbs": round((DOT_BYTES + GEMV_BYTES) / graph_us / 1e3, 1),

@@ -23,6 +23,9 @@ Modules:
                  rounding Python doubles to binary32 after each operation
   formats     -- bf16 and fp8-e4m3 decoding from the format definitions
   exact       -- correctly rounded reference sums (math.fsum) and bounds
+  parallel    -- the same expressions with the outermost map (chunks, gemv
+                 rows) split over worker processes and one fold at the end:
+                 the serial result's bits on every core of the host
 
 Parity status: every function here is pinned by the tests in
 ``tests/test_oracle_*.py`` (closed forms, laws of Sec. 5.3, integer brute
