@@ -40,6 +40,10 @@ Other workloads (one JSON line per measured item, not the headline):
     --workload generated  the headline dot and gemv strategies compiled from
                           their DPIA expressions by the generator, timed
                           beside the hand-written kernels (same bits)
+    --workload kernels    each hot kernel (dot first pass, f32 / bf16 / fp8
+                          gemvs) launched --steps times with the cache evicted
+                          in between, beside the read-stream ceiling on the
+                          same bytes: a fixed kernel mix for counter runs
 Oracle work (parity, exact references) runs only in the CPU-baseline leg,
 which --no-cpu-baseline skips.
 """
@@ -704,6 +708,68 @@ def workload_generated(args):
         g.close()
 
 
+KERNEL_CASES = (
+    # (name, format, m = k, strategy)
+    ("gemv_f32_8192", "f32", 8192, GEMV_STRATEGY),
+    ("gemv_f32_16384_C32_L512", "f32", 16384,
+     dp.Strategy(seq_len=32, local_size=512, order=dp.STRIDED, wg_combine=dp.TREE)),
+    ("gemv_f32_16384_C64_L256_R4", "f32", 16384,
+     dp.Strategy(seq_len=64, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE, rows_per_wg=4)),
+    ("gemv_f32_16384_C16_L1024", "f32", 16384,
+     dp.Strategy(seq_len=16, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE)),
+    ("gemv_bf16_16384_C32_L512", "bf16", 16384,
+     dp.Strategy(seq_len=32, local_size=512, order=dp.STRIDED, wg_combine=dp.TREE)),
+    ("gemv_fp8_16384_C64_L256", "fp8", 16384,
+     dp.Strategy(seq_len=64, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE)),
+)
+
+
+def workload_kernels(args):
+    """Each hot kernel of the headline and precision configurations, launched
+    ``--steps`` times with the last-level cache evicted before every launch:
+    the dot's first pass (2^26, headline strategy), the gemvs above, and the
+    read-stream ceiling on each matrix's bytes.  A small, fixed kernel mix for
+    rocprofv3 counter runs; each line gives the evicted median."""
+    import torch
+    import synthetic
+    from paper_1710_08332_amd.autotune import cache_evictor, time_us
+    evict = cache_evictor()
+    reps = max(3, args.steps)
+    x, y = synthetic.dot_inputs(N_DOT, SEED)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    chunk_vals = torch.empty(G_DOT * 4, dtype=torch.uint8, device="cuda")
+    med = time_us(lambda: dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals), reps=reps,
+                  between=evict)[0]
+    _line(workload="kernels", op="dot_first_pass_2p26", strategy=strategy_text(DOT_STRATEGY),
+          us=round(med, 2), gbs=_gbs(CHUNK_KERNEL_BYTES, med),
+          pct_peak=round(100 * CHUNK_KERNEL_BYTES / med / 1e3 / PEAK_GBPS, 1))
+    del xt, yt
+    mats = {}
+    for name, fmt, mk, s in KERNEL_CASES:
+        if (fmt, mk) not in mats:
+            A, xv = synthetic.gemv_inputs(mk, mk, synthetic.SEEDS["precision"])
+            if fmt == "bf16":
+                At, sc = torch.from_numpy(synthetic.quantise_bf16(A).view(np.int16)).cuda(), None
+            elif fmt == "fp8":
+                codes, scale = synthetic.quantise_fp8_rows(A)
+                At, sc = torch.from_numpy(codes).cuda(), torch.from_numpy(scale).cuda()
+            else:
+                At, sc = torch.from_numpy(A).cuda(), None
+            mats = {(fmt, mk): (At, sc, torch.from_numpy(xv).cuda())}
+        At, sc, xvt = mats[(fmt, mk)]
+        dt = {"f32": dp.F32, "bf16": dp.BF16, "fp8": dp.FP8_E4M3}[fmt]
+        yv = torch.empty(mk, device="cuda")
+        med = time_us(lambda: dp.gemv(At, xvt, s, y=yv, row_scale=sc, a_dtype=dt), reps=reps,
+                      between=evict)[0]
+        a_bytes = At.numel() * At.element_size()
+        nbytes = a_bytes + 4 * mk + 4 * mk + (4 * mk if sc is not None else 0)
+        ceil_us, grid = evicted_read_ceiling(At, evict, reps=reps)
+        _line(workload="kernels", op=name, strategy=strategy_text(s, gemv=True), us=round(med, 2),
+              gbs=_gbs(nbytes, med), pct_peak=round(100 * nbytes / med / 1e3 / PEAK_GBPS, 1),
+              read_ceiling_us=round(ceil_us, 2), read_ceiling_grid=grid,
+              pct_of_read_ceiling=round(100 * (nbytes / med) / (a_bytes / ceil_us), 1))
+
+
 def read_ceiling(dev, nbytes, reps=10):
     """The measured read-stream ceiling: the best bandwidth of the plain read
     kernel (every byte loaded once, 16-byte non-temporal loads) over a few
@@ -790,7 +856,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "small", "sweep", "precision", "batch", "scal", "vector",
-                             "generated"])
+                             "generated", "kernels"])
     ap.add_argument("--profile-copy", action="store_true",
                     help="also launch one plain 256 MiB device-to-device copy (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -809,7 +875,8 @@ def main():
     if args.workload != "scale":
         {"small": workload_small, "sweep": workload_sweep, "precision": workload_precision,
          "batch": workload_batch, "scal": workload_scal,
-         "vector": workload_vector, "generated": workload_generated}[args.workload](args)
+         "vector": workload_vector, "generated": workload_generated,
+         "kernels": workload_kernels}[args.workload](args)
         return
     from paper_1710_08332_amd.autotune import cache_evictor, time_us
     dev = torch.device("cuda:0")

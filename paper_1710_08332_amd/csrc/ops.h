@@ -181,6 +181,12 @@ __device__ __forceinline__ void fp8_to_f32(const uint8_t (&c)[NV], float (&f)[NV
 #ifndef DPIA_BF16_BATCH_ELEMS
 #define DPIA_BF16_BATCH_ELEMS 16
 #endif
+#ifndef DPIA_F32_GEMV_BATCH_ELEMS
+#define DPIA_F32_GEMV_BATCH_ELEMS 32
+#endif
+#ifndef DPIA_F32_GEMV_STREAM_A
+#define DPIA_F32_GEMV_STREAM_A 1
+#endif
 #ifndef DPIA_FP8_BATCH_ELEMS
 #define DPIA_FP8_BATCH_ELEMS 16
 #endif
@@ -191,14 +197,19 @@ struct GemvF32Acc {
   using Arith = PlainF32;
   using T = float;
   using Term = GTerm;
-  // Measured on MI355X for binary32 rows: larger load batches and cached
-  // loads of A stream faster than the dot's settings (16 elements,
-  // non-temporal); the narrow formats keep those (row-blocked kernel).
+  // Measured on MI355X for binary32 rows, with the last-level cache evicted
+  // before every call: 32-element load batches and non-temporal loads of A
+  // (16384^2, C=32 L=512: 172.4 us with cached loads of A, 158.5 us
+  // non-temporal, 97.7% of the read-stream ceiling on A's bytes; 16- and
+  // 64-element batches 162.9 and 158.2 us; 8192^2 headline strategy 46.7 ->
+  // 43.3 us).  The narrow formats stream A with 16-element batches
+  // (row-blocked kernel).  x is reused by every row and stays cached.
   static constexpr bool kF32 = std::is_same<E, float>::value;
   static constexpr int kBatchElems =
       BATCH ? BATCH
-            : (kF32 ? 32 : (sizeof(E) == 2 ? DPIA_BF16_BATCH_ELEMS : DPIA_FP8_BATCH_ELEMS));
-  static constexpr bool kStreamA = !kF32;
+            : (kF32 ? DPIA_F32_GEMV_BATCH_ELEMS
+                    : (sizeof(E) == 2 ? DPIA_BF16_BATCH_ELEMS : DPIA_FP8_BATCH_ELEMS));
+  static constexpr bool kStreamA = !kF32 || DPIA_F32_GEMV_STREAM_A;
   struct View {
     static constexpr bool kStageable = std::is_same<E, float>::value;
     // 1- and 2-byte codes: staged by contiguous_staged_codes
