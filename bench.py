@@ -2,7 +2,9 @@
 
 One step = one FP32 dot product of N = 2^26 (x, y uniform in [-1, 1]) and
 one FP32 gemv y = A x with A 8192 x 8192 row-major, entries N(0, 1), x
-uniform in [-1, 1] (seed 1712), each under a fixed DPIA strategy.  Inputs are
+uniform in [-1, 1] (seed 1712), each under a fixed DPIA strategy; the dot is
+one kernel (its last work-group folds the chunk values), and the gemv reads
+three copies of A in turn, so that none is served from the last-level cache.  Inputs are
 resident in HBM before timing starts.  Value = algorithmic bytes of the step
 (every input element read once, results written once) x steps / wall time,
 in GB/s.
@@ -40,7 +42,7 @@ Other workloads (one JSON line per measured item, not the headline):
     --workload generated  the headline dot and gemv strategies compiled from
                           their DPIA expressions by the generator, timed
                           beside the hand-written kernels (same bits)
-    --workload kernels    each hot kernel (dot first pass, f32 / bf16 / fp8
+    --workload kernels    each hot kernel (the dot, f32 / bf16 / fp8
                           gemvs) launched --steps times with the cache evicted
                           in between, beside the read-stream ceiling on the
                           same bytes: a fixed kernel mix for counter runs
@@ -70,16 +72,18 @@ SEED = 1712
 
 # split 262144 -> mapWorkgroup (1024 lanes, each folding a strided row of 256
 # -> mapLocal reduceSeq) -> tree in local memory; then reduceSeq over the 256
-# chunk values in a second pass
+# chunk values, in the last work-group to finish (one kernel)
 DOT_STRATEGY = dp.Strategy(seq_len=256, local_size=1024, order=dp.STRIDED, wg_combine=dp.TREE,
-                           passes=2)
+                           passes=1)
 # rows of 8192 = 256 lanes x 32 strided elements, tree, 4 rows per work-group
 GEMV_STRATEGY = dp.Strategy(seq_len=32, local_size=256, order=dp.STRIDED, wg_combine=dp.TREE,
                             rows_per_wg=4)
 
 DOT_BYTES = 2 * 4 * N_DOT + 4                    # x, y read; one result written
 G_DOT = N_DOT // (DOT_STRATEGY.seq_len * DOT_STRATEGY.local_size)
-CHUNK_KERNEL_BYTES = 2 * 4 * N_DOT + 4 * G_DOT   # first pass: x, y read; G values written
+# the whole dot in one kernel: x, y read, G chunk values written and read
+# back by the last work-group, the result written
+DOT_KERNEL_BYTES = 2 * 4 * N_DOT + 2 * 4 * G_DOT + 4
 GEMV_BYTES = 4 * M_GEMV * K_GEMV + 4 * K_GEMV + 4 * M_GEMV
 A_COPIES = 3
 
@@ -89,8 +93,8 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 def measured_traffic():
-    """HBM bytes per launch of the dot's first pass from the committed
-    rocprofv3 counter summary, or None when the kernel sources changed since
+    """HBM bytes per launch of the dot kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since
     the counters were taken (their hash no longer matches)."""
     import hashlib
     try:
@@ -102,7 +106,7 @@ def measured_traffic():
             h.update(open(os.path.join(root, f), "rb").read())
         if h.hexdigest() != kv["source_sha256"].strip():
             return None
-        return int(kv["dot_first_pass_traffic_bytes"])
+        return int(kv["dot_traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -727,7 +731,7 @@ KERNEL_CASES = (
 def workload_kernels(args):
     """Each hot kernel of the headline and precision configurations, launched
     ``--steps`` times with the last-level cache evicted before every launch:
-    the dot's first pass (2^26, headline strategy), the gemvs above, and the
+    the dot (2^26, headline strategy, one kernel), the gemvs above, and the
     read-stream ceiling on each matrix's bytes.  A small, fixed kernel mix for
     rocprofv3 counter runs; each line gives the evicted median."""
     import torch
@@ -737,12 +741,13 @@ def workload_kernels(args):
     reps = max(3, args.steps)
     x, y = synthetic.dot_inputs(N_DOT, SEED)
     xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
-    chunk_vals = torch.empty(G_DOT * 4, dtype=torch.uint8, device="cuda")
-    med = time_us(lambda: dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals), reps=reps,
+    out = torch.empty(1, device="cuda")
+    ws = dp.workspace(DOT_STRATEGY, dp.OP_DOT, dp.F32, 0, N_DOT)
+    med = time_us(lambda: dp.dot(xt, yt, DOT_STRATEGY, out=out, ws=ws), reps=reps,
                   between=evict)[0]
-    _line(workload="kernels", op="dot_first_pass_2p26", strategy=strategy_text(DOT_STRATEGY),
-          us=round(med, 2), gbs=_gbs(CHUNK_KERNEL_BYTES, med),
-          pct_peak=round(100 * CHUNK_KERNEL_BYTES / med / 1e3 / PEAK_GBPS, 1))
+    _line(workload="kernels", op="dot_2p26", strategy=strategy_text(DOT_STRATEGY),
+          us=round(med, 2), gbs=_gbs(DOT_KERNEL_BYTES, med),
+          pct_peak=round(100 * DOT_KERNEL_BYTES / med / 1e3 / PEAK_GBPS, 1))
     del xt, yt
     mats = {}
     for name, fmt, mk, s in KERNEL_CASES:
@@ -890,20 +895,19 @@ def main():
     xvt = torch.from_numpy(xv).to(dev)
     out = torch.empty(1, dtype=torch.float32, device=dev)
     yg = torch.empty(M_GEMV, dtype=torch.float32, device=dev)
-    chunk_vals = torch.empty(G_DOT * 4, dtype=torch.uint8, device=dev)
+    ws_dot = dp.workspace(DOT_STRATEGY, dp.OP_DOT, dp.F32, 0, N_DOT, dev)
 
-    # one step: the dot's two passes (chunk values, then their ordered fold)
-    # and the gemv, all on torch's current stream; `marks` optionally times
-    # the first pass alone (roofline), or each part of the step
+    # one step: the dot (one kernel: chunk values, then their ordered fold in
+    # the last work-group) and the gemv, on torch's current stream; `first`
+    # optionally times the dot alone (roofline), `parts` each part of the step
     def step(i, first=None, parts=None):
         if first is not None:
             first.record(i, 0)
         if parts is not None:
             parts[0].record(i, 0)
-        dp.chunks(dp.OP_DOT, DOT_STRATEGY, xt, yt, out=chunk_vals)
+        dp.dot(xt, yt, DOT_STRATEGY, out=out, ws=ws_dot)
         if first is not None:
             first.record(i, 1)
-        dp.fold(dp.OP_DOT, DOT_STRATEGY, chunk_vals, N_DOT, dp.F32, out=out)
         if parts is not None:
             parts[0].record(i, 1)
             parts[1].record(i, 0)
@@ -923,7 +927,7 @@ def main():
         step(i)
     torch.cuda.synchronize()
 
-    # the headline: K steps back to back, only the first pass bracketed
+    # the headline: K steps back to back, only the dot bracketed
     timer = TimingEvents(args.steps)
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -953,7 +957,7 @@ def main():
 
     total_bytes = (DOT_BYTES + GEMV_BYTES) * args.steps
     value = total_bytes / el / 1e9
-    achieved = CHUNK_KERNEL_BYTES / dot_avg_s / 1e9
+    achieved = DOT_KERNEL_BYTES / dot_avg_s / 1e9
     graph_us, graph_same = graph_replay(step, [out, yg])
     ceiling = read_ceiling(dev, 2 * N_DOT * 4)
     ceiling["frac"] = round(achieved / ceiling["gbs"], 4)
@@ -982,7 +986,7 @@ def main():
             "dot_end_to_end": {"us": round(dot_e2e_us, 2), "bytes": DOT_BYTES,
                                "gbs": _gbs(DOT_BYTES, dot_e2e_us),
                                "frac": round(DOT_BYTES / dot_e2e_us / 1e3 / PEAK_GBPS, 4),
-                               "what": "both passes: chunk values, then their ordered fold"},
+                               "what": "the whole dot: chunk values and their ordered fold"},
             "gemv_in_step": {"us": round(gemv_step_us, 2), "bytes": GEMV_BYTES,
                              "gbs": _gbs(GEMV_BYTES, gemv_step_us),
                              "frac": round(GEMV_BYTES / gemv_step_us / 1e3 / PEAK_GBPS, 4)},
@@ -997,15 +1001,15 @@ def main():
                          "steps_per_graph": 20, "bit_exact_vs_eager": graph_same},
         "roofline": {
             "bound": "hbm",
-            "kernel": "reduce_kernel<DotF32, strided, 4, tree> (dot first pass)",
-            "bytes_per_launch": CHUNK_KERNEL_BYTES,
+            "kernel": "reduce_kernel<DotF32, strided, 4, tree> (the whole dot, 1 pass)",
+            "bytes_per_launch": DOT_KERNEL_BYTES,
             "achieved": round(achieved, 3),
             "peak": PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_GBPS, 4),
             "traffic": measured_traffic(),
             "avg_kernel_us": round(dot_avg_s * 1e6, 3),
-            "timed_with": timer_kind + " around each first-pass launch",
+            "timed_with": timer_kind + " around each dot launch",
             "read_ceiling": ceiling,
         },
     }
