@@ -216,7 +216,9 @@ dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t n, const vo
  *              1 <= k <= seq_len * local_size * row_parts, shorter rows
  *              being read as extended with zeros (which no plain fold sees)
  *   row_scale  FP8 only (else NULL): y[r] = row_scale[r] * (row r . x)
- *   x, y       k and m elements (binary32, or I32 with an I32 A)
+ *   x, y       k and m elements: binary32 for F32, BF16 and FP8 matrices,
+ *              I32 for an I32 matrix (hence untyped pointers here;
+ *              dpia_gemv_blas, which takes no I32 matrix, types them float)
  *   ws         unused (pass NULL, 0)
  */
 dpia_status dpia_gemv(const dpia_strategy* s, dpia_dtype a_dt, int64_t m, int64_t k,

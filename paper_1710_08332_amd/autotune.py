@@ -10,7 +10,9 @@ produces are checked against the CPU oracle by the test suite, not here: this
 module only measures.
 
 Cache: a JSON file (``DPIA_TUNE_CACHE``, default ``~/.cache/dpia/tune.json``)
-mapping "device|op|dtype|shape" to the chosen descriptor.
+mapping "device|runtime|op|dtype|shape" to the chosen descriptor, where device
+is the GPU's name and architecture (``device_name``) and runtime the HIP
+version and the library's ABI version (``runtime_tag``).
 """
 
 from __future__ import annotations
@@ -129,8 +131,28 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "dpia", "tune.json"))
 
 
+def runtime_tag() -> str:
+    """The software a tuned choice was measured with: the HIP runtime torch
+    was built against and the library's ABI version."""
+    try:
+        import torch
+        hip = torch.version.hip or "none"
+    except ImportError:
+        hip = "none"
+    from ._lib import ABI_VERSION
+    return f"hip-{hip}|dpia-abi-{ABI_VERSION}"
+
+
+def device_name(device=None) -> str:
+    """Name and architecture of a GPU (e.g. 'AMD Instinct MI355X gfx950')."""
+    import torch
+    p = torch.cuda.get_device_properties(device if device is not None else 0)
+    return f"{p.name} {getattr(p, 'gcnArchName', '')}".strip()
+
+
 def _key(device: str, op: int, dtype: int, shape: Tuple[int, ...]) -> str:
-    return f"{device}|{op}|{dtype}|{'x'.join(str(v) for v in shape)}"
+    # a choice is only reused on the same device under the same software
+    return f"{device}|{runtime_tag()}|{op}|{dtype}|{'x'.join(str(v) for v in shape)}"
 
 
 def load_cache() -> Dict[str, Dict]:
