@@ -639,10 +639,9 @@ def _meta(name):
 ])
 def test_generated_reductions_equal_oracle_and_library(name, strategy):
     # a descriptor printed as its expression, compiled by the generator: the
-    # same bits as the oracle's evaluation of that text and as the library's
-    # hand-written kernels for the descriptor
+    # same bits as the oracle's expression for the descriptor and as the
+    # library's hand-written kernels for it
     import torch
-    from oracle import eval_numpy
     meta = _meta(name)
     n = meta["inputs"]["xs"][1][0]
     s = dp.Strategy(**strategy)
@@ -657,8 +656,12 @@ def test_generated_reductions_equal_oracle_and_library(name, strategy):
     out = prog.run(feed)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in out.items()}
-    args = {"xs": x, "ys": y} if "ys" in meta["inputs"] else {"xs": x}
-    want = eval_numpy.evaluate(meta["expression"], args, num=meta["num"])
+    # expected: the oracle's own expression for the descriptor (its builder,
+    # not the library's printed text)
+    if name.startswith("asum"):
+        want = S.asum(x, to_plan(s))
+    else:
+        want = S.dot(x, y, to_plan(s), num=meta["num"])
     res = got["out"][0]
     if meta["num"] == "u32":
         res = res.view(np.uint32)
@@ -673,7 +676,6 @@ def test_generated_reductions_equal_oracle_and_library(name, strategy):
 
 def test_generated_sec62_dot_equals_library_chunks():
     import torch
-    from oracle import eval_numpy
     meta = _meta("dot_sec62_chunks")
     n = meta["inputs"]["xs"][1][0]
     x, y = synthetic.dot_inputs(n, synthetic.SEEDS["scale"])
@@ -684,14 +686,14 @@ def test_generated_sec62_dot_equals_library_chunks():
     torch.cuda.synchronize()
     got = out["out"].cpu().numpy()
     assert_same_bits(got, c.cpu().numpy().view(np.float32), "Sec. 6.2 generated vs library")
-    assert_same_bits(got, eval_numpy.evaluate(meta["expression"], {"xs": x, "ys": y}),
-                     "Sec. 6.2 generated vs oracle")
+    # the oracle's builder for the same strategy (C=2048, L=64, V=4, no
+    # work-group combine): its chunk values, lane by lane
+    assert_same_bits(got, S.dot_chunks(x, y, to_plan(s)), "Sec. 6.2 generated vs oracle")
     prog.close()
 
 
 def test_generated_gemv_and_scal():
     import torch
-    from oracle import eval_numpy
     A, x = synthetic.gemv_inputs(96, 1024, synthetic.SEEDS["scale"])
     prog = _generated("gemv_strided_tree")
     y = prog.run({"A": cuda(A), "x": cuda(x)})["out"]
@@ -716,12 +718,16 @@ def test_generated_headline_dot_and_gemv_at_full_size():
     r = prog.run({"xs": cuda(x), "ys": cuda(y)})["out"]
     torch.cuda.synchronize()
     assert_same_bits(r.cpu().numpy()[0], gpu_dot(x, y, catalog.HEADLINE_DOT), "generated dot")
+    assert_same_bits(r.cpu().numpy()[0], S.dot(x, y, to_plan(catalog.HEADLINE_DOT)),
+                     "generated dot vs oracle")
     prog.close()
     A, xv = synthetic.gemv_inputs(8192, 8192, synthetic.SEEDS["scale"])
     prog = _generated("gemv_headline_8192")
     g = prog.run({"A": cuda(A), "x": cuda(xv)})["out"]
     torch.cuda.synchronize()
     assert_same_bits(g.cpu().numpy(), gpu_gemv(A, xv, catalog.HEADLINE_GEMV), "generated gemv")
+    assert_same_bits(g.cpu().numpy(), S.gemv(A, xv, to_plan(catalog.HEADLINE_GEMV)),
+                     "generated gemv vs oracle")
     prog.close()
 
 
