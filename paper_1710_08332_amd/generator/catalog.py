@@ -48,6 +48,16 @@ def programs() -> List[Tuple[str, str, Dict, str]]:
     dot("dot_v4_strided_tree", Strategy(seq_len=8, local_size=64, order=STRIDED, vec_width=4),
         4 * 8 * 64 * 11)
     dot("dot_headline_2p26", HEADLINE_DOT, 1 << 26)
+    # Sec. 6.3 hoisting: every work-group's lane values in global memory
+    # (toGlobal inside mapWorkgroup), one copy per work-group, folded in
+    # lane order by the work-group; the sequential-combine strategy C=4,
+    # L=64, contiguous
+    add, mul_add = "(lam (e a) (+ e a))", "(lam (z a) (+ (* (fst z) (snd z)) a))"
+    ng = 4 * 64 * 300
+    out.append(("dot_global_lanes",
+                f"(reduceSeq {add} 0 (mapWorkgroup (lam (ch) (reduceSeq {add} 0 ((toGlobal (lam (c)"
+                f" (mapLocal (lam (row) (reduceSeq {mul_add} 0 row)) (split 4 c)))) ch)))"
+                f" (split 256 (zip xs ys))))", _vec_inputs(ng), "f32"))
     s = Strategy(seq_len=8, local_size=128, order=STRIDED)
     out.append(("asum_strided_tree", P.asum_text(s, 8 * 128 * 19), _vec_inputs(8 * 128 * 19,
                                                                               names=("xs",)),

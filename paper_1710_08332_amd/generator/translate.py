@@ -26,10 +26,14 @@ OpenCL's memory levels: outside every parallel loop it is global memory
 (hoisted to a workspace buffer that is a kernel argument), inside a
 mapWorkgroup body and outside any mapLocal an array is local memory (hoisted
 to the top of the kernel: one copy per work-group) and a number is private,
-and inside a work-item it is private.  A toLocal / toPrivate / toGlobal
-annotation never changes a value (Sec. 6.1), so placement can follow these
-rules alone; a choice that would break sharing (a private array written by
-several work-items) is never made.
+and inside a work-item it is private.  A toGlobal annotation puts the value
+of the function it wraps in global memory wherever it is: inside parallel
+loops the temporary is hoisted out of them as the paper's rule for hoisting
+`new` out of a parallel loop has it, to one workspace buffer whose size is
+the temporary's times the extents of the enclosing parallel loops, each
+iteration using its own copy.  The annotations never change a value (Sec.
+6.1); a choice that would break sharing (a private array written by several
+work-items) is never made.
 
 Stage III: every top-level parallel loop becomes one kernel; host-level
 sequential code between them becomes a kernel run by a single work-item.
@@ -207,6 +211,8 @@ class Translator:
         self.dims: Dict[str, tuple] = {}
         self.scalars: set = set()       # private numbers declared as C scalars
         self.env: Dict[str, object] = {}
+        # the parallel loops around the code being translated: (index, extent)
+        self.par: List[Tuple[str, int]] = []
         self.input_types: Dict[str, Type] = {}
         for name, (et, shape) in inputs.items():
             ty: Type = Num(CTYPES[et])
@@ -341,17 +347,23 @@ class Translator:
     def new_var(self, ty: Type, space: str, out: list, base: str = "t"):
         name = self.fresh(base)
         leaves = _leaves(ty, (), name, [])
+        # A global temporary inside parallel loops is hoisted out of them
+        # (Sec. 6.3): one buffer with a copy per iteration of every
+        # enclosing parallel loop -- its size scaled by their extents -- and
+        # each iteration uses its own copy, indexed by the loops' indices.
+        scale = tuple(n for _, n in self.par) if space == "global" else ()
+        prefix = [ir.IVar(i) for i, _ in self.par] if space == "global" else []
         for leaf, ctype, dims in leaves:
-            self.dims[leaf] = dims
+            self.dims[leaf] = scale + dims
             size = _prod(dims) if dims else 0
             if space == "global":
-                self.buffers.append(Buffer(leaf, ctype, max(1, size), "ws"))
+                self.buffers.append(Buffer(leaf, ctype, max(1, _prod(scale) * max(1, size)), "ws"))
             else:
                 if size == 0 and space == "private":
                     self.scalars.add(leaf)
                 out.append(Decl(leaf, ctype, size, space))
-        return (_view(ty, name, [], self.dims, self.scalars),
-                _acceptor(ty, name, [], self.dims, self.scalars, space))
+        return (_view(ty, name, list(prefix), self.dims, self.scalars),
+                _acceptor(ty, name, list(prefix), self.dims, self.scalars, space))
 
     def copy(self, v: Value, a: Acc, out: list, ctx: str):
         """a := v, element by element (a sequential loop over arrays)."""
@@ -370,7 +382,7 @@ class Translator:
             out.append(For(i, a.ty.n, body))
 
     def space_for(self, ty: Type, ctx: str, hint: Optional[str]) -> str:
-        if ctx == "host":
+        if ctx == "host" or hint == "toGlobal":
             return "global"
         if ctx == "group" and (isinstance(ty, Arr) or hint == "toLocal"):
             return "local"
@@ -388,7 +400,11 @@ class Translator:
                 i = self.fresh("g" if level == "workgroup" else ("l" if level else "k"))
                 body: list = []
                 inner = {"workgroup": "group", "local": "item", "global": "item"}.get(level, ctx)
+                if level:
+                    self.par.append((i, xs.ty.n))
                 self.acc_app(f, [xs.get(ir.IVar(i))], a.at(ir.IVar(i)), body, inner)
+                if level:
+                    self.par.pop()
                 out.append(ParFor(level, i, xs.ty.n, body) if level else For(i, xs.ty.n, body))
                 return
             if h in REDUCES:

@@ -363,3 +363,58 @@ def test_a_reduction_over_rows_is_not_paired():
     feed = {"A": A, "x": x}
     want = np.atleast_1d(eval_numpy.evaluate(text, feed, num="f32"))
     assert same(GI.run(prog, feed)["out"], want)
+
+
+# ------------------------------------------------ hoisting out of parallel loops (Sec. 6.3)
+MULADD = "(lam (z a) (+ (* (fst z) (snd z)) a))"
+ADD = "(lam (e a) (+ e a))"
+
+
+def _global_lanes_in_groups(C, L, W):
+    # every work-group's lane values in global memory (toGlobal inside
+    # mapWorkgroup), folded in lane order by the work-group
+    return (f"(reduceSeq {ADD} 0 (mapWorkgroup (lam (ch) (reduceSeq {ADD} 0 "
+            f"((toGlobal (lam (c) (mapLocal (lam (row) (reduceSeq {MULADD} 0 row)) (split {C} c))))"
+            f" ch))) (split {W} (zip xs ys))))")
+
+
+def _global_lane_values(C, L, W):
+    # each lane's value in global memory (toGlobal inside mapLocal inside
+    # mapWorkgroup), then the lanes joined
+    return (f"(reduceSeq {ADD} 0 (join (mapWorkgroup (lam (ch) (mapLocal (lam (row) "
+            f"((toGlobal (lam (r) (reduceSeq {MULADD} 0 r))) row)) (split {C} ch)))"
+            f" (split {W} (zip xs ys)))))")
+
+
+@pytest.mark.parametrize("build", [_global_lanes_in_groups, _global_lane_values])
+def test_global_temporaries_in_parallel_loops_are_scaled_by_the_iterations(build):
+    C, L, G = 4, 8, 5
+    W = C * L
+    n = W * G
+    text = build(C, L, W)
+    x, y = disc(17, n)
+    prog = T.translate(text, {"xs": ("f32", (n,)), "ys": ("f32", (n,))})
+    ws = [b for b in prog.buffers if b.kind == "ws"]
+    # one copy of the temporary per iteration of the enclosing parallel
+    # loops: L lane values per work-group times G work-groups, or one value
+    # per lane times L lanes times G work-groups (a single shared copy would
+    # hold L values, or one)
+    assert any(b.elems == G * L for b in ws), [(b.name, b.elems) for b in ws]
+    assert same(GI.run(prog, {"xs": x, "ys": y})["out"][0],
+                eval_numpy.evaluate(text, {"xs": x, "ys": y}))
+    # the annotation changes no value: the same expression without it
+    plain = text.replace("(toGlobal ", "(toPrivate ")
+    assert same(eval_numpy.evaluate(plain, {"xs": x, "ys": y}),
+                eval_numpy.evaluate(text, {"xs": x, "ys": y}))
+
+
+def test_global_temporary_of_a_work_group_is_read_after_its_lanes_wrote_it():
+    # the group-level fold reads the lane values other work-items wrote to
+    # the work-group's copy: the oracle's sequential combine of the same lanes
+    C, L, G = 3, 16, 7
+    W = C * L
+    text = _global_lanes_in_groups(C, L, W)
+    x, y = disc(23, W * G)
+    prog = T.translate(text, {"xs": ("f32", (W * G,)), "ys": ("f32", (W * G,))})
+    got = GI.run(prog, {"xs": x, "ys": y})["out"][0]
+    assert same(got, S.dot(x, y, S.Plan(seq=C, lanes=L, order="contiguous", combine="seq")))

@@ -63,9 +63,10 @@ def test_every_catalogued_text_is_the_printer_output_for_its_descriptor():
     texts = {name: text for name, text, _, _ in catalog.programs()}
     assert set(CATALOGUE) <= set(texts)
     # the rest are not printed from descriptors: the paper's own Sec. 6.2
-    # expression, a map (scal) and the decoders
+    # expression, a map (scal), the decoders and a hoisting case
     assert set(texts) - set(CATALOGUE) == {"dot_sec62_chunks", "scal_global",
-                                           "decode_bf16_all", "decode_fp8_all"}
+                                           "decode_bf16_all", "decode_fp8_all",
+                                           "dot_global_lanes"}
     for name, (kind, s, args) in CATALOGUE.items():
         assert texts[name] == _print(kind, s, args), name
 

@@ -843,3 +843,21 @@ def test_contiguous_low_precision_gemv_staged_and_ragged(fmt, kw, k):
     want = S.gemv(np.ascontiguousarray(codes[:, :k]), x[:k], to_plan(s), a_format=fmt,
                   scale=scale)
     assert_same_bits(y.cpu().numpy(), want, f"{fmt} contiguous gemv k={k} {kw}")
+
+
+def test_generated_global_temporaries_hoisted_out_of_work_groups():
+    # toGlobal inside mapWorkgroup: one copy of the lane values per
+    # work-group (Sec. 6.3), written by the lanes, folded by the work-group;
+    # 300 work-groups at once would corrupt a shared copy
+    import torch
+    meta = _meta("dot_global_lanes")
+    n = meta["inputs"]["xs"][1][0]
+    ws = [b for b in meta["buffers"] if b["kind"] == "ws"]
+    assert any(b["elems"] == 300 * 64 for b in ws)
+    x, y = discriminating(31, n)
+    prog = _generated("dot_global_lanes")
+    out = prog.run({"xs": cuda(x), "ys": cuda(y)})
+    torch.cuda.synchronize()
+    want = S.dot(x, y, S.Plan(seq=4, lanes=64, order="contiguous", combine="seq"))
+    assert_same_bits(out["out"].cpu().numpy()[0], want, "hoisted global lanes vs oracle")
+    prog.close()
