@@ -188,9 +188,25 @@ def workload_small(args):
         fn()
         torch.cuda.synchronize()
         res[name] = out.cpu().numpy()[0]
+        # the ceiling for these bytes when they are cache-resident: the plain
+        # read kernel over a buffer of the same size, back to back (warm),
+        # best of five grids
+        buf = torch.ones((nbytes - 4) // 4, dtype=torch.int32, device="cuda")   # the inputs
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        sink = torch.empty(cus * 16, dtype=torch.int32, device="cuda")
+        ceil_us = min(time_us(lambda g=g: dp.read_stream(buf, g, sink=sink), reps=100)[0]
+                      for g in (cus // 4, cus // 2, cus, 2 * cus, 4 * cus))
+        one = s.with_(passes=1)
+        ws1 = dp.workspace(one, dp.OP_DOT, dp.F32, 0, n)
+        run1 = ((lambda: dp.dot(xt, yt, one, out=out, ws=ws1)) if name == "dot"
+                else (lambda: dp.asum(xt, one, out=out, ws=ws1)))
+        med1 = time_us(run1, reps=100)[0]
         _line(workload="small", op=name, n=n, strategy=strategy_text(s), us=round(med, 2),
               p10=round(p10, 2), p90=round(p90, 2), gbs=_gbs(nbytes, med),
-              note="cache-resident (2^20 elements fit in L2/MALL): no HBM claim")
+              one_pass_us=round(med1, 2), warm_read_ceiling_us=round(ceil_us, 2),
+              pct_of_warm_read_ceiling=round(100 * ceil_us / med, 1),
+              note="cache-resident (2^20 elements fit in L2/MALL): no HBM claim; the ceiling is "
+                   "the read kernel over the same bytes, warm")
     if not args.no_cpu_baseline:
         from oracle import strategies as S
         from tests.gpu_util import to_plan

@@ -341,10 +341,17 @@ dpia_status gemv_impl(const char* name, const dpia_strategy* s, dpia_dtype a_dt,
   };
   switch (a_dt) {
     case DPIA_F32:
-      e = launch_gemv<GemvF32, 4>(
-          p, with_epilogue(GemvF32{static_cast<const float*>(A), static_cast<const float*>(x),
-                                   nullptr, static_cast<float*>(y)}),
-          m, lda, hs);
+      if (p.order == DPIA_ORDER_STRIDED && p.team < 4)
+        e = launch_gemv<GemvF32Cached, 4>(
+            p, with_epilogue(GemvF32Cached{static_cast<const float*>(A),
+                                           static_cast<const float*>(x), nullptr,
+                                           static_cast<float*>(y)}),
+            m, lda, hs);
+      else
+        e = launch_gemv<GemvF32, 4>(
+            p, with_epilogue(GemvF32{static_cast<const float*>(A), static_cast<const float*>(x),
+                                     nullptr, static_cast<float*>(y)}),
+            m, lda, hs);
       break;
     case DPIA_BF16:
       e = launch_gemv<GemvBF16, 8>(

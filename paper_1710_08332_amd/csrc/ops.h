@@ -191,8 +191,9 @@ __device__ __forceinline__ void fp8_to_f32(const uint8_t (&c)[NV], float (&f)[NV
 #define DPIA_FP8_BATCH_ELEMS 16
 #endif
 
-// BATCH: elements per load batch (0: the format's default).
-template <typename E, class Decode, int BATCH = 0>
+// BATCH: elements per load batch (0: the format's default).  STREAM: 1 or 0
+// to load A with non-temporal or cached loads (-1: the format's default).
+template <typename E, class Decode, int BATCH = 0, int STREAM = -1>
 struct GemvF32Acc {
   using Arith = PlainF32;
   using T = float;
@@ -209,7 +210,7 @@ struct GemvF32Acc {
       BATCH ? BATCH
             : (kF32 ? DPIA_F32_GEMV_BATCH_ELEMS
                     : (sizeof(E) == 2 ? DPIA_BF16_BATCH_ELEMS : DPIA_FP8_BATCH_ELEMS));
-  static constexpr bool kStreamA = !kF32 || DPIA_F32_GEMV_STREAM_A;
+  static constexpr bool kStreamA = STREAM >= 0 ? STREAM != 0 : (!kF32 || DPIA_F32_GEMV_STREAM_A);
   struct View {
     static constexpr bool kStageable = std::is_same<E, float>::value;
     // 1- and 2-byte codes: staged by contiguous_staged_codes
@@ -324,6 +325,12 @@ struct DecodeFP8 {
 };
 
 using GemvF32 = GemvF32Acc<float, DecodeF32>;
+// binary32 rows read by strided teams of fewer than 4 threads: each load
+// instruction of a team covers under 64 bytes of its row, and the rest of the
+// line is read by the team's next loads, so A stays cached (measured at
+// 16384^2: C=8192 L=2 1294 us cached, 3947 us non-temporal; C=1024 L=8 with
+// two row parts 252 against 524 us; teams of 4 and more gain or break even)
+using GemvF32Cached = GemvF32Acc<float, DecodeF32, 0, 0>;
 using GemvBF16 = GemvF32Acc<uint16_t, DecodeBF16>;
 using GemvFP8 = GemvF32Acc<uint8_t, DecodeFP8>;
 // fp8 rows with long lanes: four 16-byte loads per row in flight (measured
