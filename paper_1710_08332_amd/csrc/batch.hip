@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kBatchThreads)
       // complete in memory; fold them in chunk order (the fold's own
       // barriers also free its LDS before the next tile)
       const BInst I = insts[fold];
-      final_fold<PlainF32, kFinalPlain, true>(partials + I.part_off, I.G, I.out, 0, lds);
+      final_fold<PlainF32, kFinalPlain, true, 8, 4>(partials + I.part_off, I.G, I.out, 0, lds);
       if (threadIdx.x == 0)
         __hip_atomic_store(arrive + fold, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

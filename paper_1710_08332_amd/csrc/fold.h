@@ -2,6 +2,8 @@
 // the reduction kernels and the batched engine.
 #pragma once
 
+#include <type_traits>
+
 #include "device.h"
 #include "plan.h"
 
@@ -18,17 +20,27 @@ enum : int {
 };
 
 // The outer reduceSeq over the G chunk values, from the literal 0, in chunk
-// order, by one thread.  The work-group stages blocks of chunk values in LDS
-// (coalesced), then thread 0 reads them back 32 at a time into registers
-// and folds them in order.
+// order, by one thread.  `buf` (kFoldBlock values of LDS) holds two halves.
+// The work-group copies the chunk values into them a step at a time; while
+// thread 0 folds one half, every thread already has its loads of the next
+// step's values in flight (issued together, into registers), and writes them
+// to the other half when the fold of this one has been issued.  Thread 0
+// reads its half back R values at a time, the next R requested before the
+// current R are added, so the chain of additions waits on memory once per
+// step and on LDS once per block of 16 groups.
 // COHERENT: the chunk values are read with device-coherent loads (values
 // written by other work-groups of the same launch with store_coherent).
-// R: values thread 0 reads from LDS into registers at a time (fewer
-// registers where the fold shares a kernel with other work).
-template <class A, int FINAL, bool COHERENT = false, int R = 32>
+// R: values thread 0 holds in registers per group (three groups at once);
+// LOADS: loads in flight per thread, at most.  Kernels that carry the fold
+// beside other work (1 pass) pass smaller ones, so that the fold does not
+// raise their register count.
+template <class A, int FINAL, bool COHERENT = false,
+          int R = (sizeof(typename A::T) > 4 ? 8 : 16), int LOADS = 8>
 __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
                            typename A::T* buf) {
   using T = typename A::T;
+  constexpr int kHalf = kFoldBlock / 2;
+  constexpr int kLoads = LOADS;
   T acc = A::zero();
   double acc64 = 0.0;
   auto fold1 = [&](const T& e) {
@@ -39,22 +51,78 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
     else
       acc = A::add(e, acc);
   };
-  for (int64_t b = 0; b < G; b += kFoldBlock) {
-    const int cnt = static_cast<int>(G - b < kFoldBlock ? G - b : kFoldBlock);
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-      buf[i] = COHERENT ? load_coherent(partials + b + i) : partials[b + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int i = 0;
-      for (; i + R <= cnt; i += R) {
-        T r[R];
+  const int nt = static_cast<int>(blockDim.x);
+  const int step = nt * kLoads < kHalf ? nt * kLoads : kHalf;   // values per half
+  const int mine = (step + nt - 1) / nt;                        // loads per thread
+  T reg[kLoads];
+  // this thread's values of [b, b + step), clamped into [0, G) (uniform
+  // trip count: every load is issued before any is waited for)
+  auto fetch = [&](int64_t b) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) r[j] = buf[i + j];
-#pragma unroll
-        for (int j = 0; j < R; ++j) fold1(r[j]);
+    for (int k = 0; k < kLoads; ++k) {
+      if (k < mine) {
+        int64_t i = b + threadIdx.x + static_cast<int64_t>(k) * nt;
+        i = i < G ? i : G - 1;
+        reg[k] = COHERENT ? load_coherent(partials + i) : partials[i];
       }
-      for (; i < cnt; ++i) fold1(buf[i]);
     }
+  };
+  auto put = [&](T* half, int64_t b) {
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      const int i = static_cast<int>(threadIdx.x) + k * nt;
+      if (k < mine && i < step && b + i < G) half[i] = reg[k];
+    }
+  };
+  // thread 0: the fold of half[0 .. cnt) in index order, in unrolled blocks
+  // of kBlock groups of R values.  Within a block the LDS reads of the next
+  // two groups are in flight while the current group is added (straight-line
+  // code, so the compiler waits for exactly the group it adds); the
+  // scheduling barrier keeps the reads from being sunk down to their uses.
+  auto fold_half = [&](const T* half, int cnt) {
+    constexpr int kBlock = 16;
+    T r[3][R];
+    auto read = [&](T (&dst)[R], int at) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) dst[j] = half[at + j];
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    int i = 0;
+    if constexpr (std::is_integral_v<T>) {
+      // addition modulo 2^32 is associative: any order gives the same
+      // bits, and the compiler would reorder an unrolled block anyway
+      for (; i < cnt; ++i) fold1(half[i]);
+      return;
+    }
+    for (; i + kBlock * R <= cnt; i += kBlock * R) {
+      read(r[0], i);
+      read(r[1], i + R);
+#pragma unroll
+      for (int grp = 0; grp < kBlock; ++grp) {
+        if (grp + 2 < kBlock) read(r[(grp + 2) % 3], i + (grp + 2) * R);
+#pragma unroll
+        for (int j = 0; j < R; ++j) fold1(r[grp % 3][j]);
+      }
+    }
+    for (; i + R <= cnt; i += R) {
+      read(r[0], i);
+#pragma unroll
+      for (int j = 0; j < R; ++j) fold1(r[0][j]);
+    }
+    for (; i < cnt; ++i) fold1(half[i]);
+  };
+  if (G > 0) {
+    fetch(0);
+    put(buf, 0);
+  }
+  __syncthreads();
+  int h = 0;
+  for (int64_t b = 0; b < G; b += step, h ^= 1) {
+    const int cnt = static_cast<int>(G - b < step ? G - b : step);
+    const bool more = b + step < G;
+    if (more) fetch(b + step);
+    if (threadIdx.x == 0) fold_half(buf + h * kHalf, cnt);
+    if (more) put(buf + (h ^ 1) * kHalf, b + step);
     __syncthreads();
   }
   if (threadIdx.x == 0) {

@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
     }
     __syncthreads();
     if (is_last) {
-      final_fold<typename Op::Arith, FINAL, true>(partials, a.values, a.out, a.out_f64, lds);
+      final_fold<typename Op::Arith, FINAL, true, (sizeof(T) > 4 ? 4 : 8), 4>(
+          partials, a.values, a.out, a.out_f64, lds);
       if (threadIdx.x == 0)   // leave the counter at zero for the next call
         __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

@@ -3,7 +3,8 @@ instances reach: compensated accumulators merged across wavefronts through
 LDS (teams of 128 and 256 threads), the fp8 gemv that reduces 4 rows per team
 with 64-element batches, a batch of instances drawn like the benchmark's
 (lengths up to 2^20, gemv sides up to 4096), and staged contiguous folds
-with an odd number of tiles.
+with an odd number of tiles, and the outer fold of many chunk values at the
+boundaries of the steps it copies them in.
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -273,3 +274,35 @@ def test_batch_runs_back_to_back_clear_their_counters():
         for i, (d, want) in enumerate(zip(insts, single)):
             assert_same_bits(d["out"].cpu().numpy(), want, f"run {run} instance {i}")
     plan.close()
+
+
+# ------------------------------------------------ the outer fold, step edges
+# The fold copies the chunk values into LDS a step at a time (256 values per
+# step for a 64-thread work-group folding inside a 1-pass launch, 1024 for
+# the 256-thread fold kernel of 2 passes and for wide 1-pass work-groups),
+# with the next step's loads in flight while the current one is folded.  G
+# around those sizes, with chunk values of 4 bytes (plain) and 8 (Kahan and
+# Sum2 pairs, folded in binary64), on inputs whose sum depends on the order.
+FOLD_STRATS = [
+    # W = 1: one chunk per element, 64-thread work-groups
+    dict(seq_len=1, local_size=1, order=T_, wg_combine=dp.SEQ),
+    # W = 1024: a 256-thread team per chunk
+    dict(seq_len=1, local_size=1024, order=T_),
+]
+
+
+@pytest.mark.parametrize("G", [1, 255, 256, 257, 1023, 1024, 1025, 2048, 2049, 3333])
+@pytest.mark.parametrize("kw", FOLD_STRATS, ids=["W1", "W1024"])
+@pytest.mark.parametrize("accum", [dp.PLAIN, dp.KAHAN, dp.SUM2], ids=["plain", "kahan", "sum2"])
+def test_outer_fold_at_the_edges_of_its_steps(G, kw, accum):
+    s = dp.Strategy(**kw, accum=accum, final_f64=1 if accum != dp.PLAIN else 0)
+    W = kw["seq_len"] * kw["local_size"]
+    if W > 1 and G > 1100:
+        pytest.skip("the wide chunks reach the same steps at G <= 1025")
+    n = G * W
+    print(f"outer fold G={G} W={W} accum={accum}", flush=True)
+    xd, yd = discriminating(70 + G % 13, n)
+    want = S.dot(xd, yd, to_plan(s))
+    for passes in (1, 2):
+        assert_same_bits(gpu_dot(xd, yd, s.with_(passes=passes)), want,
+                         f"G={G} W={W} passes={passes}")
