@@ -1,0 +1,175 @@
+// Contiguous lanes staged through LDS and fed by loader wavefronts.
+//
+// A strategy with one 64-lane team per chunk and fewer chunks than compute
+// units (the Sec. 6.2 form: 128 chunks of 64 vector lanes) gives each busy
+// compute unit a single wavefront, and one wavefront can keep only a couple
+// of staged tiles of loads in flight.  Here the work-group carries
+// kFedLoaders loader wavefronts beside the wavefront that folds.  The loaders
+// split every tile of the lane rows between them (each issues the same
+// 16-byte loads of its own rows, so all of them run the same straight-line
+// code), keep several tiles in flight, and write each tile into a two-slot
+// LDS ring one round ahead of the fold; one work-group barrier per tile
+// separates the rounds.  Which elements each lane folds, and in which order,
+// is exactly what contiguous_staged folds: the loaders only move data.
+#pragma once
+
+#include "device.h"
+
+namespace dpia {
+
+#ifndef DPIA_FED_LOADERS
+#define DPIA_FED_LOADERS 4
+#endif
+#ifndef DPIA_FED_STAGE
+#define DPIA_FED_STAGE 64
+#endif
+constexpr int kFedLoaders = DPIA_FED_LOADERS;
+// Elements of a lane row per tile, and the LDS row stride in floats (an odd
+// number of 16-byte units): 256 contiguous bytes of a row per load
+// instruction, and half the rounds of 32-element tiles (measured equal to
+// them on the Sec. 6.2 form; the bursts below are what the rows' DRAM pages
+// needed).
+constexpr int kFedStage = DPIA_FED_STAGE;
+constexpr int kFedRow = kFedStage + 4;
+constexpr int kFedVec = kFedStage / 4;                // 16-byte parts of a row tile
+static_assert(kWave % kFedVec == 0, "a load instruction covers whole row tiles");
+constexpr int kFedRowsPerLoad = kWave / kFedVec;
+// The deepest pipeline (tiles in flight) of any row count.
+constexpr int kFedMaxDepth = 16;
+// Tiles each loader requests back to back: consecutive pieces of its rows.
+// The lane rows lie C * V elements apart, so every row is a stream of its
+// own, and requesting kFedBurst tiles of a row together lets a DRAM page
+// serve kFedBurst * 256 bytes of it rather than 256 (measured on the Sec. 6.2
+// form at 2^26, kernel trace medians: 1, 2 and 4 tiles 103.8, 99.4 and 90.7
+// us on one box; 8 tiles, the pipeline emptying before each burst, 108.2
+// against 97.8 us for 4 on another).  At most the depth.
+#ifndef DPIA_FED_BURST
+#define DPIA_FED_BURST 4
+#endif
+constexpr int kFedBurst = DPIA_FED_BURST;
+
+// LDS floats of the ring: two slots, each two operands x 64 rows (also the
+// staging region of contiguous_staged for a ragged chunk).
+constexpr int fed_ring_floats() { return 2 * 2 * kWave * kFedRow; }
+static_assert(fed_ring_floats() >= stage_floats(kWave), "the ring holds a staging region");
+
+// ROWS lane rows (row0 .. row0 + ROWS - 1) of one chunk whose 64 lane rows
+// are whole: Cel elements each, Cel / kFedStage tiles, a multiple of the
+// depth.  Every thread of the work-group calls this; wave 0 folds (lane l <
+// ROWS folds row row0 + l into acc), waves 1 .. kFedLoaders load.  Local row
+// r of operand o in ring slot s starts at ((s * NOPS + o) * 64 + r) *
+// kFedRow floats.  An uncombined strategy may split a chunk's rows over
+// several work-groups (ROWS < 64): its lanes' values are independent.
+template <int ROWS, int NOPS>
+constexpr int fed_per() { return ROWS / kFedRowsPerLoad / kFedLoaders; }
+// Tiles in flight: every loader keeps 32 sixteen-byte loads outstanding, up
+// to kFedMaxDepth tiles.
+template <int ROWS, int NOPS>
+constexpr int fed_depth() {
+  return 32 / (NOPS * fed_per<ROWS, NOPS>()) < kFedMaxDepth ? 32 / (NOPS * fed_per<ROWS, NOPS>())
+                                                            : kFedMaxDepth;
+}
+
+template <class Op, int VEC, int ROWS, class View>
+__device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
+                                         float* ring, typename Op::T (&acc)[VEC]) {
+  constexpr int NOPS = View::kOps;
+  constexpr int kPer = fed_per<ROWS, NOPS>();       // load instructions per operand per tile
+  constexpr int D = fed_depth<ROWS, NOPS>();
+  static_assert(kPer >= 1 && kPer * kFedLoaders * kFedRowsPerLoad == ROWS,
+                "the loaders split a tile's loads evenly");
+  static_assert(D % 2 == 0 && D <= kFedMaxDepth, "a round's ring slot is the parity of its tile");
+  constexpr int B = kFedBurst < D ? kFedBurst : D;
+  static_assert(D % B == 0, "whole bursts of tiles");
+#pragma unroll
+  for (int j = 0; j < VEC; ++j) acc[j] = Op::Arith::zero();
+  const int part = lane % kFedVec;
+  // loader q = wave - 1 takes the tile's load instructions q*kPer .. q*kPer +
+  // kPer - 1; instruction i covers local rows i * kFedRowsPerLoad + lane / kFedVec
+  const int q = wave - 1;
+  const float* rowp[NOPS][kPer];
+  int rofs[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int r = (q * kPer + k) * kFedRowsPerLoad + lane / kFedVec;
+    rofs[k] = r * kFedRow + part * 4;
+#pragma unroll
+    for (int o = 0; o < NOPS; ++o) rowp[o][k] = view.operand(o) + (row0 + r) * Cel + part * 4;
+  }
+  f32x4 regs[D][NOPS][kPer];
+  auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        rg[o][k] = ld<DPIA_NT_LOADS != 0>(reinterpret_cast<const f32x4*>(rowp[o][k] +
+                                                                          tile * kFedStage));
+    // tiles are requested in round order, so that each round waits for its
+    // own tile only (the scheduler would interleave the sets' loads)
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto put = [&](const f32x4 (&rg)[NOPS][kPer], int slot) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        *reinterpret_cast<f32x4*>(ring + (slot * NOPS + o) * kWave * kFedRow + rofs[k]) =
+            rg[o][k];
+  };
+  // row `lane` of a slot, in increasing element index; element e of the
+  // row belongs to component e % VEC
+  auto fold_slot = [&](int slot) {
+    if (ROWS < kWave && lane >= ROWS) return;
+#pragma unroll
+    for (int j = 0; j < kFedVec; ++j) {
+      f32x4 v[NOPS];
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        v[o] = *reinterpret_cast<const f32x4*>(
+            ring + ((slot * NOPS + o) * kWave + lane) * kFedRow + j * 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i % VEC] = Op::step(View::term(v, i), acc[i % VEC]);
+    }
+  };
+  // Round r (0 .. ntiles - 1, each ending with a work-group barrier): the
+  // loaders put tile r into slot r % 2 (register set r % D) and load tile
+  // r + D into that set; the folding wavefront folds tile r - 1.  One more
+  // round folds the last tile.  The two roles run in loops of their own, with
+  // the same ntiles + 1 barriers, so that the loaders' D register sets stay
+  // live in the loaders' loop alone (in a shared loop the compiler staged the
+  // loads through registers of the fold and waited for each one).
+  const int ntiles = Cel / kFedStage;
+  if (wave > 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) gload(regs[d], d);
+    int r0 = 0;
+    for (; r0 + D < ntiles; r0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        put(regs[d], d & 1);
+        if (d % B == B - 1) {
+          // the last B sets are free: their next tiles, back to back
+#pragma unroll
+          for (int b = d - B + 1; b <= d; ++b) gload(regs[b], r0 + b + D);
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {   // the last D tiles: nothing more to load
+      put(regs[d], d & 1);
+      __syncthreads();
+    }
+    __syncthreads();
+  } else {
+    __syncthreads();
+    for (int r = 1; r < ntiles; ++r) {
+      fold_slot((r - 1) & 1);
+      __syncthreads();
+    }
+    fold_slot((ntiles - 1) & 1);
+    __syncthreads();   // the ring is free for the next chunk
+  }
+}
+
+}  // namespace dpia

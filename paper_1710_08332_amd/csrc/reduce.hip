@@ -13,6 +13,7 @@
 #include <mutex>
 
 #include "device.h"
+#include "fed.h"
 #include "fold.h"
 #include "ops.h"
 #include "host.h"
@@ -92,6 +93,81 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
   }
 }
 
+#ifndef DPIA_FED
+#define DPIA_FED 1
+#endif
+
+// The mapWorkgroup level of a staged contiguous strategy with one 64-lane
+// team per chunk, fed by loader wavefronts (fed.h): wave 0 folds the lanes
+// and combines them, waves 1 .. kFedLoaders load.  An uncombined strategy
+// may give each work-group ROWS < 64 of a chunk's lanes (64 / ROWS
+// work-groups per chunk, on as many compute units).  A chunk whose lane rows
+// are not all whole (the last one, when W does not divide n) is folded
+// whole by wave 0 of its first work-group alone, as reduce_kernel folds it.
+// The same chunk values, the same 1-pass arrival and fold as reduce_kernel.
+template <class Op, int COMBINE, int FINAL, int VEC, int ROWS>
+__global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op op,
+                                                                               ReduceArgs a) {
+  using T = typename Op::T;
+  static_assert(COMBINE != kSeq, "a sequential combine has barriers of the team alone");
+  static_assert(ROWS == kWave || COMBINE == kNone, "only independent lanes are split");
+  constexpr int S = kWave / ROWS;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int is_last;
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  float* ring = reinterpret_cast<float*>(lds_raw + a.stage_off);
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  T* partials = static_cast<T*>(a.partials);
+  const int Cel = a.C * VEC;
+  for (int64_t w = blockIdx.x; w < a.items * S; w += gridDim.x) {
+    const int64_t g = w / S;
+    const int row0 = static_cast<int>(w % S) * ROWS;
+    const auto view = op.chunk(g, a.W);
+    const int64_t rest = a.n - g * a.W;
+    const int limit = static_cast<int>(rest < a.W ? rest : a.W);
+    const bool whole = limit == a.W;
+    T acc[VEC];
+    if (whole)
+      fed_fold<Op, VEC, ROWS>(view, Cel, wave, lane, row0, ring, acc);
+    else if (wave == 0 && row0 == 0)
+      contiguous_staged<Op, VEC>(view, true, lane, a.C, limit, acc, ring);
+    if (wave == 0 && (row0 == 0 || whole)) {
+      if constexpr (COMBINE == kNone) {
+        if (!whole || lane < ROWS) {
+          const int64_t l = g * a.L + (whole ? row0 : 0) + lane;
+#pragma unroll
+          for (int j = 0; j < VEC; ++j) store_coherent(partials + l * VEC + j, acc[j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+          T one[1] = {acc[j]};
+          const T c = combine_lanes<typename Op::Arith, 1, COMBINE>(one, lane, kWave, a.L, lds);
+          if (lane == 0) store_coherent(partials + g * VEC + j, c);
+        }
+      }
+    }
+    __syncthreads();   // the ring may be written for the next chunk
+  }
+  if (a.one_pass) {
+    wait_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev =
+          __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+      final_fold<typename Op::Arith, FINAL, true, (sizeof(T) > 4 ? 4 : 8), 4>(
+          partials, a.values, a.out, a.out_f64, lds);
+      if (threadIdx.x == 0)
+        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 template <class A, int FINAL>
 __global__ void __launch_bounds__(256) final_kernel(const typename A::T* partials, int64_t G,
                                                     void* out, int out_f64) {
@@ -152,9 +228,76 @@ hipError_t with_reduce_shape(const Plan& p, F&& f) {
 
 // The mapWorkgroup level: chunk values into `partials`; with one_pass the
 // last work-group also folds them into `out`.
+// Lane rows per work-group when a plan's chunks are folded by
+// fed_reduce_kernel (0: they are not): staged contiguous lanes, one 64-lane
+// team per chunk, a tree or no combine, and fewer chunks than compute units
+// (otherwise the launch has wavefronts enough).  An uncombined strategy
+// splits each chunk's rows over as many work-groups as the compute units
+// allow (2 or 4): a compute unit streams at most about 37 GB/s, so 128
+// chunks on 128 of them cannot reach the memory's rate.  A chunk's tiles
+// must be a multiple of the loaders' depth for that row count.
+template <int NOPS>
+int fed_rows(const Plan& p) {
+  if (!DPIA_FED || !p.stage || p.order != DPIA_ORDER_CONTIGUOUS) return 0;
+  if (p.op != DPIA_OP_DOT && p.op != DPIA_OP_ASUM) return 0;
+  if (p.team != kWave || p.teams_per_wg != 1 || p.combine == DPIA_COMBINE_SEQ) return 0;
+  if (p.V != 1 && p.V != 4) return 0;
+  const int64_t cus = device_cus();
+  if (p.items >= cus || (p.C * p.V) % kFedStage) return 0;
+  const int64_t ntiles = p.C * p.V / kFedStage;
+  auto fits = [&](int depth) { return ntiles >= depth && ntiles % depth == 0; };
+  if (p.combine == DPIA_COMBINE_NONE) {
+    if (p.items * 4 <= cus && fits(fed_depth<16, NOPS>())) return 16;
+    if (p.items * 2 <= cus && fits(fed_depth<32, NOPS>())) return 32;
+  }
+  return fits(fed_depth<kWave, NOPS>()) ? kWave : 0;
+}
+
+template <class Op, int FINAL>
+hipError_t launch_fed(const Plan& p, const Op& op, const ReduceArgs& a, int rows,
+                      hipStream_t stream) {
+  const int64_t grid = p.items * (kWave / rows);
+  size_t lds = p.stage_off + static_cast<size_t>(fed_ring_floats()) * sizeof(float);
+  const size_t fold = static_cast<size_t>(kFoldBlock) * sizeof(typename Op::T);
+  if (fold > lds) lds = fold;
+  lds = (lds + 16 + 15) / 16 * 16;
+  Op op_copy = op;
+  ReduceArgs a_copy = a;
+  void* args[] = {&op_copy, &a_copy};
+  auto go = [&](auto comb, auto vec, auto nrows) {
+    auto kern = fed_reduce_kernel<Op, decltype(comb)::value, FINAL, decltype(vec)::value,
+                                  decltype(nrows)::value>;
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                           dim3(kWave * (1 + kFedLoaders)), args, lds, stream);
+  };
+  if constexpr (FINAL != kFinalPlain) {
+    return go(ic<kTree>{}, ic<1>{}, ic<kWave>{});   // compensated: scalar, combined lanes
+  } else {
+    if (p.combine == DPIA_COMBINE_TREE)
+      return p.V == 4 ? go(ic<kTree>{}, ic<4>{}, ic<kWave>{})
+                      : go(ic<kTree>{}, ic<1>{}, ic<kWave>{});
+    auto by_rows = [&](auto vec) {
+      if (rows == 16) return go(ic<kNone>{}, vec, ic<16>{});
+      if (rows == 32) return go(ic<kNone>{}, vec, ic<32>{});
+      return go(ic<kNone>{}, vec, ic<kWave>{});
+    };
+    return p.V == 4 ? by_rows(ic<4>{}) : by_rows(ic<1>{});
+  }
+}
+
 template <class Op, int FINAL>
 hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
   if (p.items == 0) return hipSuccess;
+  // (the loaders keep the tiles in flight, so DotF32Deeper's second staged
+  // tile would only add registers; DotF32Deep serves strided lanes only)
+  if constexpr (std::is_same<Op, DotF32Deeper>::value) {
+    if (const int rows = fed_rows<2>(p))
+      return launch_fed<DotF32, FINAL>(p, DotF32{op.x, op.y}, a, rows, stream);
+  } else if constexpr (Op::View::kStageable && !std::is_same<Op, DotF32Deep>::value) {
+    const int rows = fed_rows<Op::View::kOps>(p);
+    if (rows && (FINAL == kFinalPlain || (p.V == 1 && p.combine == DPIA_COMBINE_TREE)))
+      return launch_fed<Op, FINAL>(p, op, a, rows, stream);
+  }
   const int64_t grid = grid_size(p);
   return with_reduce_shape<FINAL == kFinalPlain>(p, [&](auto ord, auto comb, auto nvc, auto vec) {
     constexpr int ORDER = decltype(ord)::value;

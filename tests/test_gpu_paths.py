@@ -3,8 +3,9 @@ instances reach: compensated accumulators merged across wavefronts through
 LDS (teams of 128 and 256 threads), the fp8 gemv that reduces 4 rows per team
 with 64-element batches, a batch of instances drawn like the benchmark's
 (lengths up to 2^20, gemv sides up to 4096), and staged contiguous folds
-with an odd number of tiles, and the outer fold of many chunk values at the
-boundaries of the steps it copies them in.
+with an odd number of tiles, the outer fold of many chunk values at the
+boundaries of the steps it copies them in, and staged contiguous lanes fed
+by loader wavefronts.
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -306,3 +307,58 @@ def test_outer_fold_at_the_edges_of_its_steps(G, kw, accum):
     for passes in (1, 2):
         assert_same_bits(gpu_dot(xd, yd, s.with_(passes=passes)), want,
                          f"G={G} W={W} passes={passes}")
+
+
+# ------------------------------------------------ loader wavefronts
+# Contiguous strategies with one 64-lane team per chunk and fewer chunks than
+# compute units are folded by work-groups whose other wavefronts only load
+# (whole lane rows of a multiple of the loaders' depth in tiles); a ragged
+# last chunk is folded whole by one wavefront.  Tree and uncombined,
+# scalar and V = 4 lanes, dot and asum, both pass counts; the chunk values
+# of uncombined strategies element by element.
+# (Tiles of 64 elements per lane row; uncombined chunks are split over 4, 2
+# or 1 work-groups of 16, 32 or 64 lanes as the chunk count allows.)
+FED = {
+    "C256-tree": dict(seq_len=256, local_size=64, order=C_),                      # 4 tiles
+    "C512-none": dict(seq_len=512, local_size=64, order=C_, wg_combine=dp.NONE),  # 8 tiles
+    "C1024-none": dict(seq_len=1024, local_size=64, order=C_, wg_combine=dp.NONE),
+    "C64-V4-tree": dict(seq_len=64, local_size=64, order=C_, vec_width=4),          # 4 tiles
+    "sec62": dict(seq_len=2048, local_size=64, order=C_, vec_width=4, wg_combine=dp.NONE),
+}
+
+
+@pytest.mark.parametrize("chunks,short", [(1, 0), (3, 0), (37, 0), (37, 24), (100, 0),
+                                          (200, 1000), (255, 0)])
+@pytest.mark.parametrize("name", sorted(FED))
+def test_contiguous_lanes_fed_by_loader_wavefronts(name, chunks, short):
+    import torch
+    s = dp.Strategy(**FED[name])
+    W = s.seq_len * s.local_size * s.vec_width
+    if W * chunks > (1 << 24):
+        pytest.skip("the long rows reach the same path with fewer chunks")
+    n = W * chunks - short
+    print(f"fed {name} chunks={chunks} n={n}", flush=True)
+    x, y = discriminating(80 + chunks, n)
+    p = to_plan(s)
+    for passes in (1, 2):
+        sp = s.with_(passes=passes)
+        assert_same_bits(gpu_dot(x, y, sp), S.dot(x, y, p), f"dot passes={passes}")
+        assert_same_bits(gpu_asum(x, sp), S.asum(x, p), f"asum passes={passes}")
+    if s.wg_combine == dp.NONE:
+        c = dp.chunks(dp.OP_DOT, s, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+        torch.cuda.synchronize()
+        assert_same_bits(c.cpu().numpy().view(np.float32), S.dot_chunks(x, y, p),
+                         "chunk values")
+
+
+@pytest.mark.parametrize("accum", [dp.KAHAN, dp.SUM2], ids=["kahan", "sum2"])
+@pytest.mark.parametrize("final_f64", [0, 1])
+def test_compensated_lanes_fed_by_loader_wavefronts(accum, final_f64):
+    s = dp.Strategy(seq_len=256, local_size=64, order=C_, accum=accum, final_f64=final_f64)
+    n = s.seq_len * s.local_size * 41
+    x, y = synthetic.kahan_dot_inputs(n, synthetic.SEEDS["precision"])
+    want = S.dot(x, y, to_plan(s))
+    for passes in (1, 2):
+        assert_same_bits(gpu_dot(x, y, s.with_(passes=passes)), want, f"passes={passes}")
+    xd, yd = discriminating(90, n)
+    assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, to_plan(s)), "cancelling")
