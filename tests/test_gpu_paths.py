@@ -362,3 +362,4 @@ def test_compensated_lanes_fed_by_loader_wavefronts(accum, final_f64):
         assert_same_bits(gpu_dot(x, y, s.with_(passes=passes)), want, f"passes={passes}")
     xd, yd = discriminating(90, n)
     assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, to_plan(s)), "cancelling")
+
