@@ -644,12 +644,21 @@ def workload_vector(args):
         t_us = time_us(lambda: dp.dot(xt, yt, s, out=out, ws=ws), reps=40)[0]
         torch.cuda.synchronize()
         res[name] = (s, out.cpu().numpy()[0])
+        # the same strategy in one pass (one launch; with many chunk values
+        # the fold runs beside the chunk values still being computed)
+        s1 = s.with_(passes=1)
+        ws1 = dp.workspace(s1, dp.OP_DOT, dp.F32, 0, n)
+        out1 = torch.empty(1, device="cuda")
+        t1_us = time_us(lambda: dp.dot(xt, yt, s1, out=out1, ws=ws1), reps=40)[0]
+        torch.cuda.synchronize()
+        res[name + " 1-pass"] = (s1, out1.cpu().numpy()[0])
         nval = dp.num_chunks(s, n) * dp.values_per_chunk(s)
         _line(workload="vector", name=name, n=n, strategy=strategy_text(s), chunk_values=nval,
               chunks_us=round(c_us, 2), fold_us=round(f_us, 2), dot_us=round(t_us, 2),
               chunks_gbs=_gbs(8 * n + 4 * nval, c_us),
               chunks_pct_peak=round(100 * (8 * n + 4 * nval) / c_us / 1e3 / PEAK_GBPS, 1),
-              dot_gbs=_gbs(8 * n + 4, t_us))
+              dot_gbs=_gbs(8 * n + 4, t_us), dot_1pass_us=round(t1_us, 2),
+              dot_1pass_gbs=_gbs(8 * n + 4, t1_us))
     if not args.no_cpu_baseline:
         from oracle import strategies as S
         from tests.gpu_util import to_plan

@@ -34,15 +34,16 @@ enum : int {
 // LOADS: loads in flight per thread, at most.  Kernels that carry the fold
 // beside other work (1 pass) pass smaller ones, so that the fold does not
 // raise their register count.
+// fold_values continues the fold from (acc, acc64) over partials[0 .. G);
+// the results are thread 0's.  final_fold folds from the literal 0 and
+// writes the strategy's result.
 template <class A, int FINAL, bool COHERENT = false,
           int R = (sizeof(typename A::T) > 4 ? 8 : 16), int LOADS = 8>
-__device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
-                           typename A::T* buf) {
+__device__ void fold_values(const typename A::T* partials, int64_t G, typename A::T* buf,
+                            typename A::T& acc, double& acc64) {
   using T = typename A::T;
   constexpr int kHalf = kFoldBlock / 2;
   constexpr int kLoads = LOADS;
-  T acc = A::zero();
-  double acc64 = 0.0;
   auto fold1 = [&](const T& e) {
     if constexpr (FINAL == kFinalKahan64)
       acc64 = (static_cast<double>(e.s) - static_cast<double>(e.c)) + acc64;
@@ -125,6 +126,12 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
     if (more) put(buf + (h ^ 1) * kHalf, b + step);
     __syncthreads();
   }
+}
+
+// The strategy's result from the fold's accumulator (thread 0 writes it).
+template <class A, int FINAL>
+__device__ void write_fold(const typename A::T& acc, double acc64, void* out, int out_f64) {
+  using T = typename A::T;
   if (threadIdx.x == 0) {
     if constexpr (FINAL == kFinalKahan64 || FINAL == kFinalSum2_64) {
       if (out_f64)
@@ -139,6 +146,16 @@ __device__ void final_fold(const typename A::T* partials, int64_t G, void* out, 
       *static_cast<T*>(out) = acc;
     }
   }
+}
+
+template <class A, int FINAL, bool COHERENT = false,
+          int R = (sizeof(typename A::T) > 4 ? 8 : 16), int LOADS = 8>
+__device__ void final_fold(const typename A::T* partials, int64_t G, void* out, int out_f64,
+                           typename A::T* buf) {
+  typename A::T acc = A::zero();
+  double acc64 = 0.0;
+  fold_values<A, FINAL, COHERENT, R, LOADS>(partials, G, buf, acc, acc64);
+  write_fold<A, FINAL>(acc, acc64, out, out_f64);
 }
 
 }  // namespace dpia

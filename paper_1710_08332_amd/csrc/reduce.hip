@@ -495,7 +495,8 @@ constexpr size_t kScratchBytes = size_t(1) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 __global__ void scratch_clear_kernel(unsigned int* counter) {
-  if (threadIdx.x == 0) *counter = 0u;
+  // the whole 256-byte block of the arrival counter
+  if (threadIdx.x < kWsAlign / sizeof(unsigned int)) counter[threadIdx.x] = 0u;
 }
 
 namespace {

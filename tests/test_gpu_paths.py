@@ -5,7 +5,7 @@ with 64-element batches, a batch of instances drawn like the benchmark's
 (lengths up to 2^20, gemv sides up to 4096), and staged contiguous folds
 with an odd number of tiles, the outer fold of many chunk values at the
 boundaries of the steps it copies them in, and staged contiguous lanes fed
-by loader wavefronts.
+by loader wavefronts (also in one pass, with many chunk values).
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -363,3 +363,36 @@ def test_compensated_lanes_fed_by_loader_wavefronts(accum, final_f64):
     xd, yd = discriminating(90, n)
     assert_same_bits(gpu_dot(xd, yd, s), S.dot(xd, yd, to_plan(s)), "cancelling")
 
+
+# ------------------------------------------------ one pass, many chunk values
+# 1-pass uncombined strategies fed by loader wavefronts, with thousands of
+# chunk values folded by the last work-group: chunk counts that split each
+# chunk over 1, 2 or 4 work-groups, a ragged last chunk, scalar and V = 4
+# lanes, dot and asum; twice in a row on one workspace, which the launch
+# leaves with its arrival-counter block at zero.
+ONE_PASS = {
+    "C256-V4": dict(seq_len=256, local_size=64, order=C_, vec_width=4, wg_combine=dp.NONE),
+    "C1024-V1": dict(seq_len=1024, local_size=64, order=C_, wg_combine=dp.NONE),
+}
+
+
+@pytest.mark.parametrize("chunks,short", [(40, 0), (100, 0), (200, 0), (255, 777)])
+@pytest.mark.parametrize("name", sorted(ONE_PASS))
+def test_one_pass_fed_launches_with_many_chunk_values(name, chunks, short):
+    import torch
+    s = dp.Strategy(**ONE_PASS[name], passes=1)
+    W = s.seq_len * s.local_size * s.vec_width
+    n = W * chunks - short
+    print(f"one pass {name} chunks={chunks} n={n}", flush=True)
+    x, y = discriminating(95 + chunks, n)
+    p = to_plan(s)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    ws = dp.workspace(s, dp.OP_DOT, dp.F32, 0, n)
+    want = S.dot(x, y, p)
+    for rep in range(2):
+        r = dp.dot(xt, yt, s, ws=ws)
+        torch.cuda.synchronize()
+        assert_same_bits(r.cpu().numpy()[0], want, f"dot call {rep}")
+    assert_same_bits(gpu_dot(x, y, s.with_(passes=2)), want, "dot, 2 passes")
+    assert_same_bits(gpu_asum(x, s), S.asum(x, p), "asum")
+    assert not ws[-256:].any(), "arrival-counter block left non-zero"
