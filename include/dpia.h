@@ -169,8 +169,10 @@ dpia_status dpia_strategy_check(const dpia_strategy* s, dpia_op op, dpia_dtype d
  *            with accum = KAHAN and final_f64 = 1 (else the binary64 fold is
  *            rounded once to binary32)
  *   ws       device workspace of at least dpia_strategy_check's size.  Its
- *            arrival-counter word must be zero before the first 1-pass call
- *            on it (allocate it zeroed); every call leaves it zero.  Calls
+ *            arrival counters (the 256 bytes after the chunk values, and, for
+ *            staged contiguous tree strategies with at most 1024 chunks, the
+ *            per-chunk counts at its end) must be zero before the first call
+ *            on it (allocate it zeroed); every call leaves them zero.  Calls
  *            sharing one workspace must be ordered (same stream).
  */
 dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n, const void* x,

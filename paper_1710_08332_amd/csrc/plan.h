@@ -62,7 +62,16 @@ struct Plan {
   bool stage;             // contiguous order staged through LDS
   int scal_tile;          // scal staged: elements of a row per tile (16, 32, 64)
   size_t stage_off;       // byte offset of the staging region in the LDS
+  size_t split_off;       // dot/asum: byte offset in the workspace of the nodes and
+                          // per-chunk arrival counts of teams split over work-groups
+                          // (0: the workspace has none)
 };
+
+// Teams whose lanes the loader-wavefront kernel may split over work-groups
+// (tree combine, one lane per thread, at most kSplitMaxItems chunks) keep up
+// to kSplitMax nodes per chunk in the workspace.
+constexpr int kSplitMax = 8;
+constexpr int64_t kSplitMaxItems = 1024;
 
 size_t elem_bytes(dpia_dtype dt);
 

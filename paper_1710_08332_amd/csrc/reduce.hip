@@ -33,6 +33,8 @@ struct ReduceArgs {
   int out_f64;            // Kahan 64 only: write a double
   void* partials;
   unsigned int* counter;
+  void* nodes;            // split teams: kSplitMax nodes per chunk, or nullptr
+  unsigned int* node_cnt; // split teams: one arrival count per chunk
   void* out;
 };
 
@@ -97,21 +99,25 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
 #define DPIA_FED 1
 #endif
 
-// The mapWorkgroup level of a staged contiguous strategy with one 64-lane
-// team per chunk, fed by loader wavefronts (fed.h): wave 0 folds the lanes
-// and combines them, waves 1 .. kFedLoaders load.  An uncombined strategy
-// may give each work-group ROWS < 64 of a chunk's lanes (64 / ROWS
-// work-groups per chunk, on as many compute units).  A chunk whose lane rows
-// are not all whole (the last one, when W does not divide n) is folded
-// whole by wave 0 of its first work-group alone, as reduce_kernel folds it.
-// The same chunk values, the same 1-pass arrival and fold as reduce_kernel.
+// The mapWorkgroup level of a staged contiguous strategy whose teams have
+// one lane per thread (64, 128 or 256 lanes) and few chunks, fed by loader
+// wavefronts (fed.h): each work-group takes ROWS lanes of one chunk (a slice;
+// a.team / ROWS slices per chunk), its wave 0 folds them and waves 1 ..
+// kFedLoaders load.  Uncombined slices store their lanes' values.  A tree
+// combine over a split team: each slice reduces its ROWS lanes with the
+// team's butterfly levels below ROWS and stores that node (device-coherent);
+// the slice whose arrival completes the chunk's count applies the levels
+// from ROWS up to the team over the nodes in lane order, which is the same
+// tree (the levels are hierarchical), and stores the chunk value.  Lane rows
+// that are not whole (the last chunk, when W does not divide n) are folded
+// by wave 0 alone, as reduce_kernel folds them.  The same chunk values, the
+// same 1-pass arrival and fold as reduce_kernel.
 template <class Op, int COMBINE, int FINAL, int VEC, int ROWS>
 __global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op op,
                                                                                ReduceArgs a) {
   using T = typename Op::T;
+  using A = typename Op::Arith;
   static_assert(COMBINE != kSeq, "a sequential combine has barriers of the team alone");
-  static_assert(ROWS == kWave || COMBINE == kNone, "only independent lanes are split");
-  constexpr int S = kWave / ROWS;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int is_last;
   T* lds = reinterpret_cast<T*>(lds_raw);
@@ -120,35 +126,55 @@ __global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op 
   const int lane = threadIdx.x & (kWave - 1);
   T* partials = static_cast<T*>(a.partials);
   const int Cel = a.C * VEC;
+  const int S = a.team / ROWS;   // slices per chunk
   for (int64_t w = blockIdx.x; w < a.items * S; w += gridDim.x) {
     const int64_t g = w / S;
-    const int row0 = static_cast<int>(w % S) * ROWS;
+    const int s = static_cast<int>(w % S);
+    const int row0 = s * ROWS;
     const auto view = op.chunk(g, a.W);
     const int64_t rest = a.n - g * a.W;
     const int limit = static_cast<int>(rest < a.W ? rest : a.W);
-    const bool whole = limit == a.W;
     T acc[VEC];
-    if (whole)
+    if (limit == a.W)
       fed_fold<Op, VEC, ROWS>(view, Cel, wave, lane, row0, ring, acc);
-    else if (wave == 0 && row0 == 0)
-      contiguous_staged<Op, VEC>(view, true, lane, a.C, limit, acc, ring);
-    if (wave == 0 && (row0 == 0 || whole)) {
+    else if (wave == 0)
+      contiguous_staged<Op, VEC>(view, lane < ROWS, row0 + lane, a.C, limit, acc, ring);
+    if (wave == 0) {
       if constexpr (COMBINE == kNone) {
-        if (!whole || lane < ROWS) {
-          const int64_t l = g * a.L + (whole ? row0 : 0) + lane;
+        if (lane < ROWS) {
+          const int64_t l = g * a.L + row0 + lane;
 #pragma unroll
           for (int j = 0; j < VEC; ++j) store_coherent(partials + l * VEC + j, acc[j]);
         }
-      } else {
+      } else if (S == 1) {
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
           T one[1] = {acc[j]};
-          const T c = combine_lanes<typename Op::Arith, 1, COMBINE>(one, lane, kWave, a.L, lds);
+          const T c = combine_lanes<A, 1, COMBINE>(one, lane, kWave, a.L, lds);
           if (lane == 0) store_coherent(partials + g * VEC + j, c);
+        }
+      } else if constexpr (VEC == 1) {
+        T one[1] = {acc[0]};
+        const T node = combine_lanes<A, 1, COMBINE>(one, lane, ROWS, a.L, lds);
+        T* nodes = static_cast<T*>(a.nodes) + g * kSplitMax;
+        unsigned last = 0;
+        if (lane == 0) {
+          store_coherent(nodes + s, node);
+          wait_memory();
+          last = __hip_atomic_fetch_add(a.node_cnt + g, 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) == static_cast<unsigned>(S - 1);
+        }
+        if (__shfl(last, 0)) {   // every slice's node is stored
+          T v = lane < S ? load_coherent(nodes + lane) : A::zero();
+          butterfly_levels<A>(v, lane, S);
+          if (lane == 0) {
+            store_coherent(partials + g, v);
+            __hip_atomic_store(a.node_cnt + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
       }
     }
-    __syncthreads();   // the ring may be written for the next chunk
+    __syncthreads();   // the ring may be written for the next slice
   }
   if (a.one_pass) {
     wait_memory();
@@ -226,29 +252,34 @@ hipError_t with_reduce_shape(const Plan& p, F&& f) {
   return hipErrorInvalidValue;
 }
 
-// The mapWorkgroup level: chunk values into `partials`; with one_pass the
-// last work-group also folds them into `out`.
 // Lane rows per work-group when a plan's chunks are folded by
-// fed_reduce_kernel (0: they are not): staged contiguous lanes, one 64-lane
-// team per chunk, a tree or no combine, and fewer chunks than compute units
-// (otherwise the launch has wavefronts enough).  An uncombined strategy
-// splits each chunk's rows over as many work-groups as the compute units
-// allow (2 or 4): a compute unit streams at most about 37 GB/s, so 128
-// chunks on 128 of them cannot reach the memory's rate.  A chunk's tiles
-// must be a multiple of the loaders' depth for that row count.
+// fed_reduce_kernel (0: they are not): staged contiguous lanes, one lane per
+// thread, fewer chunks than compute units (otherwise the launch has
+// wavefronts enough), and a chunk's tiles a multiple of the loaders' depth
+// for that row count.  A compute unit streams at most about 37 GB/s, so the
+// chunks' lanes are split over as many work-groups as the compute units
+// allow: uncombined lanes into 2 or 4 slices of a 64-lane team, tree-combined
+// teams of 64, 128 or 256 lanes into up to kSplitMax slices when the call
+// brings the workspace's split region (`can_split`); a 64-lane tree team may
+// also stay whole.
 template <int NOPS>
-int fed_rows(const Plan& p) {
+int fed_rows(const Plan& p, bool can_split) {
   if (!DPIA_FED || !p.stage || p.order != DPIA_ORDER_CONTIGUOUS) return 0;
   if (p.op != DPIA_OP_DOT && p.op != DPIA_OP_ASUM) return 0;
-  if (p.team != kWave || p.teams_per_wg != 1 || p.combine == DPIA_COMBINE_SEQ) return 0;
+  if (p.teams_per_wg != 1 || p.combine == DPIA_COMBINE_SEQ) return 0;
   if (p.V != 1 && p.V != 4) return 0;
+  const bool split = can_split && p.split_off && p.combine == DPIA_COMBINE_TREE && p.V == 1;
+  if (p.team != kWave && !(split && (p.team == 128 || p.team == 256))) return 0;
   const int64_t cus = device_cus();
   if (p.items >= cus || (p.C * p.V) % kFedStage) return 0;
   const int64_t ntiles = p.C * p.V / kFedStage;
   auto fits = [&](int depth) { return ntiles >= depth && ntiles % depth == 0; };
-  if (p.combine == DPIA_COMBINE_NONE) {
-    if (p.items * 4 <= cus && fits(fed_depth<16, NOPS>())) return 16;
-    if (p.items * 2 <= cus && fits(fed_depth<32, NOPS>())) return 32;
+  if (p.combine == DPIA_COMBINE_NONE || split) {
+    const int64_t per16 = p.team / 16, per32 = p.team / 32;   // slices per chunk
+    if (per16 <= kSplitMax && p.items * per16 <= cus && fits(fed_depth<16, NOPS>())) return 16;
+    if (per32 <= kSplitMax && p.items * per32 <= cus && fits(fed_depth<32, NOPS>())) return 32;
+    if (p.items * (p.team / kWave) <= cus && fits(fed_depth<kWave, NOPS>())) return kWave;
+    return 0;
   }
   return fits(fed_depth<kWave, NOPS>()) ? kWave : 0;
 }
@@ -256,7 +287,7 @@ int fed_rows(const Plan& p) {
 template <class Op, int FINAL>
 hipError_t launch_fed(const Plan& p, const Op& op, const ReduceArgs& a, int rows,
                       hipStream_t stream) {
-  const int64_t grid = p.items * (kWave / rows);
+  const int64_t grid = p.items * (p.team / rows);
   size_t lds = p.stage_off + static_cast<size_t>(fed_ring_floats()) * sizeof(float);
   const size_t fold = static_cast<size_t>(kFoldBlock) * sizeof(typename Op::T);
   if (fold > lds) lds = fold;
@@ -270,31 +301,33 @@ hipError_t launch_fed(const Plan& p, const Op& op, const ReduceArgs& a, int rows
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
                            dim3(kWave * (1 + kFedLoaders)), args, lds, stream);
   };
+  auto by_rows = [&](auto comb, auto vec) {
+    if (rows == 16) return go(comb, vec, ic<16>{});
+    if (rows == 32) return go(comb, vec, ic<32>{});
+    return go(comb, vec, ic<kWave>{});
+  };
   if constexpr (FINAL != kFinalPlain) {
-    return go(ic<kTree>{}, ic<1>{}, ic<kWave>{});   // compensated: scalar, combined lanes
+    return by_rows(ic<kTree>{}, ic<1>{});   // compensated: scalar, combined lanes
   } else {
     if (p.combine == DPIA_COMBINE_TREE)
-      return p.V == 4 ? go(ic<kTree>{}, ic<4>{}, ic<kWave>{})
-                      : go(ic<kTree>{}, ic<1>{}, ic<kWave>{});
-    auto by_rows = [&](auto vec) {
-      if (rows == 16) return go(ic<kNone>{}, vec, ic<16>{});
-      if (rows == 32) return go(ic<kNone>{}, vec, ic<32>{});
-      return go(ic<kNone>{}, vec, ic<kWave>{});
-    };
-    return p.V == 4 ? by_rows(ic<4>{}) : by_rows(ic<1>{});
+      return p.V == 4 ? go(ic<kTree>{}, ic<4>{}, ic<kWave>{}) : by_rows(ic<kTree>{}, ic<1>{});
+    return p.V == 4 ? by_rows(ic<kNone>{}, ic<4>{}) : by_rows(ic<kNone>{}, ic<1>{});
   }
 }
 
+// The mapWorkgroup level: chunk values into `partials`; with one_pass the
+// last work-group also folds them into `out`.
 template <class Op, int FINAL>
 hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
   if (p.items == 0) return hipSuccess;
   // (the loaders keep the tiles in flight, so DotF32Deeper's second staged
   // tile would only add registers; DotF32Deep serves strided lanes only)
+  const bool can_split = a.nodes != nullptr;
   if constexpr (std::is_same<Op, DotF32Deeper>::value) {
-    if (const int rows = fed_rows<2>(p))
+    if (const int rows = fed_rows<2>(p, can_split))
       return launch_fed<DotF32, FINAL>(p, DotF32{op.x, op.y}, a, rows, stream);
   } else if constexpr (Op::View::kStageable && !std::is_same<Op, DotF32Deep>::value) {
-    const int rows = fed_rows<Op::View::kOps>(p);
+    const int rows = fed_rows<Op::View::kOps>(p, can_split);
     if (rows && (FINAL == kFinalPlain || (p.V == 1 && p.combine == DPIA_COMBINE_TREE)))
       return launch_fed<Op, FINAL>(p, op, a, rows, stream);
   }
@@ -328,12 +361,20 @@ hipError_t launch_fold(int64_t G, const void* partials, void* out, int out_f64,
 
 // Both passes of a reduction: chunk values into `partials`, then the outer
 // fold (1 pass: in the last work-group, which needs `counter` at zero and
-// leaves it at zero; 2 passes: a second kernel).
+// leaves it at zero; 2 passes: a second kernel).  `split`: the workspace's
+// split region (p.split_off), or nullptr where the call has none.
 template <class Op, int FINAL>
 hipError_t launch_reduce(const Plan& p, const Op& op, void* out, int out_f64, void* partials,
-                         void* counter, hipStream_t stream) {
+                         void* counter, hipStream_t stream, void* split = nullptr) {
   const bool two_pass = p.passes == 2 || p.items == 0;
   ReduceArgs a = reduce_args<Op>(p, partials, counter, out, out_f64, !two_pass);
+  if (split && p.split_off) {
+    a.nodes = split;
+    a.node_cnt = reinterpret_cast<unsigned int*>(
+        static_cast<char*>(split) +
+        (static_cast<size_t>(p.items) * kSplitMax * p.acc_bytes + kWsAlign - 1) / kWsAlign *
+            kWsAlign);
+  }
   hipError_t e = launch_chunks<Op, FINAL>(p, op, a, stream);
   if (e != hipSuccess || !two_pass) return e;
   return launch_fold<Op, FINAL>(p.values, partials, out, out_f64, stream);
@@ -414,37 +455,39 @@ namespace {
 // counter at `counter`.
 dpia_status dot_launch(const Plan& p, dpia_dtype dt, const void* x, const void* y, void* out,
                        dpia_dtype out_dt, void* partials, void* counter, hipStream_t hs,
-                       const char* name) {
+                       const char* name, void* split = nullptr) {
   hipError_t e;
   if (dt == DPIA_I32) {
     e = launch_reduce<DotU32, kFinalPlain>(
         p, DotU32{static_cast<const uint32_t*>(x), static_cast<const uint32_t*>(y)}, out, 0,
-        partials, counter, hs);
+        partials, counter, hs, split);
   } else if (p.accum == DPIA_ACCUM_KAHAN || p.accum == DPIA_ACCUM_SUM2) {
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     const int f64 = out_dt == DPIA_F64;
     if (p.accum == DPIA_ACCUM_KAHAN) {
       KahanDotF32 op{xf, yf};
-      e = p.final_f64
-              ? launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, f64, partials, counter, hs)
-              : launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, partials, counter, hs);
+      e = p.final_f64 ? launch_reduce<KahanDotF32, kFinalKahan64>(p, op, out, f64, partials,
+                                                                  counter, hs, split)
+                      : launch_reduce<KahanDotF32, kFinalKahan32>(p, op, out, 0, partials,
+                                                                  counter, hs, split);
     } else {
       Sum2DotF32 op{xf, yf};
-      e = p.final_f64
-              ? launch_reduce<Sum2DotF32, kFinalSum2_64>(p, op, out, f64, partials, counter, hs)
-              : launch_reduce<Sum2DotF32, kFinalSum2_32>(p, op, out, 0, partials, counter, hs);
+      e = p.final_f64 ? launch_reduce<Sum2DotF32, kFinalSum2_64>(p, op, out, f64, partials,
+                                                                 counter, hs, split)
+                      : launch_reduce<Sum2DotF32, kFinalSum2_32>(p, op, out, 0, partials,
+                                                                 counter, hs, split);
     }
   } else {
     const float* xf = static_cast<const float*>(x);
     const float* yf = static_cast<const float*>(y);
     const int depth = dot_depth(p);
     e = depth == 2 ? launch_reduce<DotF32Deeper, kFinalPlain>(p, DotF32Deeper{{xf, yf}}, out, 0,
-                                                               partials, counter, hs)
+                                                               partials, counter, hs, split)
         : depth == 1 ? launch_reduce<DotF32Deep, kFinalPlain>(p, DotF32Deep{{xf, yf}}, out, 0,
-                                                              partials, counter, hs)
+                                                              partials, counter, hs, split)
                      : launch_reduce<DotF32, kFinalPlain>(p, DotF32{xf, yf}, out, 0, partials,
-                                                          counter, hs);
+                                                          counter, hs, split);
   }
   if (e != hipSuccess) return hip_fail(e, name);
   clear_detail();
@@ -481,8 +524,9 @@ extern "C" dpia_status dpia_dot(const dpia_strategy* s, dpia_dtype dt, int64_t n
   if (st != DPIA_OK) return st;
   st = check_ws(p, ws, ws_bytes);
   if (st != DPIA_OK) return st;
+  void* split = p.split_off ? static_cast<char*>(ws) + p.split_off : nullptr;
   return dot_launch(p, dt, x, y, out, out_dt, ws, static_cast<char*>(ws) + p.partial_bytes,
-                    reinterpret_cast<hipStream_t>(stream), "dpia_dot launch");
+                    reinterpret_cast<hipStream_t>(stream), "dpia_dot launch", split);
 }
 
 // ------------------------------------------------------------ no-alloc dot
@@ -567,10 +611,11 @@ extern "C" dpia_status dpia_asum(const dpia_strategy* s, dpia_dtype dt, int64_t 
   if (n > 0 && !aligned16(x)) return bad(DPIA_ERR_SHAPE, "x must be 16-byte aligned");
   st = check_ws(p, ws, ws_bytes);
   if (st != DPIA_OK) return st;
+  void* split = p.split_off ? static_cast<char*>(ws) + p.split_off : nullptr;
   hipError_t e = launch_reduce<AsumF32, kFinalPlain>(p, AsumF32{static_cast<const float*>(x)},
                                                      out, 0, ws,
                                                      static_cast<char*>(ws) + p.partial_bytes,
-                                                     reinterpret_cast<hipStream_t>(stream));
+                                                     reinterpret_cast<hipStream_t>(stream), split);
   if (e != hipSuccess) return hip_fail(e, "dpia_asum launch");
   clear_detail();
   return DPIA_OK;

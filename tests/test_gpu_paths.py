@@ -5,7 +5,8 @@ with 64-element batches, a batch of instances drawn like the benchmark's
 (lengths up to 2^20, gemv sides up to 4096), and staged contiguous folds
 with an odd number of tiles, the outer fold of many chunk values at the
 boundaries of the steps it copies them in, and staged contiguous lanes fed
-by loader wavefronts (also in one pass, with many chunk values).
+by loader wavefronts (also in one pass, with many chunk values, and
+tree-combined teams split over work-groups).
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -396,3 +397,61 @@ def test_one_pass_fed_launches_with_many_chunk_values(name, chunks, short):
     assert_same_bits(gpu_dot(x, y, s.with_(passes=2)), want, "dot, 2 passes")
     assert_same_bits(gpu_asum(x, s), S.asum(x, p), "asum")
     assert not ws[-256:].any(), "arrival-counter block left non-zero"
+
+
+# ------------------------------------------------ split tree teams
+# Tree-combined contiguous teams of 64, 128 and 256 lanes with few chunks:
+# their lanes are split over 2 to 8 work-groups, each reduces its slice to a
+# node of the team's tree, and the last slice of a chunk applies the upper
+# levels.  Bit-exact against the oracle; the chunk values from dpia_chunks
+# (no workspace, so no split) equal the split launch's, and the per-chunk
+# arrival counts are left at zero.
+SPLIT = {
+    "L64-C1024": dict(seq_len=1024, local_size=64, order=C_),
+    "L128-C512": dict(seq_len=512, local_size=128, order=C_),
+    "L256-C1024": dict(seq_len=1024, local_size=256, order=C_),
+    "L256-C8192": dict(seq_len=8192, local_size=256, order=C_),
+}
+
+
+@pytest.mark.parametrize("chunks,short", [(1, 0), (5, 0), (31, 0), (31, 333), (60, 0),
+                                          (100, 0)])
+@pytest.mark.parametrize("name", sorted(SPLIT))
+def test_split_tree_teams(name, chunks, short):
+    import torch
+    s = dp.Strategy(**SPLIT[name])
+    W = s.seq_len * s.local_size
+    if W * chunks > (1 << 25):
+        pytest.skip("the long rows reach the same path with fewer chunks")
+    n = W * chunks - short
+    print(f"split tree {name} chunks={chunks} n={n}", flush=True)
+    x, y = discriminating(110 + chunks, n)
+    p = to_plan(s)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    want = S.dot(x, y, p)
+    for passes in (1, 2):
+        sp = s.with_(passes=passes)
+        ws = dp.workspace(sp, dp.OP_DOT, dp.F32, 0, n)
+        for rep in range(2):
+            r = dp.dot(xt, yt, sp, ws=ws)
+            torch.cuda.synchronize()
+            assert_same_bits(r.cpu().numpy()[0], want, f"dot passes={passes} call {rep}")
+        items = -(-n // W)
+        counts = -(-items * 4 // 256) * 256         # the split region ends with them
+        partial = -(-items * 4 // 256) * 256
+        assert not ws[-counts:].any(), "per-chunk arrival counts left non-zero"
+        assert not ws[partial:partial + 256].any(), "arrival counter left non-zero"
+        assert_same_bits(gpu_asum(x, sp), S.asum(x, p), f"asum passes={passes}")
+    c = dp.chunks(dp.OP_DOT, s, xt, yt)
+    torch.cuda.synchronize()
+    assert_same_bits(c.cpu().numpy().view(np.float32), S.dot_chunks(x, y, p), "chunk values")
+
+
+@pytest.mark.parametrize("accum", [dp.KAHAN, dp.SUM2], ids=["kahan", "sum2"])
+def test_split_tree_teams_compensated(accum):
+    s = dp.Strategy(seq_len=1024, local_size=256, order=C_, accum=accum, final_f64=1)
+    n = s.seq_len * s.local_size * 9
+    x, y = synthetic.kahan_dot_inputs(n, synthetic.SEEDS["precision"])
+    want = S.dot(x, y, to_plan(s))
+    for passes in (1, 2):
+        assert_same_bits(gpu_dot(x, y, s.with_(passes=passes)), want, f"passes={passes}")
