@@ -172,4 +172,116 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
   }
 }
 
+// The strided order, ROWS lanes (lane0 .. lane0 + ROWS - 1) of one chunk
+// whose elements all exist: lane l takes elements l, l + L, l + 2L, ...
+// (Cj of them), so step j of every lane is one contiguous row of L elements.
+// A tile is kFedStrideRows consecutive steps of the slice's ROWS lanes; the
+// loaders fetch each step's ROWS * 4 bytes (ROWS / 4 threads per step, 256 /
+// ROWS steps per load instruction), and the folding wavefront, one lane per
+// thread, reads its lane's element of each step in increasing j.  Ring rows
+// are steps, ROWS + 4 floats apart.  Cj / kFedStrideRows tiles, a multiple of
+// the depth.
+constexpr int kFedStrideRows = 64;
+static_assert(2 * kWave * (kWave + 4) <= fed_ring_floats() / 2,
+              "a strided slot of 64 lanes fits a ring slot");
+
+template <class Op, int ROWS, class View>
+__device__ __forceinline__ void fed_fold_strided(const View& view, int L, int Cj, int wave,
+                                                 int lane, int lane0, float* ring,
+                                                 typename Op::T& acc) {
+  constexpr int NOPS = View::kOps;
+  constexpr int RS = ROWS + 4;                      // ring row stride (floats)
+  constexpr int kThreadsPerStep = ROWS / 4;
+  constexpr int kStepsPerLoad = kWave / kThreadsPerStep;
+  constexpr int kPer = fed_per<ROWS, NOPS>();       // load instructions per operand per tile
+  constexpr int D = fed_depth<ROWS, NOPS>();
+  constexpr int B = kFedBurst < D ? kFedBurst : D;
+  static_assert(kPer * kFedLoaders * kStepsPerLoad == kFedStrideRows,
+                "the loaders split a tile's loads evenly");
+  static_assert(D % 2 == 0 && D % B == 0, "whole bursts; a round's slot is its tile's parity");
+  acc = Op::Arith::zero();
+  const int part = lane % kThreadsPerStep;
+  const int q = wave - 1;
+  // element offsets within the chunk (below 2^31: W is), added to the
+  // chunk's base pointers, which are the same for the whole work-group; 32-
+  // bit offsets keep the loads from holding a 64-bit address per tile set
+  uint32_t gofs[kPer];
+  int rofs[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int r = (q * kPer + k) * kStepsPerLoad + lane / kThreadsPerStep;   // step in the tile
+    rofs[k] = r * RS + part * 4;
+    gofs[k] = static_cast<uint32_t>(r * L + lane0 + part * 4);
+  }
+  f32x4 regs[D][NOPS][kPer];
+  const uint32_t tile_elems = static_cast<uint32_t>(kFedStrideRows) * static_cast<uint32_t>(L);
+  auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {
+    const uint32_t t0 = static_cast<uint32_t>(tile) * tile_elems;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        rg[o][k] = ld<DPIA_NT_LOADS != 0>(
+            reinterpret_cast<const f32x4*>(view.operand(o) + (t0 + gofs[k])));
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto put = [&](const f32x4 (&rg)[NOPS][kPer], int slot) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+        *reinterpret_cast<f32x4*>(ring + (slot * NOPS + o) * kFedStrideRows * RS + rofs[k]) =
+            rg[o][k];
+  };
+  // (blocks of 16 steps: the whole tile's reads at once would spill)
+  auto fold_slot = [&](int slot) {
+    if (lane >= ROWS) return;
+#pragma unroll 1
+    for (int r0 = 0; r0 < kFedStrideRows; r0 += 16)
+#pragma unroll
+    for (int r = r0; r < r0 + 16; r += 4) {
+      f32x4 v[NOPS];
+#pragma unroll
+      for (int o = 0; o < NOPS; ++o)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          v[o][i] = ring[((slot * NOPS + o) * kFedStrideRows + r + i) * RS + lane];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc = Op::step(View::term(v, i), acc);
+    }
+  };
+  // the same rounds as fed_fold
+  const int ntiles = Cj / kFedStrideRows;
+  if (wave > 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) gload(regs[d], d);
+    int r0 = 0;
+    for (; r0 + D < ntiles; r0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        put(regs[d], d & 1);
+        if (d % B == B - 1) {
+#pragma unroll
+          for (int b = d - B + 1; b <= d; ++b) gload(regs[b], r0 + b + D);
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      put(regs[d], d & 1);
+      __syncthreads();
+    }
+    __syncthreads();
+  } else {
+    __syncthreads();
+    for (int r = 1; r < ntiles; ++r) {
+      fold_slot((r - 1) & 1);
+      __syncthreads();
+    }
+    fold_slot((ntiles - 1) & 1);
+    __syncthreads();
+  }
+}
+
 }  // namespace dpia

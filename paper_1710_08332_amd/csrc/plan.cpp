@@ -268,12 +268,18 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     q.values = q.items * q.cv;
     q.partial_bytes = round_up(static_cast<size_t>(q.values) * q.acc_bytes, kWsAlign);
     q.ws_bytes = q.partial_bytes + kWsAlign;   // + the arrival counter
-    // staged contiguous teams of 64, 128 or 256 lanes with a tree combine
-    // and few chunks: room for the nodes of their lanes split over
-    // work-groups, and one arrival count per chunk (zero between calls)
+    // staged contiguous teams of 64, 128 or 256 lanes, and scalar strided
+    // teams of 16 to 512 lanes, with a tree combine and few chunks: room for
+    // the nodes of their lanes split over work-groups, and one arrival count
+    // per chunk (zero between calls)
     q.split_off = 0;
-    if (q.stage && q.order == DPIA_ORDER_CONTIGUOUS && q.combine == DPIA_COMBINE_TREE &&
-        V == 1 && q.teams_per_wg == 1 && (q.team == 64 || q.team == 128 || q.team == 256) &&
+    const bool split_contiguous = q.stage && q.order == DPIA_ORDER_CONTIGUOUS &&
+                                  q.teams_per_wg == 1 &&
+                                  (q.team == 64 || q.team == 128 || q.team == 256);
+    const bool split_strided = q.order == DPIA_ORDER_STRIDED && dt == DPIA_F32 &&
+                               q.accum == DPIA_ACCUM_PLAIN && q.L >= 16 && q.L <= 512 &&
+                               (q.L & (q.L - 1)) == 0 && q.C % 64 == 0;
+    if ((split_contiguous || split_strided) && q.combine == DPIA_COMBINE_TREE && V == 1 &&
         q.items > 0 && q.items <= kSplitMaxItems) {
       q.split_off = q.ws_bytes;
       q.ws_bytes += round_up(static_cast<size_t>(q.items) * kSplitMax * q.acc_bytes, kWsAlign) +

@@ -99,11 +99,11 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
 #define DPIA_FED 1
 #endif
 
-// The mapWorkgroup level of a staged contiguous strategy whose teams have
-// one lane per thread (64, 128 or 256 lanes) and few chunks, fed by loader
-// wavefronts (fed.h): each work-group takes ROWS lanes of one chunk (a slice;
-// a.team / ROWS slices per chunk), its wave 0 folds them and waves 1 ..
-// kFedLoaders load.  Uncombined slices store their lanes' values.  A tree
+// The mapWorkgroup level of a strategy with few chunks, fed by loader
+// wavefronts (fed.h): staged contiguous lanes (teams of 64, 128 or 256 lanes,
+// one per thread) or scalar strided lanes.  Each work-group takes ROWS lanes
+// of one chunk (a slice; L / ROWS slices per chunk), its wave 0 folds them,
+// one lane per thread, and waves 1 .. kFedLoaders load.  Uncombined slices store their lanes' values.  A tree
 // combine over a split team: each slice reduces its ROWS lanes with the
 // team's butterfly levels below ROWS and stores that node (device-coherent);
 // the slice whose arrival completes the chunk's count applies the levels
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(MAXT) reduce_kernel(Op op, ReduceArgs a) {
 // that are not whole (the last chunk, when W does not divide n) are folded
 // by wave 0 alone, as reduce_kernel folds them.  The same chunk values, the
 // same 1-pass arrival and fold as reduce_kernel.
-template <class Op, int COMBINE, int FINAL, int VEC, int ROWS>
+template <class Op, int ORDER, int COMBINE, int FINAL, int VEC, int ROWS>
 __global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op op,
                                                                                ReduceArgs a) {
   using T = typename Op::T;
@@ -125,8 +125,9 @@ __global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op 
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   T* partials = static_cast<T*>(a.partials);
+  static_assert(ORDER == kContiguous || VEC == 1, "strided slices are scalar lanes");
   const int Cel = a.C * VEC;
-  const int S = a.team / ROWS;   // slices per chunk
+  const int S = a.L / ROWS;   // slices per chunk
   for (int64_t w = blockIdx.x; w < a.items * S; w += gridDim.x) {
     const int64_t g = w / S;
     const int s = static_cast<int>(w % S);
@@ -135,10 +136,17 @@ __global__ void __launch_bounds__(kWave*(1 + kFedLoaders)) fed_reduce_kernel(Op 
     const int64_t rest = a.n - g * a.W;
     const int limit = static_cast<int>(rest < a.W ? rest : a.W);
     T acc[VEC];
-    if (limit == a.W)
-      fed_fold<Op, VEC, ROWS>(view, Cel, wave, lane, row0, ring, acc);
-    else if (wave == 0)
-      contiguous_staged<Op, VEC>(view, lane < ROWS, row0 + lane, a.C, limit, acc, ring);
+    if constexpr (ORDER == kStrided) {
+      if (limit == a.W)
+        fed_fold_strided<Op, ROWS>(view, a.L, a.C, wave, lane, row0, ring, acc[0]);
+      else if (wave == 0)
+        lane_folds<Op, kStrided, 1>(view, lane < ROWS, row0 + lane, a.L, a.C, limit, acc);
+    } else {
+      if (limit == a.W)
+        fed_fold<Op, VEC, ROWS>(view, Cel, wave, lane, row0, ring, acc);
+      else if (wave == 0)
+        contiguous_staged<Op, VEC>(view, lane < ROWS, row0 + lane, a.C, limit, acc, ring);
+    }
     if (wave == 0) {
       if constexpr (COMBINE == kNone) {
         if (lane < ROWS) {
@@ -263,9 +271,34 @@ hipError_t with_reduce_shape(const Plan& p, F&& f) {
 // brings the workspace's split region (`can_split`); a 64-lane tree team may
 // also stay whole.
 template <int NOPS>
+int fed_rows_strided(const Plan& p, bool can_split) {
+  // scalar strided lanes, L a power of two from 16 to 512, whole tiles of
+  // kFedStrideRows steps; a tree needs the split region beyond one slice
+  if (p.V != 1 || p.combine == DPIA_COMBINE_SEQ) return 0;
+  if (p.L < 16 || p.L > 512 || (p.L & (p.L - 1)) || p.C % kFedStrideRows) return 0;
+  const int64_t cus = device_cus();
+  if (p.items >= cus) return 0;
+  const bool split = can_split && p.split_off;
+  const int64_t ntiles = p.C / kFedStrideRows;
+  auto fits = [&](int depth) { return ntiles >= depth && ntiles % depth == 0; };
+  auto ok = [&](int rows, int depth) {
+    const int64_t per = p.L / rows;
+    if (rows > p.L || p.items * per > cus || !fits(depth)) return false;
+    if (p.combine == DPIA_COMBINE_TREE && per > 1 && (!split || per > kSplitMax)) return false;
+    return true;
+  };
+  if (ok(16, fed_depth<16, NOPS>())) return 16;
+  if (ok(32, fed_depth<32, NOPS>())) return 32;
+  if (ok(kWave, fed_depth<kWave, NOPS>())) return kWave;
+  return 0;
+}
+
+template <int NOPS>
 int fed_rows(const Plan& p, bool can_split) {
-  if (!DPIA_FED || !p.stage || p.order != DPIA_ORDER_CONTIGUOUS) return 0;
+  if (!DPIA_FED) return 0;
   if (p.op != DPIA_OP_DOT && p.op != DPIA_OP_ASUM) return 0;
+  if (p.order == DPIA_ORDER_STRIDED) return fed_rows_strided<NOPS>(p, can_split);
+  if (!p.stage || p.order != DPIA_ORDER_CONTIGUOUS) return 0;
   if (p.teams_per_wg != 1 || p.combine == DPIA_COMBINE_SEQ) return 0;
   if (p.V != 1 && p.V != 4) return 0;
   const bool split = can_split && p.split_off && p.combine == DPIA_COMBINE_TREE && p.V == 1;
@@ -287,17 +320,26 @@ int fed_rows(const Plan& p, bool can_split) {
 template <class Op, int FINAL>
 hipError_t launch_fed(const Plan& p, const Op& op, const ReduceArgs& a, int rows,
                       hipStream_t stream) {
-  const int64_t grid = p.items * (p.team / rows);
-  size_t lds = p.stage_off + static_cast<size_t>(fed_ring_floats()) * sizeof(float);
+  const int64_t grid = p.items * (p.L / rows);
+  // the ring from the start of the LDS: the kernel's combines within one
+  // wavefront need no LDS, and the 1-pass fold uses it after the chunks
+  size_t lds = static_cast<size_t>(fed_ring_floats()) * sizeof(float);
   const size_t fold = static_cast<size_t>(kFoldBlock) * sizeof(typename Op::T);
   if (fold > lds) lds = fold;
   lds = (lds + 16 + 15) / 16 * 16;
   Op op_copy = op;
   ReduceArgs a_copy = a;
+  a_copy.stage_off = 0;
   void* args[] = {&op_copy, &a_copy};
+  const bool strided = p.order == DPIA_ORDER_STRIDED;
   auto go = [&](auto comb, auto vec, auto nrows) {
-    auto kern = fed_reduce_kernel<Op, decltype(comb)::value, FINAL, decltype(vec)::value,
-                                  decltype(nrows)::value>;
+    constexpr int COMBINE = decltype(comb)::value;
+    constexpr int VEC = decltype(vec)::value;
+    constexpr int ROWS = decltype(nrows)::value;
+    auto kern = strided && VEC == 1
+                    ? fed_reduce_kernel<Op, (VEC == 1 ? kStrided : kContiguous), COMBINE, FINAL,
+                                        VEC, ROWS>
+                    : fed_reduce_kernel<Op, kContiguous, COMBINE, FINAL, VEC, ROWS>;
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
                            dim3(kWave * (1 + kFedLoaders)), args, lds, stream);
   };
@@ -320,13 +362,13 @@ hipError_t launch_fed(const Plan& p, const Op& op, const ReduceArgs& a, int rows
 template <class Op, int FINAL>
 hipError_t launch_chunks(const Plan& p, const Op& op, const ReduceArgs& a, hipStream_t stream) {
   if (p.items == 0) return hipSuccess;
-  // (the loaders keep the tiles in flight, so DotF32Deeper's second staged
-  // tile would only add registers; DotF32Deep serves strided lanes only)
+  // (the loaders keep the tiles in flight, so the deeper load batches of
+  // DotF32Deep and DotF32Deeper would only add registers)
   const bool can_split = a.nodes != nullptr;
-  if constexpr (std::is_same<Op, DotF32Deeper>::value) {
+  if constexpr (std::is_same<Op, DotF32Deeper>::value || std::is_same<Op, DotF32Deep>::value) {
     if (const int rows = fed_rows<2>(p, can_split))
       return launch_fed<DotF32, FINAL>(p, DotF32{op.x, op.y}, a, rows, stream);
-  } else if constexpr (Op::View::kStageable && !std::is_same<Op, DotF32Deep>::value) {
+  } else if constexpr (Op::View::kStageable) {
     const int rows = fed_rows<Op::View::kOps>(p, can_split);
     if (rows && (FINAL == kFinalPlain || (p.V == 1 && p.combine == DPIA_COMBINE_TREE)))
       return launch_fed<Op, FINAL>(p, op, a, rows, stream);

@@ -6,7 +6,8 @@ with 64-element batches, a batch of instances drawn like the benchmark's
 with an odd number of tiles, the outer fold of many chunk values at the
 boundaries of the steps it copies them in, and staged contiguous lanes fed
 by loader wavefronts (also in one pass, with many chunk values, and
-tree-combined teams split over work-groups).
+tree-combined teams split over work-groups), and strided lanes fed the same
+way.
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -455,3 +456,38 @@ def test_split_tree_teams_compensated(accum):
     want = S.dot(x, y, to_plan(s))
     for passes in (1, 2):
         assert_same_bits(gpu_dot(x, y, s.with_(passes=passes)), want, f"passes={passes}")
+
+
+# ------------------------------------------------ strided slices
+# Scalar strided strategies with few chunks: each work-group folds a slice
+# of 16, 32 or 64 lanes, one per thread, from 64-step tiles that loader
+# wavefronts bring into LDS (step j of all lanes is one contiguous row);
+# tree-combined chunks end in the split combine.  Ragged last chunks are
+# folded by lane folds of one lane per thread.
+STRIDED = {
+    "L256-C8192-tree": dict(seq_len=8192, local_size=256, order=T_),
+    "L64-C1024-tree": dict(seq_len=1024, local_size=64, order=T_),
+    "L128-C512-none": dict(seq_len=512, local_size=128, order=T_, wg_combine=dp.NONE),
+    "L512-C256-tree": dict(seq_len=256, local_size=512, order=T_),
+}
+
+
+@pytest.mark.parametrize("chunks,short", [(1, 0), (3, 0), (13, 5), (30, 0), (60, 1000)])
+@pytest.mark.parametrize("name", sorted(STRIDED))
+def test_strided_slices_fed_by_loader_wavefronts(name, chunks, short):
+    import torch
+    s = dp.Strategy(**STRIDED[name])
+    W = s.seq_len * s.local_size
+    if W * chunks > (1 << 25):
+        pytest.skip("the long rows reach the same path with fewer chunks")
+    n = W * chunks - short
+    print(f"strided slices {name} chunks={chunks} n={n}", flush=True)
+    x, y = discriminating(130 + chunks, n)
+    p = to_plan(s)
+    for passes in (1, 2):
+        sp = s.with_(passes=passes)
+        assert_same_bits(gpu_dot(x, y, sp), S.dot(x, y, p), f"dot passes={passes}")
+        assert_same_bits(gpu_asum(x, sp), S.asum(x, p), f"asum passes={passes}")
+    c = dp.chunks(dp.OP_DOT, s, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    assert_same_bits(c.cpu().numpy().view(np.float32), S.dot_chunks(x, y, p), "chunk values")
