@@ -676,8 +676,9 @@ struct StageableCodes<V, decltype(void(V::kStageableCodes))> {
 };
 
 // `stage`: this wavefront's LDS staging region (contiguous order, stageable
-// views) or nullptr for direct loads.  The choice is uniform per launch.
-template <class Op, int ORDER, int NV, int COMBINE, class View>
+// views; with SS, also the strided order with one thread per chunk) or
+// nullptr for direct loads.  The choice is uniform per launch.
+template <class Op, int ORDER, int NV, int COMBINE, bool SS = false, class View>
 __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool active, int t,
                                                       int team, int L, int C, int limit,
                                                       typename Op::T* scratch,
@@ -687,6 +688,14 @@ __device__ __forceinline__ typename Op::T chunk_value(const View& view, bool act
   if constexpr (ORDER == kContiguous && View::kStageable) {
     if (stage != nullptr) {
       contiguous_staged<Op, 1>(view, active, t, C, limit, acc, stage);
+      return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
+    }
+  } else if constexpr (ORDER == kStrided && SS && View::kStageable && 4 % NV == 0) {
+    // one thread holds all NV = L lanes of its chunk (team 1; the plan
+    // stages only then): its chunk is C * NV contiguous elements, element e
+    // belonging to lane e % NV, which contiguous_staged folds as components
+    if (stage != nullptr) {
+      contiguous_staged<Op, NV>(view, active, 0, C, limit, acc, stage);
       return combine_lanes<typename Op::Arith, NL, COMBINE>(acc, t, team, L, scratch);
     }
   } else if constexpr (ORDER == kContiguous && StageableCodes<View>::value) {

@@ -192,7 +192,10 @@ __global__ void __launch_bounds__(256) gemv_block_kernel(Op op, GemvArgs a) {
 
 // MAXT: the largest work-group it is launched with (256 or 1024); the
 // 256-thread build may use twice the registers of the 1024-thread one.
-template <class Op, int ORDER, int NV, int COMBINE, int MAXT>
+// SS: strided rows of one thread each, staged through LDS (a build of its
+// own: the staged fold's registers would lower every other strided launch's
+// occupancy).
+template <class Op, int ORDER, int NV, int COMBINE, int MAXT, bool SS = false>
 __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
@@ -201,9 +204,11 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
   const int team_id = threadIdx.x / a.team;
   const int t = threadIdx.x - team_id * a.team;
   T* scratch = lds + team_id * a.team_lds_elems;
-  float* stage = a.stage_off < 0 ? nullptr
-                                 : reinterpret_cast<float*>(lds_raw + a.stage_off) +
-                                       (threadIdx.x / kWave) * stage_floats(kWave);
+  // (staging needs work-groups of at most 256 threads: none in the 1024 build)
+  float* stage = MAXT > 256 || a.stage_off < 0
+                     ? nullptr
+                     : reinterpret_cast<float*>(lds_raw + a.stage_off) +
+                           (threadIdx.x / kWave) * stage_floats(kWave);
   const int64_t stride = static_cast<int64_t>(gridDim.x) * a.teams_per_wg;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * a.teams_per_wg; base < a.m;
        base += stride) {
@@ -213,13 +218,13 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
     // elements of each row part that exist (k may stop short of W * parts:
     // the row is zero-extended)
     const int lim0 = static_cast<int>(a.k < a.W ? a.k : a.W);
-    T v = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 0, a.lda, a.W), active, t, a.team,
-                                              a.L, a.C, lim0, scratch, stage);
+    T v = chunk_value<Op, ORDER, NV, COMBINE, SS>(op.part(r, 0, a.lda, a.W), active, t, a.team,
+                                                  a.L, a.C, lim0, scratch, stage);
     if (a.parts == 2) {
       const int lim1 = static_cast<int>(a.k - a.W);
-      const T h1 = chunk_value<Op, ORDER, NV, COMBINE>(op.part(r, 1, a.lda, a.W), active, t,
-                                                       a.team, a.L, a.C, lim1 > 0 ? lim1 : 0,
-                                                       scratch, stage);
+      const T h1 = chunk_value<Op, ORDER, NV, COMBINE, SS>(op.part(r, 1, a.lda, a.W), active, t,
+                                                           a.team, a.L, a.C, lim1 > 0 ? lim1 : 0,
+                                                           scratch, stage);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
     if (active && t == 0) op.store(row, v);
@@ -273,6 +278,11 @@ hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipS
       constexpr int NV = decltype(nvc)::value;
       auto kern = p.wg_threads <= 256 ? gemv_kernel<Op, ORDER, NV, COMBINE, 256>
                                       : gemv_kernel<Op, ORDER, NV, COMBINE, 1024>;
+      if constexpr (ORDER == kStrided && NV <= 4) {
+        // (the staged fold loads 16-byte pieces of every row)
+        if (p.stage && p.wg_threads <= 256 && lda % 4 == 0)
+          kern = gemv_kernel<Op, ORDER, NV, COMBINE, 256, true>;
+      }
       Op op_copy = op;
       void* args[] = {&op_copy, &a};
       return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),

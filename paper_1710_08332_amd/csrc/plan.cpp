@@ -229,6 +229,14 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
   if (op == DPIA_OP_GEMV && (dt == DPIA_BF16 || dt == DPIA_FP8_E4M3))
     q.stage = q.order == DPIA_ORDER_CONTIGUOUS && q.C % kStage == 0 &&
               q.wg_threads <= 256 && q.wg_threads % 64 == 0;
+  // binary32 gemv rows in the strided order with one thread per row (L = 1,
+  // 2 or 4 lanes, all in that thread): the thread walks its row part
+  // contiguously, lane l taking elements l, l + L, ..., which is the staged
+  // contiguous fold with L components; without staging every load
+  // instruction of a wavefront touched 64 rows
+  if (op == DPIA_OP_GEMV && dt == DPIA_F32 && q.order == DPIA_ORDER_STRIDED && q.team == 1 &&
+      (q.C * q.L) % kStage == 0 && q.wg_threads <= 256 && q.wg_threads % 64 == 0)
+    q.stage = true;
   q.stage_off = 0;
   if (q.stage) {
     q.stage_off = round_up(lds, 16);

@@ -7,7 +7,8 @@ with an odd number of tiles, the outer fold of many chunk values at the
 boundaries of the steps it copies them in, and staged contiguous lanes fed
 by loader wavefronts (also in one pass, with many chunk values, and
 tree-combined teams split over work-groups), and strided lanes fed the same
-way.
+way; binary32 gemv rows of one thread each in the strided order, staged
+through LDS.
 
 Every comparison is bit for bit against the oracle on the same inputs.  Where
 the full problem is too large for the oracle, it is evaluated on sampled
@@ -491,3 +492,27 @@ def test_strided_slices_fed_by_loader_wavefronts(name, chunks, short):
     c = dp.chunks(dp.OP_DOT, s, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
     torch.cuda.synchronize()
     assert_same_bits(c.cpu().numpy().view(np.float32), S.dot_chunks(x, y, p), "chunk values")
+
+
+# ------------------------------------------------ strided gemv rows, one thread each
+# A binary32 gemv in the strided order with L = 1, 2 or 4 lanes per row has
+# one thread per row, holding all the row's lanes: it is folded through the
+# contiguous LDS staging with L components.  One or two row parts, k that
+# leaves the last part short, m not a multiple of the rows per work-group,
+# and an odd k (L = 1: rows not 16-byte aligned, so not staged).
+@pytest.mark.parametrize("L", [1, 2, 4])
+@pytest.mark.parametrize("k,parts", [(4096, 1), (4096 - 40, 1), (2 * 2048 + 32, 2),
+                                     (4096 - 3, 1)])
+def test_strided_gemv_rows_of_one_thread_staged(L, k, parts):
+    if k % L:
+        pytest.skip("rows must stay aligned for L-lane loads (the call rejects this lda)")
+    C = -(-k // (L * parts))
+    C = -(-C // 32) * 32                  # whole 32-element tiles per row part
+    s = dp.Strategy(seq_len=C, local_size=L, order=T_, rows_per_wg=4, row_parts=parts)
+    m = 300                               # 256 rows per work-group: a partial last one
+    print(f"strided gemv L={L} k={k} parts={parts} C={C}", flush=True)
+    g = np.random.default_rng(L * 7 + k)
+    A = (g.standard_normal((m, k)) * 2.0 ** g.uniform(-8, 8, (m, k))).astype(np.float32)
+    x = (g.standard_normal(k) * 2.0 ** g.uniform(-8, 8, k)).astype(np.float32)
+    from tests.gpu_util import gpu_gemv
+    assert_same_bits(gpu_gemv(A, x, s), S.gemv(A, x, to_plan(s)), f"L={L} k={k}")
