@@ -503,6 +503,53 @@ def test_single_calls_in_a_graph_replay_exactly():
                 f"replay {rep} call {i}"
 
 
+def test_dots_and_gemvs_on_two_graph_branches_replay_exactly():
+    # the headline step's strategies with the dots on one graph branch and the
+    # gemvs (three copies of A in turn) on another, joined at the end: every
+    # replay reproduces the eager bits, which equal the oracle's
+    import torch
+    dot_s = dp.Strategy(seq_len=256, local_size=1024, order=T_, wg_combine=TREE, passes=1)
+    gemv_s = dp.Strategy(seq_len=32, local_size=256, order=T_, wg_combine=TREE, rows_per_wg=4)
+    n, m, k, steps = (1 << 22) + 77, 256, 8192, 6
+    x, y = synthetic.dot_inputs(n, synthetic.SEEDS["small"])
+    A, xv = synthetic.gemv_inputs(m, k, synthetic.SEEDS["scale"])
+    xt, yt, xvt = cuda(x), cuda(y), cuda(xv)
+    Ats = [cuda(A) for _ in range(3)]
+    out = torch.empty(1, dtype=torch.float32, device="cuda")
+    yg = torch.empty(m, dtype=torch.float32, device="cuda")
+    ws = dp.workspace(dot_s, dp.OP_DOT, dp.F32, 0, n)
+    dp.dot(xt, yt, dot_s, out=out, ws=ws)
+    dp.gemv(Ats[0], xvt, gemv_s, y=yg)
+    torch.cuda.synchronize()
+    assert_same_bits(out.cpu().numpy()[0], S.dot(x, y, to_plan(dot_s)), "eager dot")
+    assert_same_bits(yg.cpu().numpy(), S.gemv(A, xv, to_plan(gemv_s)), "eager gemv")
+    eager = (out.clone(), yg.clone())
+    main, branch = torch.cuda.Stream(), torch.cuda.Stream()
+    main.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(main):
+        with torch.cuda.graph(graph, stream=main):
+            branch.wait_stream(main)
+            for _ in range(steps):
+                dp.dot(xt, yt, dot_s, out=out, ws=ws)
+            with torch.cuda.stream(branch):
+                for j in range(steps):
+                    dp.gemv(Ats[j % 3], xvt, gemv_s, y=yg)
+            main.wait_stream(branch)
+    torch.cuda.current_stream().wait_stream(main)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        out.fill_(float(rep) - 5.0)                    # eager work between replays
+        yg.fill_(float(rep) + 3.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int32), eager[0].view(torch.int32)), f"dot, replay {rep}"
+        assert torch.equal(yg.view(torch.int32), eager[1].view(torch.int32)), f"gemv, replay {rep}"
+    # the 1-pass arrival counter is left at zero by every call
+    assert not ws[-256:].any(), "arrival-counter block left non-zero"
+
+
 @pytest.mark.parametrize("kw", [dict(seq_len=16, local_size=256, order=T_),
                                 dict(seq_len=64, local_size=64, order=C_),     # staged, tile 64
                                 dict(seq_len=96, local_size=128, order=C_),    # staged, tile 32
