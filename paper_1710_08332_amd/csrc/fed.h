@@ -60,6 +60,10 @@ static_assert(fed_ring_floats() >= stage_floats(kWave), "the ring holds a stagin
 // r of operand o in ring slot s starts at ((s * NOPS + o) * 64 + r) *
 // kFedRow floats.  An uncombined strategy may split a chunk's rows over
 // several work-groups (ROWS < 64): its lanes' values are independent.
+// Rows lie `rstride` elements apart (0: Cel, the lane rows of a chunk).
+// SHARED1: operand 1 is the same Cel elements for every row (the x of a
+// gemv, whose rows are the rows of A): read with cached loads, since every
+// row and every work-group reads it again.
 template <int ROWS, int NOPS>
 constexpr int fed_per() { return ROWS / kFedRowsPerLoad / kFedLoaders; }
 // Tiles in flight: every loader keeps 32 sixteen-byte loads outstanding, up
@@ -70,9 +74,10 @@ constexpr int fed_depth() {
                                                             : kFedMaxDepth;
 }
 
-template <class Op, int VEC, int ROWS, class View>
+template <class Op, int VEC, int ROWS, bool SHARED1 = false, class View>
 __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
-                                         float* ring, typename Op::T (&acc)[VEC]) {
+                                         float* ring, typename Op::T (&acc)[VEC],
+                                         int rstride = 0) {
   constexpr int NOPS = View::kOps;
   constexpr int kPer = fed_per<ROWS, NOPS>();       // load instructions per operand per tile
   constexpr int D = fed_depth<ROWS, NOPS>();
@@ -89,21 +94,24 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
   const int q = wave - 1;
   const float* rowp[NOPS][kPer];
   int rofs[kPer];
+  const int64_t rs = rstride > 0 ? rstride : Cel;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int r = (q * kPer + k) * kFedRowsPerLoad + lane / kFedVec;
     rofs[k] = r * kFedRow + part * 4;
 #pragma unroll
-    for (int o = 0; o < NOPS; ++o) rowp[o][k] = view.operand(o) + (row0 + r) * Cel + part * 4;
+    for (int o = 0; o < NOPS; ++o)
+      rowp[o][k] = view.operand(o) + (SHARED1 && o == 1 ? 0 : (row0 + r) * rs) + part * 4;
   }
   f32x4 regs[D][NOPS][kPer];
   auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
 #pragma unroll
-      for (int o = 0; o < NOPS; ++o)
-        rg[o][k] = ld<DPIA_NT_LOADS != 0>(reinterpret_cast<const f32x4*>(rowp[o][k] +
-                                                                          tile * kFedStage));
+      for (int o = 0; o < NOPS; ++o) {
+        const f32x4* g = reinterpret_cast<const f32x4*>(rowp[o][k] + tile * kFedStage);
+        rg[o][k] = SHARED1 && o == 1 ? ld<false>(g) : ld<DPIA_NT_LOADS != 0>(g);
+      }
     // tiles are requested in round order, so that each round waits for its
     // own tile only (the scheduler would interleave the sets' loads)
     __builtin_amdgcn_sched_barrier(0);

@@ -8,6 +8,7 @@
 // multiply; fp8 rows are scaled after the reduction: y[r] = scale[r] * sum.
 // No cross-work-group step: each team owns whole rows of y.
 #include "device.h"
+#include "fed.h"
 #include "ops.h"
 #include "host.h"
 #include "plan.h"
@@ -231,6 +232,108 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
   }
 }
 
+// Rows of one thread each (a team of one thread: the strided order with
+// L = NL lanes held as that thread's components, or a single contiguous
+// lane), binary32 A, row parts of whole tiles, fed by loader wavefronts.
+// The strategy's work-groups of R rows give each busy compute unit a
+// wavefront or two (16384 rows of R = 128: 128 work-groups), too few loads in
+// flight to stream A.  The rows are independent, so a hardware work-group
+// here takes ROWS consecutive rows of its own: wave 0 folds them (lane l row
+// row0 + l, element e of a part into component e % NL, in increasing e, as
+// chunk_value's staged fold does), kFedLoaders wavefronts load A's rows and
+// x into the LDS ring.  The components are combined by combine_lanes and the
+// parts by tree_node, as in gemv_kernel: every row's association is the
+// strategy's.
+template <class Op, int NL, int COMBINE, int ROWS>
+__global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op op, GemvArgs a) {
+  using T = typename Op::T;
+  using A = typename Op::Arith;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* ring = reinterpret_cast<float*>(lds_raw);
+  // each thread's combine region (a team of one: its NL lane values)
+  T* scratch = reinterpret_cast<T*>(ring + fed_ring_floats()) + threadIdx.x * NL;
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  const int lane = static_cast<int>(threadIdx.x) % kWave;
+  for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS; row0 < a.m;
+       row0 += static_cast<int64_t>(gridDim.x) * ROWS) {
+    T acc[NL];
+    fed_fold<Op, NL, ROWS, true>(op.part(row0, 0, a.lda, a.W), a.W, wave, lane, 0, ring, acc,
+                                 static_cast<int>(a.lda));
+    T v = combine_lanes<A, NL, COMBINE>(acc, 0, 1, a.L, scratch);
+    if (a.parts == 2) {
+      fed_fold<Op, NL, ROWS, true>(op.part(row0, 1, a.lda, a.W), a.W, wave, lane, 0, ring, acc,
+                                   static_cast<int>(a.lda));
+      const T h1 = combine_lanes<A, NL, COMBINE>(acc, 0, 1, a.L, scratch);
+      v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
+    }
+    if (wave == 0 && lane < ROWS) op.store(row0 + lane, v);
+  }
+}
+
+// Rows per work-group of gemv_fed_kernel for this plan, or 0 where it does
+// not apply: teams of one thread, binary32 A (the caller's check), every row
+// part whole (k = W * parts) and at least 16 tiles of 64 elements long,
+// 16-byte aligned rows, and m a multiple of the rows.  The most rows that
+// still give every compute unit a work-group.
+template <int ROWS>
+constexpr bool fed_gemv_fits(int64_t tiles) {
+  return tiles % fed_depth<ROWS, 2>() == 0;
+}
+static int fed_gemv_rows(const Plan& p, int64_t m, int64_t lda) {
+  if (p.team != 1 || m <= 0 || lda % 4 || lda > (int64_t(1) << 24)) return 0;
+  const bool lanes = p.order == DPIA_ORDER_STRIDED
+                         ? (p.nv == p.L && (p.L == 1 || p.L == 2 || p.L == 4))
+                         : p.L == 1;
+  if (!lanes || p.W % kFedStage || p.k != p.W * p.row_parts) return 0;
+  const int64_t tiles = p.W / kFedStage;
+  if (tiles < 16) return 0;
+  const int64_t cus = device_cus();
+  if (m % 64 == 0 && m / 64 >= cus && fed_gemv_fits<64>(tiles)) return 64;
+  if (m % 32 == 0 && m / 32 >= cus && fed_gemv_fits<32>(tiles)) return 32;
+  if (m % 16 == 0 && fed_gemv_fits<16>(tiles)) return 16;
+  return 0;
+}
+
+template <class Op>
+hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, int rows,
+                           hipStream_t stream) {
+  GemvArgs a{};
+  a.m = m;
+  a.k = p.k;
+  a.lda = lda;
+  a.W = static_cast<int>(p.W);
+  a.L = static_cast<int>(p.L);
+  a.C = static_cast<int>(p.C);
+  a.team = 1;
+  a.teams_per_wg = rows;
+  a.parts = p.row_parts;
+  a.stage_off = -1;
+  const int nl = p.order == DPIA_ORDER_STRIDED ? p.nv : 1;
+  const int64_t need = m / rows;
+  const int64_t grid = p.max_grid && need > static_cast<int64_t>(p.max_grid)
+                           ? static_cast<int64_t>(p.max_grid) : need;
+  const size_t lds = sizeof(float) * fed_ring_floats() +
+                     sizeof(typename Op::T) * kWave * (1 + kFedLoaders) * 4;
+  auto go = [&](auto nlc, auto comb, auto rc) {
+    constexpr int NL = decltype(nlc)::value;
+    constexpr int COMBINE = decltype(comb)::value;
+    constexpr int ROWS = decltype(rc)::value;
+    auto kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS>;
+    Op op_copy = op;
+    void* args[] = {&op_copy, &a};
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                           dim3(kWave * (1 + kFedLoaders)), args, lds, stream);
+  };
+  auto by_rows = [&](auto nlc, auto comb) {
+    return rows == 64 ? go(nlc, comb, ic<64>{})
+                      : (rows == 32 ? go(nlc, comb, ic<32>{}) : go(nlc, comb, ic<16>{}));
+  };
+  auto by_combine = [&](auto nlc) {
+    return p.combine == DPIA_COMBINE_TREE ? by_rows(nlc, ic<kTree>{}) : by_rows(nlc, ic<kSeq>{});
+  };
+  return nl == 4 ? by_combine(ic<4>{}) : (nl == 2 ? by_combine(ic<2>{}) : by_combine(ic<1>{}));
+}
+
 template <class Op, int MAXNV>
 hipError_t launch_gemv(const Plan& p, const Op& op, int64_t m, int64_t lda, hipStream_t stream,
                        int rb = 1) {
@@ -351,7 +454,12 @@ dpia_status gemv_impl(const char* name, const dpia_strategy* s, dpia_dtype a_dt,
   };
   switch (a_dt) {
     case DPIA_F32:
-      if (p.order == DPIA_ORDER_STRIDED && p.team < 4)
+      if (const int rows = fed_gemv_rows(p, m, lda))
+        e = launch_gemv_fed(
+            p, with_epilogue(GemvF32{static_cast<const float*>(A), static_cast<const float*>(x),
+                                     nullptr, static_cast<float*>(y)}),
+            m, lda, rows, hs);
+      else if (p.order == DPIA_ORDER_STRIDED && p.team < 4)
         e = launch_gemv<GemvF32Cached, 4>(
             p, with_epilogue(GemvF32Cached{static_cast<const float*>(A),
                                            static_cast<const float*>(x), nullptr,
