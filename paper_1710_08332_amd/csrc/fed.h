@@ -61,9 +61,10 @@ static_assert(fed_ring_floats() >= stage_floats(kWave), "the ring holds a stagin
 // kFedRow floats.  An uncombined strategy may split a chunk's rows over
 // several work-groups (ROWS < 64): its lanes' values are independent.
 // Rows lie `rstride` elements apart (0: Cel, the lane rows of a chunk).
-// SHARED1: operand 1 is the same Cel elements for every row (the x of a
-// gemv, whose rows are the rows of A): read with cached loads, since every
-// row and every work-group reads it again.
+// SHARED1 (a gemv: operand 0 is A, operand 1 is x): lane row q is lane
+// q % lanes of matrix row q / lanes, Cel elements at (q % lanes) * Cel of
+// that row (rows of A `rstride` apart) and of x.  x is read with cached
+// loads, since every row and every work-group reads it again.
 template <int ROWS, int NOPS>
 constexpr int fed_per() { return ROWS / kFedRowsPerLoad / kFedLoaders; }
 // Tiles in flight: every loader keeps 32 sixteen-byte loads outstanding, up
@@ -77,7 +78,7 @@ constexpr int fed_depth() {
 template <class Op, int VEC, int ROWS, bool SHARED1 = false, class View>
 __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
                                          float* ring, typename Op::T (&acc)[VEC],
-                                         int rstride = 0) {
+                                         int rstride = 0, int lanes = 1) {
   constexpr int NOPS = View::kOps;
   constexpr int kPer = fed_per<ROWS, NOPS>();       // load instructions per operand per tile
   constexpr int D = fed_depth<ROWS, NOPS>();
@@ -99,9 +100,14 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
   for (int k = 0; k < kPer; ++k) {
     const int r = (q * kPer + k) * kFedRowsPerLoad + lane / kFedVec;
     rofs[k] = r * kFedRow + part * 4;
+    if constexpr (SHARED1) {
+      const int mr = (row0 + r) / lanes, ml = (row0 + r) - mr * lanes;
+      rowp[0][k] = view.operand(0) + mr * rs + static_cast<int64_t>(ml) * Cel + part * 4;
+      rowp[1][k] = view.operand(1) + static_cast<int64_t>(ml) * Cel + part * 4;
+    } else {
 #pragma unroll
-    for (int o = 0; o < NOPS; ++o)
-      rowp[o][k] = view.operand(o) + (SHARED1 && o == 1 ? 0 : (row0 + r) * rs) + part * 4;
+      for (int o = 0; o < NOPS; ++o) rowp[o][k] = view.operand(o) + (row0 + r) * rs + part * 4;
+    }
   }
   f32x4 regs[D][NOPS][kPer];
   auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {

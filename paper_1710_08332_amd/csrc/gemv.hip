@@ -232,65 +232,80 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
   }
 }
 
-// Rows of one thread each (a team of one thread: the strided order with
-// L = NL lanes held as that thread's components, or a single contiguous
-// lane), binary32 A, row parts of whole tiles, fed by loader wavefronts.
-// The strategy's work-groups of R rows give each busy compute unit a
-// wavefront or two (16384 rows of R = 128: 128 work-groups), too few loads in
-// flight to stream A.  The rows are independent, so a hardware work-group
-// here takes ROWS consecutive rows of its own: wave 0 folds them (lane l row
-// row0 + l, element e of a part into component e % NL, in increasing e, as
-// chunk_value's staged fold does), kFedLoaders wavefronts load A's rows and
-// x into the LDS ring.  The components are combined by combine_lanes and the
-// parts by tree_node, as in gemv_kernel: every row's association is the
-// strategy's.
+// Binary32 rows fed by loader wavefronts: teams of one thread (the strided
+// order with L = NL lanes held as that thread's components, or one
+// contiguous lane) and contiguous teams of L threads (one lane each), row
+// parts of whole tiles.  The strategy's work-groups of R rows give each busy
+// compute unit a wavefront or two (16384 rows of R = 128: 128 work-groups),
+// too few loads in flight to stream A.  The rows are independent, so a
+// hardware work-group here takes ROWS lane rows of its own, ROWS / team
+// consecutive matrix rows: wave 0 folds them (lane q the Cel = W / team
+// elements of lane q % team of its row, element e into component e % NL, in
+// increasing e, as chunk_value's staged folds do), kFedLoaders wavefronts
+// load A and x into the LDS ring.  The lanes are combined by combine_lanes
+// over teams of `team` adjacent lanes of wave 0 and the parts by tree_node,
+// as in gemv_kernel: every row's association is the strategy's.
 template <class Op, int NL, int COMBINE, int ROWS>
 __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* ring = reinterpret_cast<float*>(lds_raw);
-  // each thread's combine region (a team of one: its NL lane values)
-  T* scratch = reinterpret_cast<T*>(ring + fed_ring_floats()) + threadIdx.x * NL;
+  const int team = a.team;
+  const int t = static_cast<int>(threadIdx.x) % team;
+  // each team's combine region (its team * NL lane values)
+  T* scratch = reinterpret_cast<T*>(ring + fed_ring_floats()) +
+               (static_cast<int>(threadIdx.x) - t) * NL;
   const int wave = static_cast<int>(threadIdx.x) / kWave;
   const int lane = static_cast<int>(threadIdx.x) % kWave;
-  for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS; row0 < a.m;
-       row0 += static_cast<int64_t>(gridDim.x) * ROWS) {
+  const int cel = a.W / team;
+  const int rows_per_wg = ROWS / team;
+  for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg; row0 < a.m;
+       row0 += static_cast<int64_t>(gridDim.x) * rows_per_wg) {
     T acc[NL];
-    fed_fold<Op, NL, ROWS, true>(op.part(row0, 0, a.lda, a.W), a.W, wave, lane, 0, ring, acc,
-                                 static_cast<int>(a.lda));
-    T v = combine_lanes<A, NL, COMBINE>(acc, 0, 1, a.L, scratch);
+    fed_fold<Op, NL, ROWS, true>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0, ring, acc,
+                                 static_cast<int>(a.lda), team);
+    T v = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
     if (a.parts == 2) {
-      fed_fold<Op, NL, ROWS, true>(op.part(row0, 1, a.lda, a.W), a.W, wave, lane, 0, ring, acc,
-                                   static_cast<int>(a.lda));
-      const T h1 = combine_lanes<A, NL, COMBINE>(acc, 0, 1, a.L, scratch);
+      fed_fold<Op, NL, ROWS, true>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0, ring, acc,
+                                   static_cast<int>(a.lda), team);
+      const T h1 = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
-    if (wave == 0 && lane < ROWS) op.store(row0 + lane, v);
+    if (wave == 0 && lane < ROWS && t == 0) op.store(row0 + lane / team, v);
   }
 }
 
-// Rows per work-group of gemv_fed_kernel for this plan, or 0 where it does
-// not apply: teams of one thread, binary32 A (the caller's check), every row
-// part whole (k = W * parts) and at least 16 tiles of 64 elements long,
-// 16-byte aligned rows, and m a multiple of the rows.  The most rows that
-// still give every compute unit a work-group.
+// Lane rows per work-group of gemv_fed_kernel for this plan, or 0 where it
+// does not apply: teams of one thread or contiguous teams of at most 64
+// threads, binary32 A (the caller's check), every row part whole (k = W *
+// parts) with lanes of at least 64 tiles of 64 elements, and m a multiple
+// of the matrix rows per work-group.  The most lane rows that still give
+// every compute unit a work-group.
 template <int ROWS>
 constexpr bool fed_gemv_fits(int64_t tiles) {
   return tiles % fed_depth<ROWS, 2>() == 0;
 }
 static int fed_gemv_rows(const Plan& p, int64_t m, int64_t lda) {
-  if (p.team != 1 || m <= 0 || lda % 4 || lda > (int64_t(1) << 24)) return 0;
+  if (m <= 0 || lda % 4 || lda > (int64_t(1) << 24)) return 0;
   const bool lanes = p.order == DPIA_ORDER_STRIDED
-                         ? (p.nv == p.L && (p.L == 1 || p.L == 2 || p.L == 4))
-                         : p.L == 1;
-  if (!lanes || p.W % kFedStage || p.k != p.W * p.row_parts) return 0;
-  const int64_t tiles = p.W / kFedStage;
-  if (tiles < 16) return 0;
+                         ? (p.team == 1 && p.nv == p.L && (p.L == 1 || p.L == 2 || p.L == 4))
+                         : p.team == p.L && p.L <= 64 && (p.L & (p.L - 1)) == 0;
+  if (!lanes || p.W % (int64_t(kFedStage) * p.team) || p.k != p.W * p.row_parts) return 0;
+  // (lanes of 16 tiles measured slower than gemv_kernel: 16384^2 contiguous
+  // C=1024 L=16 234.9 -> 248.3 us, L=8 with two parts 191.6 -> 251.0 us; a
+  // work-group's pipeline fills and drains every 16 rounds)
+  const int64_t tiles = p.W / p.team / kFedStage;
+  if (tiles < 64) return 0;
   const int64_t cus = device_cus();
-  if (m % 64 == 0 && m / 64 >= cus && fed_gemv_fits<64>(tiles)) return 64;
-  if (m % 32 == 0 && m / 32 >= cus && fed_gemv_fits<32>(tiles)) return 32;
-  if (m % 16 == 0 && fed_gemv_fits<16>(tiles)) return 16;
+  const int64_t lane_rows = m * p.team;
+  auto fits = [&](int rows, bool fill) {
+    return rows % p.team == 0 && m % (rows / p.team) == 0 && (!fill || lane_rows / rows >= cus);
+  };
+  if (fits(64, true) && fed_gemv_fits<64>(tiles)) return 64;
+  if (fits(32, true) && fed_gemv_fits<32>(tiles)) return 32;
+  if (fits(16, false) && fed_gemv_fits<16>(tiles)) return 16;
+  if (fits(64, false) && fed_gemv_fits<64>(tiles)) return 64;
   return 0;
 }
 
@@ -304,12 +319,12 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
   a.W = static_cast<int>(p.W);
   a.L = static_cast<int>(p.L);
   a.C = static_cast<int>(p.C);
-  a.team = 1;
-  a.teams_per_wg = rows;
+  a.team = p.order == DPIA_ORDER_STRIDED ? 1 : static_cast<int>(p.L);
+  a.teams_per_wg = rows / a.team;
   a.parts = p.row_parts;
   a.stage_off = -1;
   const int nl = p.order == DPIA_ORDER_STRIDED ? p.nv : 1;
-  const int64_t need = m / rows;
+  const int64_t need = m / a.teams_per_wg;
   const int64_t grid = p.max_grid && need > static_cast<int64_t>(p.max_grid)
                            ? static_cast<int64_t>(p.max_grid) : need;
   const size_t lds = sizeof(float) * fed_ring_floats() +

@@ -518,30 +518,38 @@ def test_strided_gemv_rows_of_one_thread_staged(L, k, parts):
     assert_same_bits(gpu_gemv(A, x, s), S.gemv(A, x, to_plan(s)), f"L={L} k={k}")
 
 
-# Rows of one thread each fed by loader wavefronts: teams of one thread
-# (strided L = 1, 2 or 4 lanes as the thread's components, or one contiguous
-# lane), binary32 A, whole row parts of at least 16 tiles of 64 elements;
-# 16, 32 or 64 rows per work-group.  (m, k, C, L, order, combine, parts,
-# lda padding)
+# Gemv rows fed by loader wavefronts: teams of one thread (strided L = 1, 2
+# or 4 lanes as the thread's components, or one contiguous lane) and
+# contiguous teams of L threads, binary32 A, whole row parts with lanes of at
+# least 64 tiles of 64 elements; 16, 32 or 64 lane rows per work-group.
+# (m, k, C, L, order, combine, parts, lda padding)
 FED_GEMV = {
     "L2-tree-16rows": (256, 16384, 8192, 2, T_, dp.TREE, 1, 0),
     "L1-2parts": (320, 16384, 8192, 1, T_, dp.TREE, 2, 0),
     "L4-tree": (64, 4096, 1024, 4, T_, dp.TREE, 1, 0),
-    "L2-seq": (48, 2048, 1024, 2, T_, dp.SEQ, 1, 0),
-    "L4-seq-2parts": (32, 4096, 512, 4, T_, dp.SEQ, 2, 0),
+    "L2-seq": (48, 8192, 4096, 2, T_, dp.SEQ, 1, 0),
+    "L4-seq-2parts": (32, 8192, 1024, 4, T_, dp.SEQ, 2, 0),
     "contig-L1-2parts": (32, 8192, 4096, 1, C_, dp.TREE, 2, 0),
-    "contig-L1": (16, 1024, 1024, 1, C_, dp.TREE, 1, 0),
-    "L2-padded-rows": (64, 2048, 1024, 2, T_, dp.TREE, 1, 12),
-    "L4-32rows": (8192, 2048, 512, 4, T_, dp.TREE, 1, 0),
+    "contig-L1": (16, 4096, 4096, 1, C_, dp.TREE, 1, 0),
+    "L2-padded-rows": (64, 4096, 2048, 2, T_, dp.TREE, 1, 12),
+    "L4-32rows": (8192, 4096, 1024, 4, T_, dp.TREE, 1, 0),
+    # contiguous teams of L threads, one lane each
+    "contig-L2-tree": (128, 16384, 8192, 2, C_, dp.TREE, 1, 0),
+    "contig-L16": (16, 65536, 4096, 16, C_, dp.TREE, 1, 0),
+    "contig-L8-2parts-seq": (16, 65536, 4096, 8, C_, dp.SEQ, 2, 0),
+    "contig-L64": (4, 262144, 4096, 64, C_, dp.TREE, 1, 0),
+    "contig-L32-padded": (8, 131072, 4096, 32, C_, dp.TREE, 1, 8),
+    "contig-L4-64rows": (4096, 16384, 4096, 4, C_, dp.SEQ, 1, 0),
 }
 
 
 @pytest.mark.parametrize("name", list(FED_GEMV))
-def test_gemv_rows_of_one_thread_fed_by_loader_wavefronts(name):
+def test_gemv_rows_fed_by_loader_wavefronts(name):
     import torch
     m, k, C, L, order, comb, parts, pad = FED_GEMV[name]
+    import math
     s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb,
-                    rows_per_wg=16, row_parts=parts)
+                    rows_per_wg=math.gcd(16, m), row_parts=parts)
     print(f"fed gemv {name}: m={m} k={k} C={C} L={L} parts={parts} pad={pad}", flush=True)
     g = np.random.default_rng(m + k + C + L)
     A = (g.standard_normal((m, k)) * 2.0 ** g.uniform(-12, 12, (m, k))).astype(np.float32)
@@ -560,8 +568,8 @@ def test_gemv_rows_of_one_thread_fed_by_loader_wavefronts(name):
 
 def test_gemv_blas_rows_of_one_thread_fed():
     import torch
-    m, k = 32, 2048
-    s = dp.Strategy(seq_len=1024, local_size=2, order=T_, rows_per_wg=16)
+    m, k = 32, 8192
+    s = dp.Strategy(seq_len=4096, local_size=2, order=T_, rows_per_wg=16)
     g = np.random.default_rng(77)
     A = (g.standard_normal((m, k)) * 2.0 ** g.uniform(-6, 6, (m, k))).astype(np.float32)
     x = g.standard_normal(k).astype(np.float32)
