@@ -193,6 +193,14 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     int lg = 256 / (q.team * q.R);
     if (lg < 1) lg = 1;
     q.teams_per_wg = lg * q.R;
+#if DPIA_MIN_WORKGROUPS
+    // few rows per compute unit (R rows of many threads each): fewer rows per
+    // hardware work-group, down to one wavefront.  Rows are independent, so
+    // which work-group reduces a row does not change its association.
+    while (q.teams_per_wg > 1 && (q.teams_per_wg / 2) * q.team >= 64 &&
+           (q.items + q.teams_per_wg - 1) / q.teams_per_wg < DPIA_MIN_WORKGROUPS)
+      q.teams_per_wg /= 2;
+#endif
   } else {
     q.teams_per_wg = q.team >= 256 ? 1 : 256 / q.team;
 #if DPIA_MIN_WORKGROUPS
