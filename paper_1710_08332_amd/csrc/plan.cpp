@@ -7,6 +7,13 @@
 #ifndef DPIA_MIN_WORKGROUPS
 #define DPIA_MIN_WORKGROUPS 256   // the MI355X's compute units
 #endif
+// gemv rows spread down to this many work-groups (four per compute unit;
+// measured at 16384^2, back to back, 256 / 512 / 1024: contiguous C=1024
+// L=8 with two parts 190.8 / 191.2 / 182.0 us, strided C=1024 L=16 179.6 /
+// 174.7 / 176.9 us, strided C=1024 L=8 with two parts 239.1 / 234.3 / 235.5)
+#ifndef DPIA_GEMV_MIN_WORKGROUPS
+#define DPIA_GEMV_MIN_WORKGROUPS 1024
+#endif
 
 namespace dpia {
 
@@ -198,7 +205,7 @@ dpia_status make_plan(const dpia_strategy* s, dpia_op op, dpia_dtype dt, int64_t
     // hardware work-group, down to one wavefront.  Rows are independent, so
     // which work-group reduces a row does not change its association.
     while (q.teams_per_wg > 1 && (q.teams_per_wg / 2) * q.team >= 64 &&
-           (q.items + q.teams_per_wg - 1) / q.teams_per_wg < DPIA_MIN_WORKGROUPS)
+           (q.items + q.teams_per_wg - 1) / q.teams_per_wg < DPIA_GEMV_MIN_WORKGROUPS)
       q.teams_per_wg /= 2;
 #endif
   } else {
