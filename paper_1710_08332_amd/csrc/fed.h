@@ -65,6 +65,11 @@ static_assert(fed_ring_floats() >= stage_floats(kWave), "the ring holds a stagin
 // q % lanes of matrix row q / lanes, Cel elements at (q % lanes) * Cel of
 // that row (rows of A `rstride` apart) and of x.  x is read with cached
 // loads, since every row and every work-group reads it again.
+// TPR > 1 (strided teams of TPR threads holding 4 lanes each, L = 4 * TPR):
+// folding lane l reads row l / TPR, whose every step of L elements gives
+// thread t = l % TPR the 4 elements at 4 t, in increasing step: its lanes'
+// elements in index order (VEC = 4, element 4 t + i of a step into
+// component i).  The ROWS rows then feed ROWS * TPR folding lanes.
 template <int ROWS, int NOPS>
 constexpr int fed_per() { return ROWS / kFedRowsPerLoad / kFedLoaders; }
 // Tiles in flight: every loader keeps 32 sixteen-byte loads outstanding, up
@@ -75,7 +80,7 @@ constexpr int fed_depth() {
                                                             : kFedMaxDepth;
 }
 
-template <class Op, int VEC, int ROWS, bool SHARED1 = false, class View>
+template <class Op, int VEC, int ROWS, bool SHARED1 = false, int TPR = 1, class View>
 __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
                                          float* ring, typename Op::T (&acc)[VEC],
                                          int rstride = 0, int lanes = 1) {
@@ -132,15 +137,18 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
   };
   // row `lane` of a slot, in increasing element index; element e of the
   // row belongs to component e % VEC
+  static_assert(TPR == 1 || (VEC == 4 && ROWS * TPR <= kWave && kFedVec % TPR == 0),
+                "teams sharing a row hold 4 lanes per thread and fit the folding wavefront");
   auto fold_slot = [&](int slot) {
-    if (ROWS < kWave && lane >= ROWS) return;
+    if (ROWS * TPR < kWave && lane >= ROWS * TPR) return;
+    const int row = lane / TPR, t = lane % TPR;
 #pragma unroll
-    for (int j = 0; j < kFedVec; ++j) {
+    for (int j = 0; j < kFedVec / TPR; ++j) {
       f32x4 v[NOPS];
 #pragma unroll
       for (int o = 0; o < NOPS; ++o)
         v[o] = *reinterpret_cast<const f32x4*>(
-            ring + ((slot * NOPS + o) * kWave + lane) * kFedRow + j * 4);
+            ring + ((slot * NOPS + o) * kWave + row) * kFedRow + (j * TPR + t) * 4);
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i % VEC] = Op::step(View::term(v, i), acc[i % VEC]);
     }

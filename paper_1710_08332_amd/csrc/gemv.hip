@@ -245,34 +245,38 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
 // load A and x into the LDS ring.  The lanes are combined by combine_lanes
 // over teams of `team` adjacent lanes of wave 0 and the parts by tree_node,
 // as in gemv_kernel: every row's association is the strategy's.
-template <class Op, int NL, int COMBINE, int ROWS>
+// TPR = 2: strided teams of 2 threads holding 4 lanes each (L = 8);
+// the ROWS ring rows are whole matrix row parts, and the team's threads fold
+// their own 16-byte pieces of every step of the shared row (fed_fold).
+template <class Op, int NL, int COMBINE, int ROWS, int TPR = 1>
 __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* ring = reinterpret_cast<float*>(lds_raw);
-  const int team = a.team;
+  const int team = TPR > 1 ? TPR : a.team;
   const int t = static_cast<int>(threadIdx.x) % team;
   // each team's combine region (its team * NL lane values)
   T* scratch = reinterpret_cast<T*>(ring + fed_ring_floats()) +
                (static_cast<int>(threadIdx.x) - t) * NL;
   const int wave = static_cast<int>(threadIdx.x) / kWave;
   const int lane = static_cast<int>(threadIdx.x) % kWave;
-  const int cel = a.W / team;
-  const int rows_per_wg = ROWS / team;
+  const int row_lanes = TPR > 1 ? 1 : team;   // ring rows per matrix row
+  const int cel = a.W / row_lanes;
+  const int rows_per_wg = ROWS / row_lanes;
   for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg; row0 < a.m;
        row0 += static_cast<int64_t>(gridDim.x) * rows_per_wg) {
     T acc[NL];
-    fed_fold<Op, NL, ROWS, true>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0, ring, acc,
-                                 static_cast<int>(a.lda), team);
+    fed_fold<Op, NL, ROWS, true, TPR>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0, ring,
+                                      acc, static_cast<int>(a.lda), row_lanes);
     T v = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
     if (a.parts == 2) {
-      fed_fold<Op, NL, ROWS, true>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0, ring, acc,
-                                   static_cast<int>(a.lda), team);
+      fed_fold<Op, NL, ROWS, true, TPR>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0, ring,
+                                        acc, static_cast<int>(a.lda), row_lanes);
       const T h1 = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
-    if (wave == 0 && lane < ROWS && t == 0) op.store(row0 + lane / team, v);
+    if (wave == 0 && lane < ROWS * TPR && t == 0) op.store(row0 + lane / team, v);
   }
 }
 
@@ -286,8 +290,20 @@ template <int ROWS>
 constexpr bool fed_gemv_fits(int64_t tiles) {
   return tiles % fed_depth<ROWS, 2>() == 0;
 }
+// Strided teams of 2 threads of 4 lanes each (L = 8): ring rows are matrix
+// rows, 16 or 32 of them (at most 64 folding lanes).  (Teams of 4 threads
+// were measured slower this way, 16 rows of 4 KB per round: 16384^2 strided
+// C=1024 L=16 176.9 -> 209.6 us, C=512 L=16 with two parts 175.2 -> 205.5
+// us; teams of 2: C=1024 L=8 with two parts 235.5 -> 221.7 us.)
 static int fed_gemv_rows(const Plan& p, int64_t m, int64_t lda) {
   if (m <= 0 || lda % 4 || lda > (int64_t(1) << 24)) return 0;
+  if (p.order == DPIA_ORDER_STRIDED && p.nv == 4 && p.team == 2 && p.L == 8) {
+    if (p.W % kFedStage || p.k != p.W * p.row_parts || p.W / kFedStage < 64) return 0;
+    const int64_t tiles = p.W / kFedStage;
+    if (m % 32 == 0 && m / 32 >= device_cus() && fed_gemv_fits<32>(tiles)) return 32;
+    if (m % 16 == 0 && fed_gemv_fits<16>(tiles)) return 16;
+    return 0;
+  }
   const bool lanes = p.order == DPIA_ORDER_STRIDED
                          ? (p.team == 1 && p.nv == p.L && (p.L == 1 || p.L == 2 || p.L == 4))
                          : p.team == p.L && p.L <= 64 && (p.L & (p.L - 1)) == 0;
@@ -319,8 +335,10 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
   a.W = static_cast<int>(p.W);
   a.L = static_cast<int>(p.L);
   a.C = static_cast<int>(p.C);
-  a.team = p.order == DPIA_ORDER_STRIDED ? 1 : static_cast<int>(p.L);
-  a.teams_per_wg = rows / a.team;
+  // threads per row: strided teams of 1, 2 or 4 threads, contiguous teams of L
+  a.team = p.order == DPIA_ORDER_STRIDED ? p.team : static_cast<int>(p.L);
+  // matrix rows per work-group (ring rows are matrix rows for strided teams)
+  a.teams_per_wg = p.order == DPIA_ORDER_STRIDED ? rows : rows / a.team;
   a.parts = p.row_parts;
   a.stage_off = -1;
   const int nl = p.order == DPIA_ORDER_STRIDED ? p.nv : 1;
@@ -346,6 +364,19 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
   auto by_combine = [&](auto nlc) {
     return p.combine == DPIA_COMBINE_TREE ? by_rows(nlc, ic<kTree>{}) : by_rows(nlc, ic<kSeq>{});
   };
+  auto team_go = [&](auto comb, auto rc, auto tc) {
+    auto kern = gemv_fed_kernel<Op, 4, decltype(comb)::value, decltype(rc)::value,
+                                decltype(tc)::value>;
+    Op op_copy = op;
+    void* args[] = {&op_copy, &a};
+    return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                           dim3(kWave * (1 + kFedLoaders)), args, lds, stream);
+  };
+  auto team_rows = [&](auto comb) {
+    return rows == 32 ? team_go(comb, ic<32>{}, ic<2>{}) : team_go(comb, ic<16>{}, ic<2>{});
+  };
+  if (p.order == DPIA_ORDER_STRIDED && a.team > 1)
+    return p.combine == DPIA_COMBINE_TREE ? team_rows(ic<kTree>{}) : team_rows(ic<kSeq>{});
   return nl == 4 ? by_combine(ic<4>{}) : (nl == 2 ? by_combine(ic<2>{}) : by_combine(ic<1>{}));
 }
 

@@ -519,8 +519,8 @@ def test_strided_gemv_rows_of_one_thread_staged(L, k, parts):
 
 
 # Gemv rows fed by loader wavefronts: teams of one thread (strided L = 1, 2
-# or 4 lanes as the thread's components, or one contiguous lane) and
-# contiguous teams of L threads, binary32 A, whole row parts with lanes of at
+# or 4 lanes as the thread's components, or one contiguous lane), strided
+# teams of 2 threads of 4 lanes each, and contiguous teams of L threads, binary32 A, whole row parts with lanes of at
 # least 64 tiles of 64 elements; 16, 32 or 64 lane rows per work-group.
 # (m, k, C, L, order, combine, parts, lda padding)
 FED_GEMV = {
@@ -540,6 +540,11 @@ FED_GEMV = {
     "contig-L64": (4, 262144, 4096, 64, C_, dp.TREE, 1, 0),
     "contig-L32-padded": (8, 131072, 4096, 32, C_, dp.TREE, 1, 8),
     "contig-L4-64rows": (4096, 16384, 4096, 4, C_, dp.SEQ, 1, 0),
+    # strided teams of 2 threads of 4 lanes each, sharing a row tile
+    "strided-L8-tree": (64, 8192, 1024, 8, T_, dp.TREE, 1, 0),
+    "strided-L8-2parts-seq": (32, 8192, 512, 8, T_, dp.SEQ, 2, 0),
+    "strided-L8-2parts-padded": (16, 16384, 1024, 8, T_, dp.TREE, 2, 20),
+    "strided-L8-32rows": (8192, 4096, 512, 8, T_, dp.TREE, 1, 0),
 }
 
 
