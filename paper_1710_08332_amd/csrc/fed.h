@@ -80,13 +80,23 @@ constexpr int fed_depth() {
                                                             : kFedMaxDepth;
 }
 
-template <class Op, int VEC, int ROWS, bool SHARED1 = false, int TPR = 1, class View>
+// XONE (with SHARED1, lanes = 1): x is one row for all lane rows of a tile.
+// Each loader fetches it with one cached load per tile (16-byte piece
+// lane % 16) and loader 1's first 16 lanes write it to row 0 of the x part
+// of the slot, which every folding lane reads (an LDS broadcast).
+template <class Op, int VEC, int ROWS, bool SHARED1 = false, int TPR = 1, bool XONE = false,
+          class View>
 __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
                                          float* ring, typename Op::T (&acc)[VEC],
                                          int rstride = 0, int lanes = 1) {
   constexpr int NOPS = View::kOps;
   constexpr int kPer = fed_per<ROWS, NOPS>();       // load instructions per operand per tile
-  constexpr int D = fed_depth<ROWS, NOPS>();
+  // One x row: a loader's loads in flight are A's (one x load per tile
+  // aside), 8 tiles deep.  Measured at 16384^2: rows of one thread (64 rows
+  // per work-group) 4 -> 8 tiles 199.6 -> 155.6 us (C=8192 L=2); teams of
+  // two (32 rows) 8 -> 16 tiles 180.6 -> 190.6 us (C=1024 L=8, two parts).
+  constexpr int kXoneDepth = fed_depth<ROWS, 1>() < 8 ? fed_depth<ROWS, 1>() : 8;
+  constexpr int D = XONE ? kXoneDepth : fed_depth<ROWS, NOPS>();
   static_assert(kPer >= 1 && kPer * kFedLoaders * kFedRowsPerLoad == ROWS,
                 "the loaders split a tile's loads evenly");
   static_assert(D % 2 == 0 && D <= kFedMaxDepth, "a round's ring slot is the parity of its tile");
@@ -115,11 +125,18 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
     }
   }
   f32x4 regs[D][NOPS][kPer];
+  static_assert(!XONE || (SHARED1 && NOPS == 2), "one x row: a gemv");
+  const float* xpiece = view.operand(NOPS - 1) + (lane % kFedVec) * 4;
   auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
 #pragma unroll
       for (int o = 0; o < NOPS; ++o) {
+        if (XONE && o == 1) {
+          if (k == 0)
+            rg[1][0] = ld<false>(reinterpret_cast<const f32x4*>(xpiece + tile * kFedStage));
+          continue;
+        }
         const f32x4* g = reinterpret_cast<const f32x4*>(rowp[o][k] + tile * kFedStage);
         rg[o][k] = SHARED1 && o == 1 ? ld<false>(g) : ld<DPIA_NT_LOADS != 0>(g);
       }
@@ -131,9 +148,16 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
 #pragma unroll
-      for (int o = 0; o < NOPS; ++o)
+      for (int o = 0; o < NOPS; ++o) {
+        if (XONE && o == 1) continue;
         *reinterpret_cast<f32x4*>(ring + (slot * NOPS + o) * kWave * kFedRow + rofs[k]) =
             rg[o][k];
+      }
+    if constexpr (XONE) {
+      if (q == 0 && lane < kFedVec)
+        *reinterpret_cast<f32x4*>(ring + (slot * NOPS + 1) * kWave * kFedRow + lane * 4) =
+            rg[1][0];
+    }
   };
   // row `lane` of a slot, in increasing element index; element e of the
   // row belongs to component e % VEC
@@ -148,7 +172,8 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
 #pragma unroll
       for (int o = 0; o < NOPS; ++o)
         v[o] = *reinterpret_cast<const f32x4*>(
-            ring + ((slot * NOPS + o) * kWave + row) * kFedRow + (j * TPR + t) * 4);
+            ring + ((slot * NOPS + o) * kWave + (XONE && o == 1 ? 0 : row)) * kFedRow +
+            (j * TPR + t) * 4);
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i % VEC] = Op::step(View::term(v, i), acc[i % VEC]);
     }

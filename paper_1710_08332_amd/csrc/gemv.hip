@@ -248,7 +248,9 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
 // TPR = 2: strided teams of 2 threads holding 4 lanes each (L = 8);
 // the ROWS ring rows are whole matrix row parts, and the team's threads fold
 // their own 16-byte pieces of every step of the shared row (fed_fold).
-template <class Op, int NL, int COMBINE, int ROWS, int TPR = 1>
+// XONE: a matrix row is one ring row (every team but the contiguous teams
+// of L > 1 lanes), so x is one row of the ring slot.
+template <class Op, int NL, int COMBINE, int ROWS, int TPR = 1, bool XONE = false>
 __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
@@ -267,12 +269,12 @@ __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op 
   for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg; row0 < a.m;
        row0 += static_cast<int64_t>(gridDim.x) * rows_per_wg) {
     T acc[NL];
-    fed_fold<Op, NL, ROWS, true, TPR>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0, ring,
-                                      acc, static_cast<int>(a.lda), row_lanes);
+    fed_fold<Op, NL, ROWS, true, TPR, XONE>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0,
+                                            ring, acc, static_cast<int>(a.lda), row_lanes);
     T v = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
     if (a.parts == 2) {
-      fed_fold<Op, NL, ROWS, true, TPR>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0, ring,
-                                        acc, static_cast<int>(a.lda), row_lanes);
+      fed_fold<Op, NL, ROWS, true, TPR, XONE>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0,
+                                              ring, acc, static_cast<int>(a.lda), row_lanes);
       const T h1 = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
     }
@@ -288,7 +290,8 @@ __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op 
 // every compute unit a work-group.
 template <int ROWS>
 constexpr bool fed_gemv_fits(int64_t tiles) {
-  return tiles % fed_depth<ROWS, 2>() == 0;
+  // (the depth with one x row, a multiple of the depth with x in every row)
+  return tiles % fed_depth<ROWS, 1>() == 0;
 }
 // Strided teams of 2 threads of 4 lanes each (L = 8): ring rows are matrix
 // rows, 16 or 32 of them (at most 64 folding lanes).  (Teams of 4 threads
@@ -351,7 +354,10 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
     constexpr int NL = decltype(nlc)::value;
     constexpr int COMBINE = decltype(comb)::value;
     constexpr int ROWS = decltype(rc)::value;
-    auto kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS>;
+    auto kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, true>;
+    if constexpr (NL == 1) {
+      if (a.team > 1) kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, false>;
+    }
     Op op_copy = op;
     void* args[] = {&op_copy, &a};
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
@@ -366,7 +372,7 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
   };
   auto team_go = [&](auto comb, auto rc, auto tc) {
     auto kern = gemv_fed_kernel<Op, 4, decltype(comb)::value, decltype(rc)::value,
-                                decltype(tc)::value>;
+                                decltype(tc)::value, true>;
     Op op_copy = op;
     void* args[] = {&op_copy, &a};
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
