@@ -80,11 +80,12 @@ constexpr int fed_depth() {
                                                             : kFedMaxDepth;
 }
 
-// XONE (with SHARED1, lanes = 1): x is one row for all lane rows of a tile.
-// Each loader fetches it with one cached load per tile (16-byte piece
-// lane % 16) and loader 1's first 16 lanes write it to row 0 of the x part
-// of the slot, which every folding lane reads (an LDS broadcast).
-template <class Op, int VEC, int ROWS, bool SHARED1 = false, int TPR = 1, bool XONE = false,
+// XR > 0 (with SHARED1, lanes = XR = 1, 2 or 4): x is XR rows for all lane
+// rows of a tile, lane row q reading row q % XR.  Each loader fetches them
+// with one cached load per tile (lane l: piece l % 16 of row (l / 16) % XR)
+// and loader 1's first 16 XR lanes write them to rows 0 .. XR - 1 of the x
+// part of the slot, which the folding lanes read (LDS broadcasts).
+template <class Op, int VEC, int ROWS, bool SHARED1 = false, int TPR = 1, int XR = 0,
           class View>
 __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, int lane, int row0,
                                          float* ring, typename Op::T (&acc)[VEC],
@@ -96,7 +97,7 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
   // per work-group) 4 -> 8 tiles 199.6 -> 155.6 us (C=8192 L=2); teams of
   // two (32 rows) 8 -> 16 tiles 180.6 -> 190.6 us (C=1024 L=8, two parts).
   constexpr int kXoneDepth = fed_depth<ROWS, 1>() < 8 ? fed_depth<ROWS, 1>() : 8;
-  constexpr int D = XONE ? kXoneDepth : fed_depth<ROWS, NOPS>();
+  constexpr int D = XR > 0 ? kXoneDepth : fed_depth<ROWS, NOPS>();
   static_assert(kPer >= 1 && kPer * kFedLoaders * kFedRowsPerLoad == ROWS,
                 "the loaders split a tile's loads evenly");
   static_assert(D % 2 == 0 && D <= kFedMaxDepth, "a round's ring slot is the parity of its tile");
@@ -125,14 +126,17 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
     }
   }
   f32x4 regs[D][NOPS][kPer];
-  static_assert(!XONE || (SHARED1 && NOPS == 2), "one x row: a gemv");
-  const float* xpiece = view.operand(NOPS - 1) + (lane % kFedVec) * 4;
+  static_assert(XR == 0 || (SHARED1 && NOPS == 2 && (XR == 1 || XR == 2 || XR == 4)),
+                "x rows: a gemv's, one per lane of a matrix row");
+  const float* xpiece = view.operand(NOPS - 1) +
+                        static_cast<int64_t>(XR > 0 ? (lane / kFedVec) % XR : 0) * Cel +
+                        (lane % kFedVec) * 4;
   auto gload = [&](f32x4 (&rg)[NOPS][kPer], int tile) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k)
 #pragma unroll
       for (int o = 0; o < NOPS; ++o) {
-        if (XONE && o == 1) {
+        if (XR > 0 && o == 1) {
           if (k == 0)
             rg[1][0] = ld<false>(reinterpret_cast<const f32x4*>(xpiece + tile * kFedStage));
           continue;
@@ -149,14 +153,14 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
     for (int k = 0; k < kPer; ++k)
 #pragma unroll
       for (int o = 0; o < NOPS; ++o) {
-        if (XONE && o == 1) continue;
+        if (XR > 0 && o == 1) continue;
         *reinterpret_cast<f32x4*>(ring + (slot * NOPS + o) * kWave * kFedRow + rofs[k]) =
             rg[o][k];
       }
-    if constexpr (XONE) {
-      if (q == 0 && lane < kFedVec)
-        *reinterpret_cast<f32x4*>(ring + (slot * NOPS + 1) * kWave * kFedRow + lane * 4) =
-            rg[1][0];
+    if constexpr (XR > 0) {
+      if (q == 0 && lane < kFedVec * XR)
+        *reinterpret_cast<f32x4*>(ring + ((slot * NOPS + 1) * kWave + lane / kFedVec) * kFedRow +
+                                  (lane % kFedVec) * 4) = rg[1][0];
     }
   };
   // row `lane` of a slot, in increasing element index; element e of the
@@ -172,7 +176,8 @@ __device__ __forceinline__ void fed_fold(const View& view, int Cel, int wave, in
 #pragma unroll
       for (int o = 0; o < NOPS; ++o)
         v[o] = *reinterpret_cast<const f32x4*>(
-            ring + ((slot * NOPS + o) * kWave + (XONE && o == 1 ? 0 : row)) * kFedRow +
+            ring + ((slot * NOPS + o) * kWave + (XR > 0 && o == 1 ? row % (XR > 0 ? XR : 1) : row)) *
+                       kFedRow +
             (j * TPR + t) * 4);
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i % VEC] = Op::step(View::term(v, i), acc[i % VEC]);

@@ -248,9 +248,10 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
 // TPR = 2: strided teams of 2 threads holding 4 lanes each (L = 8);
 // the ROWS ring rows are whole matrix row parts, and the team's threads fold
 // their own 16-byte pieces of every step of the shared row (fed_fold).
-// XONE: a matrix row is one ring row (every team but the contiguous teams
-// of L > 1 lanes), so x is one row of the ring slot.
-template <class Op, int NL, int COMBINE, int ROWS, int TPR = 1, bool XONE = false>
+// XR: x rows of a ring slot, 1 where a matrix row is one ring row (every
+// team but the contiguous teams of L > 1 lanes), L for contiguous teams of
+// L = 2 or 4 lanes (lane l reads x row l), 0: one x row per ring row.
+template <class Op, int NL, int COMBINE, int ROWS, int TPR = 1, int XR = 0>
 __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op op, GemvArgs a) {
   using T = typename Op::T;
   using A = typename Op::Arith;
@@ -269,11 +270,11 @@ __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op 
   for (int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg; row0 < a.m;
        row0 += static_cast<int64_t>(gridDim.x) * rows_per_wg) {
     T acc[NL];
-    fed_fold<Op, NL, ROWS, true, TPR, XONE>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0,
+    fed_fold<Op, NL, ROWS, true, TPR, XR>(op.part(row0, 0, a.lda, a.W), cel, wave, lane, 0,
                                             ring, acc, static_cast<int>(a.lda), row_lanes);
     T v = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
     if (a.parts == 2) {
-      fed_fold<Op, NL, ROWS, true, TPR, XONE>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0,
+      fed_fold<Op, NL, ROWS, true, TPR, XR>(op.part(row0, 1, a.lda, a.W), cel, wave, lane, 0,
                                               ring, acc, static_cast<int>(a.lda), row_lanes);
       const T h1 = combine_lanes<A, NL, COMBINE>(acc, t, team, a.L, scratch);
       v = tree_node<A>(v, h1);   // reduceSeq (+) 0 [h0, h1]
@@ -354,9 +355,11 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
     constexpr int NL = decltype(nlc)::value;
     constexpr int COMBINE = decltype(comb)::value;
     constexpr int ROWS = decltype(rc)::value;
-    auto kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, true>;
+    auto kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, 1>;
     if constexpr (NL == 1) {
-      if (a.team > 1) kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, false>;
+      if (a.team == 2) kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, 2>;
+      else if (a.team == 4) kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, 4>;
+      else if (a.team > 4) kern = gemv_fed_kernel<Op, NL, COMBINE, ROWS, 1, 0>;
     }
     Op op_copy = op;
     void* args[] = {&op_copy, &a};
@@ -372,7 +375,7 @@ hipError_t launch_gemv_fed(const Plan& p, const Op& op, int64_t m, int64_t lda, 
   };
   auto team_go = [&](auto comb, auto rc, auto tc) {
     auto kern = gemv_fed_kernel<Op, 4, decltype(comb)::value, decltype(rc)::value,
-                                decltype(tc)::value, true>;
+                                decltype(tc)::value, 1>;
     Op op_copy = op;
     void* args[] = {&op_copy, &a};
     return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),

@@ -540,6 +540,8 @@ FED_GEMV = {
     "contig-L64": (4, 262144, 4096, 64, C_, dp.TREE, 1, 0),
     "contig-L32-padded": (8, 131072, 4096, 32, C_, dp.TREE, 1, 8),
     "contig-L4-64rows": (4096, 16384, 4096, 4, C_, dp.SEQ, 1, 0),
+    "contig-L2-2parts-padded": (32, 16384, 4096, 2, C_, dp.TREE, 2, 12),
+    "contig-L4-tree": (16, 16384, 4096, 4, C_, dp.TREE, 1, 0),
     # strided teams of 2 threads of 4 lanes each, sharing a row tile
     "strided-L8-tree": (64, 8192, 1024, 8, T_, dp.TREE, 1, 0),
     "strided-L8-2parts-seq": (32, 8192, 512, 8, T_, dp.SEQ, 2, 0),
