@@ -234,8 +234,8 @@ __global__ void __launch_bounds__(MAXT) gemv_kernel(Op op, GemvArgs a) {
 
 // Binary32 rows fed by loader wavefronts: teams of one thread (the strided
 // order with L = NL lanes held as that thread's components, or one
-// contiguous lane) and contiguous teams of L threads (one lane each), row
-// parts of whole tiles.  The strategy's work-groups of R rows give each busy
+// contiguous lane), strided teams of two threads (TPR below) and contiguous
+// teams of L threads (one lane each), row parts of whole tiles.  The strategy's work-groups of R rows give each busy
 // compute unit a wavefront or two (16384 rows of R = 128: 128 work-groups),
 // too few loads in flight to stream A.  The rows are independent, so a
 // hardware work-group here takes ROWS lane rows of its own, ROWS / team
@@ -284,21 +284,21 @@ __global__ void __launch_bounds__(kWave * (1 + kFedLoaders)) gemv_fed_kernel(Op 
 }
 
 // Lane rows per work-group of gemv_fed_kernel for this plan, or 0 where it
-// does not apply: teams of one thread or contiguous teams of at most 64
-// threads, binary32 A (the caller's check), every row part whole (k = W *
+// does not apply: teams of one thread, strided teams of two, or contiguous
+// teams of at most 64 threads, binary32 A (the caller's check), every row part whole (k = W *
 // parts) with lanes of at least 64 tiles of 64 elements, and m a multiple
 // of the matrix rows per work-group.  The most lane rows that still give
 // every compute unit a work-group.
 template <int ROWS>
 constexpr bool fed_gemv_fits(int64_t tiles) {
-  // (the depth with one x row, a multiple of the depth with x in every row)
+  // (a multiple of every depth fed_fold uses for these rows: 4 to 16 tiles)
   return tiles % fed_depth<ROWS, 1>() == 0;
 }
 // Strided teams of 2 threads of 4 lanes each (L = 8): ring rows are matrix
-// rows, 16 or 32 of them (at most 64 folding lanes).  (Teams of 4 threads
-// were measured slower this way, 16 rows of 4 KB per round: 16384^2 strided
-// C=1024 L=16 176.9 -> 209.6 us, C=512 L=16 with two parts 175.2 -> 205.5
-// us; teams of 2: C=1024 L=8 with two parts 235.5 -> 221.7 us.)
+// rows, 16 or 32 of them (at most 64 folding lanes).  (Teams of 4 threads,
+// 16 rows of 4 KB per round, measured no faster this way at 16384^2:
+// strided C=1024 L=16 177.9 -> 175.1 us, C=512 L=16 with two parts 174.6
+// -> 176.0 us; teams of 2: C=1024 L=8 with two parts 235.5 -> 181.8 us.)
 static int fed_gemv_rows(const Plan& p, int64_t m, int64_t lda) {
   if (m <= 0 || lda % 4 || lda > (int64_t(1) << 24)) return 0;
   if (p.order == DPIA_ORDER_STRIDED && p.nv == 4 && p.team == 2 && p.L == 8) {
