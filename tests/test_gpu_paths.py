@@ -586,3 +586,30 @@ def test_gemv_blas_rows_of_one_thread_fed():
     torch.cuda.synchronize()
     want = S.gemv_blas(np.float32(1.5), A, x, np.float32(-0.75), y0, to_plan(s))
     assert_same_bits(yt.cpu().numpy(), want, "gemv_blas fed")
+
+
+# Fed gemv work-groups looping over several row groups (the strategy caps the
+# grid at 2 work-groups): the ring, the x rows and the combine regions are
+# reused from one row group to the next.  (m, k, C, L, order, combine, parts)
+FED_GEMV_LOOP = {
+    "L2-rows-of-one": (96, 4096, 2048, 2, T_, dp.TREE, 1),
+    "L8-teams-of-two-seq": (64, 8192, 512, 8, T_, dp.SEQ, 2),
+    "contig-L2-x-rows": (48, 16384, 4096, 2, C_, dp.TREE, 2),
+    "contig-L16-seq": (8, 65536, 4096, 16, C_, dp.SEQ, 1),
+}
+
+
+@pytest.mark.parametrize("name", list(FED_GEMV_LOOP))
+def test_gemv_fed_work_groups_loop_over_row_groups(name):
+    import math
+    import torch
+    m, k, C, L, order, comb, parts = FED_GEMV_LOOP[name]
+    s = dp.Strategy(seq_len=C, local_size=L, order=order, wg_combine=comb,
+                    rows_per_wg=math.gcd(16, m), row_parts=parts, max_grid=2)
+    print(f"fed gemv loop {name}: m={m} k={k} C={C} L={L} parts={parts}", flush=True)
+    g = np.random.default_rng(m * 7 + L)
+    A = (g.standard_normal((m, k)) * 2.0 ** g.uniform(-12, 12, (m, k))).astype(np.float32)
+    x = (g.standard_normal(k) * 2.0 ** g.uniform(-12, 12, k)).astype(np.float32)
+    y = dp.gemv(cuda(A), cuda(x), s)
+    torch.cuda.synchronize()
+    assert_same_bits(y.cpu().numpy(), S.gemv(A, x, to_plan(s)), name)
